@@ -1,0 +1,91 @@
+"""Pins for the FMT derivatives: finite differences of the printed Phi_hs,
+and the bulk Percus-Yevick / scaled-particle closed forms."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import dphi_hs, phi_hs
+
+
+def _point(rng):
+    n3 = rng.uniform(0.05, 0.6)
+    return dict(n0=rng.uniform(1, 10), n1=rng.uniform(0.1, 2), n2=rng.uniform(1, 8), n3=n3,
+                n1v=rng.uniform(-0.5, 0.5, size=3), n2v=rng.uniform(-2, 2, size=3))
+
+
+@pytest.mark.parametrize("seed", range(5))
+def test_derivatives_match_finite_differences(seed):
+    rng = np.random.default_rng(seed)
+    p = _point(rng)
+    args = lambda q: (np.array(q["n0"]), np.array(q["n1"]), np.array(q["n2"]), np.array(q["n3"]),
+                      np.asarray(q["n1v"])[:, None], np.asarray(q["n2v"])[:, None])
+    d = dphi_hs(*args(p))
+    for key, dk in (("n0", "d0"), ("n1", "d1"), ("n2", "d2"), ("n3", "d3")):
+        eps = 1e-6 * max(1.0, abs(p[key]))
+        qp, qm = dict(p), dict(p)
+        qp[key] = p[key] + eps
+        qm[key] = p[key] - eps
+        fd = (phi_hs(*args(qp)) - phi_hs(*args(qm))) / (2 * eps)
+        assert float(d[dk]) == pytest.approx(float(fd), rel=1e-7, abs=1e-8), key
+    for key, dk in (("n1v", "d1v"), ("n2v", "d2v")):
+        for c in range(3):
+            eps = 1e-6
+            qp, qm = dict(p), dict(p)
+            qp[key] = np.array(p[key]); qp[key][c] += eps
+            qm[key] = np.array(p[key]); qm[key][c] -= eps
+            fd = (phi_hs(*args(qp)) - phi_hs(*args(qm))) / (2 * eps)
+            assert float(d[dk][c]) == pytest.approx(float(fd), rel=1e-7, abs=1e-8), (key, c)
+
+
+def _bulk_mu(rho, d):
+    """beta mu_i from the FMT derivatives at bulk weighted densities."""
+    R = 0.5 * np.asarray(d)
+    rho = np.asarray(rho)
+    n0, n1 = rho.sum(), (rho * R).sum()
+    n2, n3 = (rho * 4 * math.pi * R ** 2).sum(), (rho * 4 / 3 * math.pi * R ** 3).sum()
+    z = np.zeros((3, 1))
+    dd = dphi_hs(np.array([n0]), np.array([n1]), np.array([n2]), np.array([n3]), z, z)
+    return np.array([float(dd["d0"][0] + Ri * dd["d1"][0] + 4 * math.pi * Ri ** 2 * dd["d2"][0]
+                           + 4 / 3 * math.pi * Ri ** 3 * dd["d3"][0]) for Ri in R])
+
+
+def spt_mu(rho, d):
+    """Scaled-particle / Percus-Yevick compressibility excess chemical
+    potentials of a hard-sphere mixture (Lebowitz 1964; Reiss-Frisch-Lebowitz)."""
+    rho, d = np.asarray(rho, float), np.asarray(d, float)
+    xi = [math.pi / 6 * float((rho * d ** m).sum()) for m in range(4)]
+    one = 1.0 - xi[3]
+    # beta P = (6/pi) [xi0/(1-xi3) + 3 xi1 xi2/(1-xi3)^2 + 3 xi2^3/(1-xi3)^3]
+    p = 6 / math.pi * (xi[0] / one + 3 * xi[1] * xi[2] / one ** 2 + 3 * xi[2] ** 3 / one ** 3)
+    return np.array([-math.log(one) + 3 * xi[2] * s / one + 3 * xi[1] * s * s / one
+                     + 4.5 * xi[2] ** 2 * s * s / one ** 2 + math.pi / 6 * s ** 3 * p for s in d])
+
+
+def py_single(eta):
+    return -math.log(1 - eta) + (14 * eta - 13 * eta ** 2 + 5 * eta ** 3) / (2 * (1 - eta) ** 3)
+
+
+@pytest.mark.parametrize("eta", [1e-4, 0.0170272018534497, 0.2, 0.45, 0.6])
+def test_single_species_bulk_is_percus_yevick(eta):
+    d = 0.3
+    rho = eta / (math.pi / 6 * d ** 3)
+    assert _bulk_mu([rho], [d])[0] == pytest.approx(py_single(eta), rel=1e-13)
+
+
+def test_py_value_at_045():
+    assert py_single(0.45) == pytest.approx(12.988896354624895, rel=1e-15)
+
+
+def test_mixture_bulk_is_scaled_particle_theory():
+    rng = np.random.default_rng(3)
+    for _ in range(5):
+        d = rng.uniform(0.1, 0.5, size=4)
+        rho = rng.uniform(0.1, 3.0, size=4)
+        assert np.allclose(_bulk_mu(rho, d), spt_mu(rho, d), rtol=1e-12, atol=0)
+
+
+def test_packing_violation_raises():
+    z = np.zeros((3, 1))
+    with pytest.raises(ValueError):
+        dphi_hs(np.ones(1), np.ones(1), np.ones(1), np.array([1.0]), z, z)
