@@ -1,0 +1,216 @@
+/*
+ * pnp_cdft.h -- C ABI of the MI355X (gfx950) evaluator of cDFT excess chemical
+ * potentials for 3D Poisson-Nernst-Planck-cDFT solvers.
+ *
+ * Method: Meng, Zheng, Lin, Sushko, "Numerical Solution of 3D Poisson-Nernst-
+ * Planck Equations Coupled with Classical Density Functional Theory ...",
+ * Sec. 2.3 (the cDFT free-energy terms and their chemical potentials) and
+ * Sec. 3.4 (every cDFT integral evaluated as a convolution through FFTs).
+ *
+ * What one evaluation computes, for S species on a periodic n^3 grid of
+ * spacing h (all outputs dimensionless, in units of k_B T):
+ *   - FMT weighted densities n0..n3, n1v, n2v (Sec. 2.3.1, correlations of
+ *     rho_i with the weight functions omega_i);
+ *   - the ten partial derivatives of the Rosenfeld free-energy density
+ *     (Sec. 2.3.1), evaluated pointwise in FP64;
+ *   - beta mu_hs_i by back-convolution (Sec. 2.3.1);
+ *   - beta mu_el_i, the MSA electrostatic-correlation term (Sec. 2.3.4):
+ *     mu_el_bulk_i - sum_j C_ij (*) (rho_j - rho_j^bulk);
+ *   - beta mu_sh_i, the mean-field square-well term (Sec. 2.3.2) with the
+ *     printed prefactor 1/2 (configurable);
+ *   - beta mu_ex = hs + el + sh and the Slotboom factor exp(-beta mu_ex),
+ *     the mu_ex part of the transformed diffusion coefficient (Sec. 2.1).
+ * The Coulomb term of Sec. 2.3.3 is not part of mu_ex here: in a PNP solve it
+ * is the Poisson potential.
+ *
+ * Discrete operator: each weight / pair kernel is the inverse DFT of its
+ * continuous Fourier transform sampled at the grid wave-vectors (exact bulk
+ * sums, no r = 0 singularity); vector weights drop their component along an
+ * axis on that axis's Nyquist plane.  Forward weighted densities are
+ * correlations and back-convolutions are convolutions, as in Sec. 2.3.1.
+ *
+ * Units: lengths nm, energies eV, temperature K, densities nm^-3.
+ *
+ * Memory: every pointer marked "device" is caller-owned device memory (for
+ * example allocated by PyTorch) on the context's device; the library never
+ * allocates, frees or retains caller memory.  The context owns only a few
+ * small host-side records.  Scratch space comes in through `workspace`,
+ * sized by pnp_workspace_bytes().
+ *
+ * Errors: every function returns a pnp_status; nothing aborts or throws
+ * across this boundary.  Outputs are unspecified when the return is not
+ * PNP_OK.  pnp_last_error() gives a human-readable reason.
+ *
+ * Concurrency: a context is not thread-safe; use one per host thread.  Work
+ * is enqueued on the caller's HIP stream.  Unless PNP_FLAG_ASYNC is set, a
+ * call waits for its own work to finish so that it can return the status
+ * that the kernels raised (packing fraction >= 1, non-finite values,
+ * overflow of exp(-mu)).
+ */
+#ifndef PNP_CDFT_H
+#define PNP_CDFT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  PNP_OK = 0,
+  PNP_E_ARG = -1,              /* invalid argument (null pointer, bad count, ...) */
+  PNP_E_UNSUPPORTED_SIZE = -2, /* grid size not in the supported set */
+  PNP_E_NOMEM = -3,            /* workspace too small */
+  PNP_E_PACKING = -4,          /* some weighted density n3 >= 1: ln(1 - n3) undefined */
+  PNP_E_OVERFLOW = -5,         /* exp(-beta mu_ex) overflowed a double */
+  PNP_E_NONFINITE = -6,        /* a non-finite value appeared in the evaluation */
+  PNP_E_DEVICE = -7,           /* HIP runtime error */
+  PNP_E_BUDGET = -8            /* request does not fit the memory budget */
+} pnp_status;
+
+/* terms of beta mu_ex */
+enum { PNP_TERM_HS = 1, PNP_TERM_EC = 2, PNP_TERM_SW = 4, PNP_TERM_ALL = 7 };
+
+/* arithmetic of the spectral path */
+enum {
+  PNP_FP64 = 0,  /* FFTs, weights and pointwise work in double */
+  PNP_MIXED = 1  /* FFTs and weight multiplies in float; FMT derivatives,
+                    final accumulation and exp in double */
+};
+
+/* flags */
+enum {
+  PNP_FLAG_ASYNC = 1  /* do not wait for the status word; read it later with
+                         pnp_read_status() */
+};
+
+typedef struct pnp_ctx_s* pnp_ctx;
+
+/* Periodic grid with nx = ny = nz = n points of spacing h [nm].  Supported n:
+ * 8, 16, 24, 32, 48, 64, 96, 128, 192, 256 (see pnp_supported_size). */
+typedef struct {
+  int32_t nx, ny, nz;
+  double h;
+} pnp_grid;
+
+/* One species (Sec. 2.3: charged hard spheres). */
+typedef struct {
+  double d;           /* hard-core diameter [nm], > 0 */
+  double q;           /* valence (signed) */
+  double rho_bulk;    /* bulk density [nm^-3] (reference of the EC expansion, and kappa) */
+  double mu_el_bulk;  /* beta mu_el_i[bulk] [k_B T]; the paper gives no formula, 0 is typical */
+} pnp_species;
+
+typedef struct {
+  uint32_t terms;         /* PNP_TERM_* mask */
+  int32_t precision;      /* PNP_FP64 or PNP_MIXED */
+  int32_t per_term;       /* 0: mu_ex is [S][N]; 1: mu_ex is [3][S][N] = (hs, el, sh) */
+  uint32_t flags;         /* PNP_FLAG_* */
+  double eps_r;           /* relative permittivity (Table 1 uses 16.6) */
+  const double* sw_eps;   /* host, S*S row-major well depths [eV] (> 0 attractive); NULL: none */
+  const double* sw_rout;  /* host, S*S outer radii [nm]; NULL or entries <= 0: gamma*sigma_ij */
+  double sw_gamma;        /* well extent factor, 1.2 in Sec. 2.3.2 */
+  double sw_prefactor;    /* factor in front of the mean-field integral, 1/2 as printed */
+} pnp_params;
+
+/* Create a context bound to HIP device `device` (used for every call). */
+pnp_status pnp_create(int device, pnp_ctx* out);
+void pnp_destroy(pnp_ctx ctx);
+
+/* Human-readable description of the last error on this context. */
+const char* pnp_last_error(pnp_ctx ctx);
+
+/* 1 when n is a supported grid size, else 0. */
+int pnp_supported_size(int32_t n);
+
+/* Bytes of device workspace one evaluation of this shape needs. */
+pnp_status pnp_workspace_bytes(pnp_ctx ctx, const pnp_grid* grid, int32_t S,
+                               const pnp_params* params, size_t* bytes);
+
+/*
+ * One evaluation of beta mu_ex (Sec. 2.3) and exp(-beta mu_ex) (Sec. 2.1).
+ *   rho       device, float64 [S][nx][ny][nz], z fastest; read-only
+ *   T         temperature [K] > 0
+ *   mu_ex     device, float64 [S][N] (per_term = 0) or [3][S][N] (per_term = 1)
+ *   slotboom  device, float64 [S][N] exp(-beta mu_ex); may be NULL
+ *   workspace device, >= pnp_workspace_bytes(), 256-byte aligned
+ *   stream    hipStream_t (NULL = default stream)
+ * Errors: PNP_E_ARG, PNP_E_UNSUPPORTED_SIZE, PNP_E_NOMEM (workspace_bytes too
+ * small), PNP_E_PACKING (some n3 >= 1), PNP_E_NONFINITE, PNP_E_OVERFLOW,
+ * PNP_E_DEVICE.
+ */
+pnp_status pnp_cdft_mu_ex(pnp_ctx ctx, const pnp_grid* grid, int32_t S,
+                          const pnp_species* species, const double* rho, double T,
+                          const pnp_params* params, double* mu_ex, double* slotboom,
+                          void* workspace, size_t workspace_bytes, void* stream);
+
+/*
+ * The weighted densities of Sec. 2.3.1 alone, in real space.
+ *   n_out  device, float64 [10][N] in the order n0, n1, n2, n3, n1v(x,y,z), n2v(x,y,z)
+ * Same errors as pnp_cdft_mu_ex (no packing check).
+ */
+pnp_status pnp_weighted_densities(pnp_ctx ctx, const pnp_grid* grid, int32_t S,
+                                  const pnp_species* species, const double* rho,
+                                  const pnp_params* params, double* n_out,
+                                  void* workspace, size_t workspace_bytes, void* stream);
+
+/* One request of a batch: an independent evaluation with its own shape. */
+typedef struct {
+  pnp_grid grid;
+  int32_t S;
+  const pnp_species* species;  /* host, S entries */
+  const double* rho;           /* device */
+  double T;
+  const pnp_params* params;    /* host */
+  double* mu_ex;               /* device */
+  double* slotboom;            /* device or NULL */
+  void* workspace;             /* device, this request's own workspace */
+  size_t workspace_bytes;
+  int32_t status;              /* out: pnp_status of this request */
+} pnp_request;
+
+/*
+ * Evaluate `count` independent requests of possibly different sizes,
+ * temperatures and compositions.  Requests with equal grid size share every
+ * kernel launch (one grid of workgroups spans all of them).  A request that
+ * fails (bad packing, overflow, ...) reports its own status and does not
+ * affect the others.  Returns PNP_OK when the batch ran (check each status).
+ */
+pnp_status pnp_batch_mu_ex(pnp_ctx ctx, int32_t count, pnp_request* reqs, void* stream);
+
+/* Read the status word left by an asynchronous call (after the stream has
+ * finished the work).  workspace: the one passed to that call. */
+pnp_status pnp_read_status(pnp_ctx ctx, const void* workspace, void* stream);
+
+/*
+ * Consumer stub of the PNP loop (not part of the evaluation): relaxes every
+ * density toward the equilibrium of its current excess chemical potential,
+ *   rho_i <- (1 - lambda) rho_i + lambda rho_i^bulk exp(beta mu_b,i - beta mu_ex,i),
+ * where beta mu_b,i = mu_bulk[i].  Sec. 3.2 uses relaxation
+ * rho <- lambda2 rho_new + (1 - lambda2) rho_old.
+ *   rho      device, float64 [S][N], updated in place
+ *   mu_ex    device, float64 [S][N]
+ *   mu_bulk  host, S values [k_B T]
+ */
+pnp_status pnp_relax_densities(pnp_ctx ctx, const pnp_grid* grid, int32_t S,
+                               const pnp_species* species, double* rho,
+                               const double* mu_ex, const double* mu_bulk, double lambda,
+                               void* stream);
+
+/*
+ * Test hook: 3D real-to-complex DFT of `count` fields through the same
+ * kernels the evaluation uses, written in numpy's rfftn layout
+ * (complex128 [count][n][n][n/2+1]).  `inverse` = 1 runs the reverse
+ * (unnormalised complex-to-real, numpy irfftn times N) from that layout.
+ *   in/out device float64 (real fields [count][N] or interleaved complex).
+ */
+pnp_status pnp_debug_rfft3(pnp_ctx ctx, const pnp_grid* grid, int32_t precision,
+                           int32_t count, int32_t inverse, const double* in, double* out,
+                           void* workspace, size_t workspace_bytes, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PNP_CDFT_H */

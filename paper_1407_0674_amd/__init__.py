@@ -1,0 +1,12 @@
+"""MI355X (gfx950) evaluator of cDFT excess chemical potentials.
+
+The hot path is hand-written HIP behind the C ABI in include/pnp_cdft.h;
+this package only marshals arguments to it (see ``binding``).  Importing it
+does not load the library; the first call does, and fails loudly when the
+library has not been built.
+"""
+from .binding import (PnpError, Evaluator, lib_path, load_library, STATUS_NAMES,
+                      TERM_HS, TERM_EC, TERM_SW, TERM_ALL, FP64, MIXED, FLAG_ASYNC)
+
+__all__ = ["PnpError", "Evaluator", "lib_path", "load_library", "STATUS_NAMES",
+           "TERM_HS", "TERM_EC", "TERM_SW", "TERM_ALL", "FP64", "MIXED", "FLAG_ASYNC"]

@@ -1,0 +1,305 @@
+"""ctypes binding of the C ABI in include/pnp_cdft.h (argument marshalling only).
+
+PyTorch provides device memory (outputs, workspaces) and the current HIP
+stream; every step of the evaluation runs in the HIP library.  There is no
+fallback: a missing library raises PnpError.
+"""
+import ctypes
+import os
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+TERM_HS, TERM_EC, TERM_SW, TERM_ALL = 1, 2, 4, 7
+FP64, MIXED = 0, 1
+FLAG_ASYNC = 1
+
+STATUS_NAMES = {
+    0: "PNP_OK", -1: "PNP_E_ARG", -2: "PNP_E_UNSUPPORTED_SIZE", -3: "PNP_E_NOMEM",
+    -4: "PNP_E_PACKING", -5: "PNP_E_OVERFLOW", -6: "PNP_E_NONFINITE", -7: "PNP_E_DEVICE",
+    -8: "PNP_E_BUDGET",
+}
+
+EXPORTED = [
+    "pnp_create", "pnp_destroy", "pnp_last_error", "pnp_supported_size", "pnp_workspace_bytes",
+    "pnp_cdft_mu_ex", "pnp_weighted_densities", "pnp_batch_mu_ex", "pnp_read_status",
+    "pnp_relax_densities", "pnp_debug_rfft3",
+]
+
+
+class PnpError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Grid(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("h", ctypes.c_double)]
+
+
+class SpeciesC(ctypes.Structure):
+    _fields_ = [("d", ctypes.c_double), ("q", ctypes.c_double), ("rho_bulk", ctypes.c_double),
+                ("mu_el_bulk", ctypes.c_double)]
+
+
+class ParamsC(ctypes.Structure):
+    _fields_ = [("terms", ctypes.c_uint32), ("precision", ctypes.c_int32),
+                ("per_term", ctypes.c_int32), ("flags", ctypes.c_uint32),
+                ("eps_r", ctypes.c_double), ("sw_eps", ctypes.POINTER(ctypes.c_double)),
+                ("sw_rout", ctypes.POINTER(ctypes.c_double)), ("sw_gamma", ctypes.c_double),
+                ("sw_prefactor", ctypes.c_double)]
+
+
+class RequestC(ctypes.Structure):
+    _fields_ = [("grid", Grid), ("S", ctypes.c_int32), ("species", ctypes.POINTER(SpeciesC)),
+                ("rho", ctypes.c_void_p), ("T", ctypes.c_double),
+                ("params", ctypes.POINTER(ParamsC)), ("mu_ex", ctypes.c_void_p),
+                ("slotboom", ctypes.c_void_p), ("workspace", ctypes.c_void_p),
+                ("workspace_bytes", ctypes.c_size_t), ("status", ctypes.c_int32)]
+
+
+_LIB = None
+
+
+def lib_path() -> str:
+    return os.environ.get("PNP_CDFT_LIB", os.path.join(HERE, "libpnpcdft.so"))
+
+
+def load_library():
+    """Load libpnpcdft.so (built in-tree by paper_1407_0674_amd.build)."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    path = lib_path()
+    if not os.path.exists(path):
+        raise PnpError(-7, f"HIP library not built: {path} (run python -m paper_1407_0674_amd.build)")
+    lib = ctypes.CDLL(path)
+    P = ctypes.c_void_p
+    lib.pnp_create.argtypes = [ctypes.c_int, ctypes.POINTER(P)]
+    lib.pnp_destroy.argtypes = [P]
+    lib.pnp_destroy.restype = None
+    lib.pnp_last_error.argtypes = [P]
+    lib.pnp_last_error.restype = ctypes.c_char_p
+    lib.pnp_supported_size.argtypes = [ctypes.c_int32]
+    lib.pnp_workspace_bytes.argtypes = [P, ctypes.POINTER(Grid), ctypes.c_int32,
+                                        ctypes.POINTER(ParamsC), ctypes.POINTER(ctypes.c_size_t)]
+    lib.pnp_cdft_mu_ex.argtypes = [P, ctypes.POINTER(Grid), ctypes.c_int32, ctypes.POINTER(SpeciesC),
+                                   P, ctypes.c_double, ctypes.POINTER(ParamsC), P, P, P,
+                                   ctypes.c_size_t, P]
+    lib.pnp_weighted_densities.argtypes = [P, ctypes.POINTER(Grid), ctypes.c_int32,
+                                           ctypes.POINTER(SpeciesC), P, ctypes.POINTER(ParamsC), P,
+                                           P, ctypes.c_size_t, P]
+    lib.pnp_batch_mu_ex.argtypes = [P, ctypes.c_int32, ctypes.POINTER(RequestC), P]
+    lib.pnp_read_status.argtypes = [P, P, P]
+    lib.pnp_relax_densities.argtypes = [P, ctypes.POINTER(Grid), ctypes.c_int32,
+                                        ctypes.POINTER(SpeciesC), P, P,
+                                        ctypes.POINTER(ctypes.c_double), ctypes.c_double, P]
+    lib.pnp_debug_rfft3.argtypes = [P, ctypes.POINTER(Grid), ctypes.c_int32, ctypes.c_int32,
+                                    ctypes.c_int32, P, P, P, ctypes.c_size_t, P]
+    for name in EXPORTED:
+        f = getattr(lib, name)
+        if name not in ("pnp_destroy", "pnp_last_error"):
+            f.restype = ctypes.c_int
+    _LIB = lib
+    return lib
+
+
+class _Marshal:
+    """Host-side C records of one problem description (kept alive for a call)."""
+
+    def __init__(self, problem, per_term=False, flags=0, precision=None):
+        S = len(problem.species)
+        self.grid = Grid(problem.n, problem.n, problem.n, float(problem.h))
+        self.species = (SpeciesC * S)(*[SpeciesC(s.d, s.q, s.rho_bulk, s.mu_el_bulk)
+                                         for s in problem.species])
+        self._eps = None if problem.sw_eps is None else np.ascontiguousarray(problem.sw_eps, dtype=np.float64)
+        self._rout = None if problem.sw_rout is None else np.ascontiguousarray(problem.sw_rout, dtype=np.float64)
+        dp = ctypes.POINTER(ctypes.c_double)
+        self.params = ParamsC(
+            int(problem.terms), int(problem.precision if precision is None else precision),
+            int(bool(per_term)), int(flags), float(problem.eps_r),
+            self._eps.ctypes.data_as(dp) if self._eps is not None else dp(),
+            self._rout.ctypes.data_as(dp) if self._rout is not None else dp(),
+            float(problem.sw_gamma), float(problem.sw_prefactor))
+        self.S = S
+        self.T = float(problem.T)
+
+
+def _torch():
+    import torch
+    return torch
+
+
+class Evaluator:
+    """One library context on one GPU."""
+
+    def __init__(self, device: Optional[int] = None):
+        torch = _torch()
+        self.lib = load_library()
+        self.device = torch.cuda.current_device() if device is None else int(device)
+        ctx = ctypes.c_void_p()
+        st = self.lib.pnp_create(self.device, ctypes.byref(ctx))
+        if st != 0:
+            raise PnpError(st, "pnp_create failed")
+        self.ctx = ctx
+        self._ws = {}
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            self.lib.pnp_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- helpers -----------------------------------------------------------
+    def _check(self, st):
+        if st != 0:
+            raise PnpError(st, self.lib.pnp_last_error(self.ctx).decode())
+
+    def _stream(self):
+        return ctypes.c_void_p(_torch().cuda.current_stream().cuda_stream)
+
+    def workspace_bytes(self, problem, per_term=False, precision=None) -> int:
+        m = _Marshal(problem, per_term, precision=precision)
+        out = ctypes.c_size_t()
+        self._check(self.lib.pnp_workspace_bytes(self.ctx, ctypes.byref(m.grid), m.S,
+                                                 ctypes.byref(m.params), ctypes.byref(out)))
+        return int(out.value)
+
+    def workspace(self, nbytes: int, key="default"):
+        """A cached uint8 device buffer of at least nbytes (torch allocations
+        are 256-byte aligned)."""
+        torch = _torch()
+        buf = self._ws.get(key)
+        if buf is None or buf.numel() < nbytes:
+            buf = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=f"cuda:{self.device}")
+            self._ws[key] = buf
+        return buf
+
+    @staticmethod
+    def _dev(t, name):
+        torch = _torch()
+        if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+            raise PnpError(-1, f"{name} must be a contiguous float64 CUDA tensor")
+        return ctypes.c_void_p(t.data_ptr())
+
+    # -- the C ABI calls ------------------------------------------------------
+    def mu_ex(self, problem, rho, per_term=False, slotboom=True, out=None, slot=None,
+              workspace=None, flags=0, precision=None):
+        torch = _torch()
+        m = _Marshal(problem, per_term, flags, precision)
+        n3 = problem.n ** 3
+        if tuple(rho.shape) != (m.S, problem.n, problem.n, problem.n):
+            raise PnpError(-1, f"rho has shape {tuple(rho.shape)}")
+        if out is None:
+            shape = (3, m.S, problem.n, problem.n, problem.n) if per_term else (m.S, problem.n, problem.n, problem.n)
+            out = torch.empty(shape, dtype=torch.float64, device=rho.device)
+        if slotboom and slot is None:
+            slot = torch.empty((m.S, problem.n, problem.n, problem.n), dtype=torch.float64, device=rho.device)
+        nb = self.workspace_bytes(problem, per_term, precision)
+        ws = self.workspace(nb) if workspace is None else workspace
+        st = self.lib.pnp_cdft_mu_ex(
+            self.ctx, ctypes.byref(m.grid), m.S, m.species, self._dev(rho, "rho"), m.T,
+            ctypes.byref(m.params), self._dev(out, "mu_ex"),
+            self._dev(slot, "slotboom") if slotboom else ctypes.c_void_p(0),
+            ctypes.c_void_p(ws.data_ptr()), ctypes.c_size_t(ws.numel()), self._stream())
+        self._check(st)
+        return out, (slot if slotboom else None)
+
+    def weighted_densities(self, problem, rho, precision=None):
+        torch = _torch()
+        m = _Marshal(problem, False, 0, precision)
+        out = torch.empty((10, problem.n, problem.n, problem.n), dtype=torch.float64, device=rho.device)
+        q = problem.with_(terms=TERM_HS) if hasattr(problem, "with_") else problem
+        nb = self.workspace_bytes(q, False, precision)
+        ws = self.workspace(nb)
+        st = self.lib.pnp_weighted_densities(
+            self.ctx, ctypes.byref(m.grid), m.S, m.species, self._dev(rho, "rho"),
+            ctypes.byref(m.params), self._dev(out, "n_out"), ctypes.c_void_p(ws.data_ptr()),
+            ctypes.c_size_t(ws.numel()), self._stream())
+        self._check(st)
+        return out
+
+    def batch(self, problems: Sequence, rhos: Sequence, slotboom=True, workspaces=None,
+              outs=None, slots=None):
+        """Evaluate independent problems in shared launches.  Returns
+        (mu list, slot list, status list)."""
+        torch = _torch()
+        count = len(problems)
+        ms = [_Marshal(p) for p in problems]
+        reqs = (RequestC * count)()
+        keep = []
+        mus, sls = [], []
+        for r, (p, m, rho) in enumerate(zip(problems, ms, rhos)):
+            mu = outs[r] if outs is not None else torch.empty(tuple(rho.shape), dtype=torch.float64, device=rho.device)
+            sl = None
+            if slotboom:
+                sl = slots[r] if slots is not None else torch.empty(tuple(rho.shape), dtype=torch.float64, device=rho.device)
+            nb = self.workspace_bytes(p)
+            ws = workspaces[r] if workspaces is not None else torch.empty(nb, dtype=torch.uint8, device=rho.device)
+            keep.append(ws)
+            reqs[r].grid = m.grid
+            reqs[r].S = m.S
+            reqs[r].species = ctypes.cast(m.species, ctypes.POINTER(SpeciesC))
+            reqs[r].rho = self._dev(rho, "rho").value
+            reqs[r].T = m.T
+            reqs[r].params = ctypes.pointer(m.params)
+            reqs[r].mu_ex = mu.data_ptr()
+            reqs[r].slotboom = sl.data_ptr() if sl is not None else None
+            reqs[r].workspace = ws.data_ptr()
+            reqs[r].workspace_bytes = ws.numel()
+            mus.append(mu)
+            sls.append(sl)
+        st = self.lib.pnp_batch_mu_ex(self.ctx, count, reqs, self._stream())
+        self._check(st)
+        return mus, sls, [int(reqs[r].status) for r in range(count)]
+
+    def relax(self, problem, rho, mu, mu_bulk, lam=0.1):
+        m = _Marshal(problem)
+        mb = (ctypes.c_double * m.S)(*[float(x) for x in mu_bulk])
+        self._check(self.lib.pnp_relax_densities(self.ctx, ctypes.byref(m.grid), m.S, m.species,
+                                                 self._dev(rho, "rho"), self._dev(mu, "mu"), mb,
+                                                 float(lam), self._stream()))
+
+    def _fft_workspace(self, n, count, precision):
+        g = Grid(n, n, n, 1.0)
+        prm = ParamsC(0, int(precision), 0, 0, 1.0, ctypes.POINTER(ctypes.c_double)(),
+                      ctypes.POINTER(ctypes.c_double)(), 1.2, 0.5)
+        nb = ctypes.c_size_t()
+        self._check(self.lib.pnp_workspace_bytes(self.ctx, ctypes.byref(g), count, ctypes.byref(prm),
+                                                 ctypes.byref(nb)))
+        return self.workspace(int(nb.value), "fft")
+
+    def rfft3(self, x, precision=FP64):
+        """Forward 3D real DFT through the library's passes, numpy layout."""
+        torch = _torch()
+        count, n = x.shape[0], x.shape[1]
+        out = torch.empty((count, n, n, n // 2 + 1, 2), dtype=torch.float64, device=x.device)
+        g = Grid(n, n, n, 1.0)
+        ws = self._fft_workspace(n, count, precision)
+        self._check(self.lib.pnp_debug_rfft3(self.ctx, ctypes.byref(g), precision, count, 0,
+                                             self._dev(x, "in"), self._dev(out, "out"),
+                                             ctypes.c_void_p(ws.data_ptr()), ctypes.c_size_t(ws.numel()),
+                                             self._stream()))
+        return torch.view_as_complex(out)
+
+    def irfft3(self, X, precision=FP64):
+        """Unnormalised inverse (numpy irfftn times n^3) from numpy layout."""
+        torch = _torch()
+        count, n = X.shape[0], X.shape[1]
+        Xr = torch.view_as_real(X.contiguous()).contiguous()
+        out = torch.empty((count, n, n, n), dtype=torch.float64, device=X.device)
+        g = Grid(n, n, n, 1.0)
+        ws = self._fft_workspace(n, count, precision)
+        self._check(self.lib.pnp_debug_rfft3(self.ctx, ctypes.byref(g), precision, count, 1,
+                                             self._dev(Xr, "in"), self._dev(out, "out"),
+                                             ctypes.c_void_p(ws.data_ptr()), ctypes.c_size_t(ws.numel()),
+                                             self._stream()))
+        return out

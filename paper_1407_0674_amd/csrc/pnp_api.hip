@@ -1,0 +1,635 @@
+// Host driver of the C ABI declared in include/pnp_cdft.h.
+//
+// Responsibilities: argument validation, the physical constants and pair
+// parameters of Sec. 2.3 (in double on the host), the workspace layout, the
+// per-instance argument tables uploaded to a small context-owned device ring,
+// the launch sequence of the nine passes, batching of equal-size requests into
+// shared launches, and the device status word.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "pnp_cdft.h"
+#include "pnp_kernels.hip"
+
+using namespace pnp;
+
+struct pnp_ctx_s {
+  int device = 0;
+  std::string err;
+  char* arena = nullptr;      // device ring for argument tables
+  size_t arena_bytes = 0;
+  size_t arena_pos = 0;
+};
+
+namespace {
+
+constexpr double kElementaryCharge = 1.602176634e-19;  // C
+constexpr double kVacuumPermittivity = 8.8541878128e-12;  // F/m
+constexpr double kBoltzmann = 1.380649e-23;  // J/K
+constexpr double kBoltzmannEv = kBoltzmann / kElementaryCharge;  // eV/K
+// e^2 / (4 pi eps0) in eV nm
+const double kCoulombEvNm = kElementaryCharge / (4.0 * M_PI * kVacuumPermittivity) * 1e9;
+
+constexpr size_t kAlign = 256;
+inline size_t up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+pnp_status fail(pnp_ctx c, pnp_status s, const std::string& m) {
+  if (c) c->err = m;
+  return s;
+}
+
+bool size_ok(int n) {
+  switch (n) {
+    case 8: case 16: case 24: case 32: case 48: case 64: case 96: case 128: case 192: case 256:
+      return true;
+    default:
+      return false;
+  }
+}
+
+// Derived quantities of one evaluation (host, double precision).
+struct Derived {
+  int n = 0, S = 0, np = 0, precision = 0;
+  bool hs = false, ec = false, sw = false;
+  double beta = 0, lB = 0, kappa = 0;
+  double sigma[kMaxPairs], B[kMaxPairs], rout[kMaxPairs], eps[kMaxPairs];
+  int pi[kMaxSpecies][kMaxSpecies];
+  double cfin_ec[kMaxSpecies];
+};
+
+struct Layout {
+  size_t status, hs, rsq, pair, pair2, A, B, C, total;
+  long fstride;
+  int M;
+};
+
+Layout layout_of(int n, int S, int precision, bool hs, bool pairs, bool per_term) {
+  Layout L{};
+  const size_t ts = precision == PNP_MIXED ? 4 : 8;
+  const long H = n / 2;
+  L.M = (int)(3 * H * H + 1);
+  L.fstride = (long)n * n * H + (long)n * n;
+  const int np = S * (S + 1) / 2;
+  size_t o = 0;
+  L.status = o; o = up(o + 64);
+  L.hs = o; o = up(o + (size_t)L.M * 3 * S * ts);
+  L.rsq = o; o = up(o + (size_t)L.M * ts);
+  L.pair = o; if (pairs) o = up(o + (size_t)L.M * np * ts);
+  L.pair2 = o; if (pairs && per_term) o = up(o + (size_t)L.M * np * ts);
+  L.A = o; o = up(o + (size_t)S * L.fstride * 2 * ts);
+  L.B = o; if (hs) o = up(o + (size_t)kFields * L.fstride * 2 * ts);
+  L.C = o; o = up(o + (size_t)S * L.fstride * 2 * ts);
+  L.total = o;
+  return L;
+}
+
+pnp_status validate(pnp_ctx ctx, const pnp_grid* g, int S, const pnp_species* sp, double T,
+                    const pnp_params* p, Derived& d, bool need_T) {
+  if (!ctx) return PNP_E_ARG;
+  if (!g || !sp || !p) return fail(ctx, PNP_E_ARG, "null grid, species or params");
+  if (g->nx != g->ny || g->ny != g->nz) return fail(ctx, PNP_E_UNSUPPORTED_SIZE, "grid must be cubic (nx = ny = nz)");
+  if (!size_ok(g->nx))
+    return fail(ctx, PNP_E_UNSUPPORTED_SIZE, "grid size " + std::to_string(g->nx) + " not supported");
+  if (!(g->h > 0.0) || !std::isfinite(g->h)) return fail(ctx, PNP_E_ARG, "spacing h must be > 0");
+  if (S < 1 || S > kMaxSpecies) return fail(ctx, PNP_E_ARG, "species count must be in [1, 8]");
+  if (p->terms == 0 || (p->terms & ~7u)) return fail(ctx, PNP_E_ARG, "terms must be a non-empty PNP_TERM_* mask");
+  if (p->precision != PNP_FP64 && p->precision != PNP_MIXED) return fail(ctx, PNP_E_ARG, "bad precision");
+  if (need_T && !(T > 0.0 && std::isfinite(T))) return fail(ctx, PNP_E_ARG, "temperature must be > 0");
+  for (int i = 0; i < S; ++i)
+    if (!(sp[i].d > 0.0) || !std::isfinite(sp[i].q) || !std::isfinite(sp[i].rho_bulk) ||
+        !std::isfinite(sp[i].mu_el_bulk))
+      return fail(ctx, PNP_E_ARG, "species " + std::to_string(i) + ": bad diameter, valence or bulk density");
+  d.n = g->nx; d.S = S; d.np = S * (S + 1) / 2; d.precision = p->precision;
+  d.hs = p->terms & PNP_TERM_HS; d.ec = p->terms & PNP_TERM_EC; d.sw = p->terms & PNP_TERM_SW;
+  if (need_T) {
+    if (d.ec && !(p->eps_r > 0.0)) return fail(ctx, PNP_E_ARG, "eps_r must be > 0");
+    d.beta = 1.0 / (kBoltzmannEv * T);
+    d.lB = d.ec ? kCoulombEvNm / p->eps_r * d.beta : 0.0;
+    double k2 = 0.0;
+    for (int i = 0; i < S; ++i) k2 += sp[i].rho_bulk * sp[i].q * sp[i].q;
+    d.kappa = std::sqrt(std::max(0.0, 4.0 * M_PI * d.lB * k2));
+  }
+  int q = 0;
+  for (int i = 0; i < S; ++i)
+    for (int j = i; j < S; ++j, ++q) {
+      d.pi[i][j] = d.pi[j][i] = q;
+      const double s = 0.5 * (sp[i].d + sp[j].d);
+      d.sigma[q] = s;
+      const double xi = d.kappa * s;
+      d.B[q] = xi == 0.0 ? 0.0 : xi / (xi + 1.0 + std::sqrt(1.0 + 2.0 * xi));
+      double e = 0.0, ro = 0.0;
+      if (p->sw_eps) {
+        e = p->sw_eps[i * S + j];
+        if (std::fabs(e - p->sw_eps[j * S + i]) > 1e-12 * std::max(1.0, std::fabs(e)))
+          return fail(ctx, PNP_E_ARG, "sw_eps must be symmetric");
+      }
+      if (p->sw_rout) ro = p->sw_rout[i * S + j];
+      if (!(ro > 0.0)) ro = (p->sw_gamma > 0.0 ? p->sw_gamma : 1.2) * s;
+      d.eps[q] = e;
+      d.rout[q] = ro;
+    }
+  for (int i = 0; i < S; ++i) {
+    double c = sp[i].mu_el_bulk;
+    if (d.ec)
+      for (int j = 0; j < S; ++j) {
+        const int pq = d.pi[i][j];
+        const double s = d.sigma[pq], b = d.B[pq];
+        // integral of C_ij over the ball r <= sigma (Sec. 2.3.4)
+        const double c0 = -sp[i].q * sp[j].q * d.lB * M_PI * s * s * (8.0 * b / 3.0 - b * b - 2.0);
+        c += c0 * sp[j].rho_bulk;
+      }
+    d.cfin_ec[i] = c;
+  }
+  return PNP_OK;
+}
+
+void fill_table_args(TableArgs& t, const Derived& d, const pnp_species* sp, double h, double sw_pref_scale,
+                     bool ec, bool sw, void* hs, void* rsq, void* pair, int M) {
+  std::memset(&t, 0, sizeof(t));
+  t.n = d.n; t.S = d.S; t.np = d.np; t.M = M;
+  t.kscale = 2.0 * M_PI / (d.n * h);
+  for (int i = 0; i < d.S; ++i) t.R[i] = 0.5 * sp[i].d;
+  int q = 0;
+  for (int i = 0; i < d.S; ++i)
+    for (int j = i; j < d.S; ++j, ++q) {
+      t.sigma[q] = d.sigma[q];
+      t.Bsig[q] = d.B[q] / d.sigma[q];
+      t.ec_pref[q] = ec ? sp[i].q * sp[j].q * d.lB : 0.0;
+      t.sw_pref[q] = sw ? -d.beta * sw_pref_scale * d.eps[q] : 0.0;
+      t.rout[q] = d.rout[q];
+    }
+  t.hs_tab = hs; t.rsq_tab = rsq; t.pair_tab = pair;
+  t.single = d.precision == PNP_MIXED;
+}
+
+void fill_eval_args(EvalArgs& e, const Derived& d, const pnp_species* sp, const Layout& L, char* ws,
+                    const double* rho) {
+  std::memset(&e, 0, sizeof(e));
+  e.n = d.n; e.S = d.S; e.np = d.np;
+  e.hs_on = d.hs; e.pair_on = d.ec || d.sw;
+  e.fstride = L.fstride;
+  e.inv_n3 = 1.0 / ((double)d.n * d.n * d.n);
+  for (int i = 0; i < d.S; ++i) {
+    const double R = 0.5 * sp[i].d;
+    e.R[i] = R;
+    e.area[i] = 4.0 * M_PI * R * R;
+    e.inv4piR[i] = 1.0 / (4.0 * M_PI * R);
+    e.cfin[i] = d.cfin_ec[i];
+    for (int j = 0; j < d.S; ++j) e.pidx[i][j] = (int8_t)d.pi[i][j];
+  }
+  e.rho = rho;
+  e.specA = ws + L.A;
+  e.specB = ws + L.B;
+  e.specC = ws + L.C;
+  e.hs_tab = ws + L.hs;
+  e.rsq_tab = ws + L.rsq;
+  e.pair_tab = ws + L.pair;
+  e.status = (uint32_t*)(ws + L.status);
+  e.final_mode = 1;
+  e.nreal = d.S;
+}
+
+// copy host bytes into the context's device ring (stream ordered)
+void* upload(pnp_ctx c, const void* src, size_t bytes, hipStream_t s) {
+  const size_t need = up(bytes);
+  if (c->arena_pos + need > c->arena_bytes) c->arena_pos = 0;
+  void* dst = c->arena + c->arena_pos;
+  c->arena_pos += need;
+  if (hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s) != hipSuccess) return nullptr;
+  return dst;
+}
+
+pnp_status device_check(pnp_ctx c, const char* where) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(c, PNP_E_DEVICE, std::string(where) + ": " + hipGetErrorString(e));
+  return PNP_OK;
+}
+
+pnp_status status_of(pnp_ctx c, const uint32_t st[2]) {
+  if (st[0] == 0) return PNP_OK;
+  const std::string at = " (first flat index " + std::to_string(st[1]) + ")";
+  if (st[0] & kStPacking) return fail(c, PNP_E_PACKING, "weighted density n3 >= 1" + at);
+  if (st[0] & kStNonFinite) return fail(c, PNP_E_NONFINITE, "non-finite value" + at);
+  return fail(c, PNP_E_OVERFLOW, "exp(-beta mu_ex) overflows" + at);
+}
+
+pnp_status read_status(pnp_ctx c, const void* status_dev, hipStream_t s) {
+  uint32_t st[2] = {0, 0};
+  if (hipMemcpyAsync(st, status_dev, sizeof(st), hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return device_check(c, "status read");
+  return status_of(c, st);
+}
+
+// ---------------------------------------------------------------------------
+// launchers per (precision, n)
+// ---------------------------------------------------------------------------
+struct Ops {
+  void (*tables)(const TableArgs*, int, int, hipStream_t);
+  void (*zfwd)(const EvalArgs*, int, hipStream_t);
+  void (*ystep)(const EvalArgs*, int, int, int, bool, hipStream_t);
+  void (*xfwd)(const EvalArgs*, int, hipStream_t);
+  void (*zderiv)(const EvalArgs*, int, hipStream_t);
+  void (*xback)(const EvalArgs*, int, int, hipStream_t);
+  void (*zinv)(const EvalArgs*, int, int, hipStream_t);
+  void (*xplain)(const EvalArgs*, int, int, bool, hipStream_t);
+  void (*xport)(const EvalArgs*, int, double*, int, hipStream_t);
+};
+
+template <typename T, int N> struct Launch {
+  using G = Geo<T, N>;
+  static void tables(const TableArgs* a, int count, int M, hipStream_t s) {
+    const int bp = (M + 255) / 256;
+    hipLaunchKernelGGL(k_tables<T>, dim3(count * bp), dim3(256), 0, s, a, bp);
+  }
+  static void zfwd(const EvalArgs* a, int count, hipStream_t s) {
+    hipLaunchKernelGGL((k_zfwd<T, N>), dim3(count * G::tiles_z), dim3(G::RZ * G::TZ), 0, s, a);
+  }
+  static void ystep(const EvalArgs* a, int count, int sel, int nf, bool fwd, hipStream_t s) {
+    if (fwd)
+      hipLaunchKernelGGL((k_ystep<T, N, true>), dim3(count * G::tiles_y), dim3(G::PY * G::TY), 0, s, a, sel, nf);
+    else
+      hipLaunchKernelGGL((k_ystep<T, N, false>), dim3(count * G::tiles_y), dim3(G::PY * G::TY), 0, s, a, sel, nf);
+  }
+  static void xfwd(const EvalArgs* a, int count, hipStream_t s) {
+    hipLaunchKernelGGL((k_xfwd<T, N>), dim3(count * G::tiles_x), dim3(G::PX * G::TX), 0, s, a);
+  }
+  static void zderiv(const EvalArgs* a, int count, hipStream_t s) {
+    hipLaunchKernelGGL((k_zderiv<T, N>), dim3(count * G::tiles_d), dim3(G::RD * G::TZ), 0, s, a);
+  }
+  static void xback(const EvalArgs* a, int count, int ch, hipStream_t s) {
+    const dim3 g(count * G::tiles_x), b(G::PX * G::TX);
+    switch (ch) {
+      case 1: hipLaunchKernelGGL((k_xback<T, N, 1>), g, b, 0, s, a); break;
+      case 2: hipLaunchKernelGGL((k_xback<T, N, 2>), g, b, 0, s, a); break;
+      case 3: hipLaunchKernelGGL((k_xback<T, N, 3>), g, b, 0, s, a); break;
+      default: hipLaunchKernelGGL((k_xback<T, N, 4>), g, b, 0, s, a); break;
+    }
+  }
+  static void zinv(const EvalArgs* a, int count, int sel, hipStream_t s) {
+    hipLaunchKernelGGL((k_zinv<T, N>), dim3(count * G::tiles_z), dim3(G::RZ * G::TZ), 0, s, a, sel);
+  }
+  static void xplain(const EvalArgs* a, int count, int nf, bool fwd, hipStream_t s) {
+    if (fwd)
+      hipLaunchKernelGGL((k_xplain<T, N, true>), dim3(count * G::tiles_x), dim3(G::PX * G::TX), 0, s, a, 0, nf);
+    else
+      hipLaunchKernelGGL((k_xplain<T, N, false>), dim3(count * G::tiles_x), dim3(G::PX * G::TX), 0, s, a, 0, nf);
+  }
+  static void xport(const EvalArgs* a, int nf, double* buf, int to_numpy, hipStream_t s) {
+    const long total = (long)nf * N * N * (N / 2 + 1);
+    const int blocks = (int)std::min<long>((total + 255) / 256, 4096);
+    hipLaunchKernelGGL((k_export<T, N>), dim3(blocks), dim3(256), 0, s, a, nf, buf, to_numpy);
+  }
+  static constexpr Ops ops{tables, zfwd, ystep, xfwd, zderiv, xback, zinv, xplain, xport};
+};
+
+template <typename T>
+const Ops* ops_for_n(int n) {
+  switch (n) {
+    case 8: return &Launch<T, 8>::ops;
+    case 16: return &Launch<T, 16>::ops;
+    case 24: return &Launch<T, 24>::ops;
+    case 32: return &Launch<T, 32>::ops;
+    case 48: return &Launch<T, 48>::ops;
+    case 64: return &Launch<T, 64>::ops;
+    case 96: return &Launch<T, 96>::ops;
+    case 128: return &Launch<T, 128>::ops;
+    case 192: return &Launch<T, 192>::ops;
+    case 256: return &Launch<T, 256>::ops;
+    default: return nullptr;
+  }
+}
+
+const Ops* ops_for(int precision, int n) {
+  return precision == PNP_MIXED ? ops_for_n<float>(n) : ops_for_n<double>(n);
+}
+
+// The full launch sequence for `count` instances of one size and precision.
+// ea: device arg tables; hs_any: some instance has the HS term on;
+// pair_any likewise; ch: output chunk of the back pass.
+void run_sequence(const Ops* op, const EvalArgs* ea, const TableArgs* ta, int count, int M, bool hs_any,
+                  bool pair_any, int ch, hipStream_t s) {
+  op->tables(ta, count, M, s);
+  op->zfwd(ea, count, s);
+  op->ystep(ea, count, 0, -1, true, s);
+  if (hs_any) {
+    op->xfwd(ea, count, s);
+    op->ystep(ea, count, 1, kFields, false, s);
+    op->zderiv(ea, count, s);
+    op->ystep(ea, count, 1, kFields, true, s);
+  }
+  (void)pair_any;
+  op->xback(ea, count, ch, s);
+  op->ystep(ea, count, 2, -1, false, s);
+  op->zinv(ea, count, 2, s);
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+pnp_status pnp_create(int device, pnp_ctx* out) {
+  if (!out) return PNP_E_ARG;
+  *out = nullptr;
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count) return PNP_E_DEVICE;
+  pnp_ctx c = new pnp_ctx_s();
+  c->device = device;
+  c->arena_bytes = 4u << 20;
+  if (hipSetDevice(device) != hipSuccess || hipMalloc((void**)&c->arena, c->arena_bytes) != hipSuccess) {
+    delete c;
+    return PNP_E_DEVICE;
+  }
+  *out = c;
+  return PNP_OK;
+}
+
+void pnp_destroy(pnp_ctx c) {
+  if (!c) return;
+  if (c->arena) {
+    hipSetDevice(c->device);
+    hipDeviceSynchronize();
+    hipFree(c->arena);
+  }
+  delete c;
+}
+
+const char* pnp_last_error(pnp_ctx c) { return c ? c->err.c_str() : "null context"; }
+
+int pnp_supported_size(int32_t n) { return size_ok(n) ? 1 : 0; }
+
+pnp_status pnp_workspace_bytes(pnp_ctx ctx, const pnp_grid* g, int32_t S, const pnp_params* p, size_t* bytes) {
+  if (!ctx || !g || !p || !bytes) return fail(ctx, PNP_E_ARG, "null argument");
+  if (g->nx != g->ny || g->ny != g->nz || !size_ok(g->nx))
+    return fail(ctx, PNP_E_UNSUPPORTED_SIZE, "unsupported grid");
+  if (S < 1 || S > kMaxSpecies) return fail(ctx, PNP_E_ARG, "species count must be in [1, 8]");
+  if (p->precision != PNP_FP64 && p->precision != PNP_MIXED) return fail(ctx, PNP_E_ARG, "bad precision");
+  const bool hs = p->terms & PNP_TERM_HS, pairs = p->terms & (PNP_TERM_EC | PNP_TERM_SW);
+  *bytes = layout_of(g->nx, S, p->precision, hs, pairs, p->per_term).total;
+  return PNP_OK;
+}
+
+pnp_status pnp_cdft_mu_ex(pnp_ctx ctx, const pnp_grid* g, int32_t S, const pnp_species* sp, const double* rho,
+                          double T, const pnp_params* p, double* mu, double* slot, void* ws, size_t ws_bytes,
+                          void* stream) {
+  Derived d;
+  pnp_status st = validate(ctx, g, S, sp, T, p, d, true);
+  if (st != PNP_OK) return st;
+  if (!rho || !mu || !ws) return fail(ctx, PNP_E_ARG, "null device pointer");
+  if ((uintptr_t)ws % kAlign) return fail(ctx, PNP_E_ARG, "workspace must be 256-byte aligned");
+  const bool pairs = d.ec || d.sw;
+  const Layout L = layout_of(d.n, S, d.precision, d.hs, pairs, p->per_term);
+  if (ws_bytes < L.total) return fail(ctx, PNP_E_NOMEM, "workspace too small: need " + std::to_string(L.total));
+  if (hipSetDevice(ctx->device) != hipSuccess) return device_check(ctx, "set device");
+  hipStream_t s = (hipStream_t)stream;
+  const Ops* op = ops_for(d.precision, d.n);
+  char* w = (char*)ws;
+  const double sw_c = p->sw_prefactor;
+  const int ch = std::min(S, 4);
+  const long n3 = (long)d.n * d.n * d.n;
+
+  if (!p->per_term) {
+    TableArgs ta;
+    fill_table_args(ta, d, sp, g->h, sw_c, d.ec, d.sw, w + L.hs, w + L.rsq, pairs ? w + L.pair : nullptr, L.M);
+    EvalArgs ea;
+    fill_eval_args(ea, d, sp, L, w, rho);
+    ea.out = mu;
+    ea.slot = slot;
+    const TableArgs* dta = (const TableArgs*)upload(ctx, &ta, sizeof(ta), s);
+    const EvalArgs* dea = (const EvalArgs*)upload(ctx, &ea, sizeof(ea), s);
+    if (!dta || !dea) return device_check(ctx, "argument upload");
+    run_sequence(op, dea, dta, 1, L.M, d.hs, pairs, ch, s);
+  } else {
+    // tables: HS (+ EC pairs into pair), SW pairs into pair2
+    TableArgs ta[2];
+    fill_table_args(ta[0], d, sp, g->h, sw_c, d.ec, false, w + L.hs, w + L.rsq, pairs ? w + L.pair : nullptr, L.M);
+    fill_table_args(ta[1], d, sp, g->h, sw_c, false, d.sw, w + L.hs, w + L.rsq, pairs ? w + L.pair2 : nullptr,
+                    L.M);
+    // four argument records: forward half, hs-only, el-only, sh-only
+    EvalArgs ea[4];
+    for (int k = 0; k < 4; ++k) {
+      fill_eval_args(ea[k], d, sp, L, w, rho);
+      ea[k].slot = nullptr;
+    }
+    ea[0].out = mu;
+    ea[1].out = mu; ea[1].pair_on = 0;
+    for (int i = 0; i < S; ++i) ea[1].cfin[i] = 0.0;
+    ea[2].out = mu + (long)S * n3; ea[2].hs_on = 0; ea[2].pair_on = d.ec;
+    ea[3].out = mu + 2L * S * n3; ea[3].hs_on = 0; ea[3].pair_on = d.sw; ea[3].pair_tab = w + L.pair2;
+    for (int i = 0; i < S; ++i) ea[3].cfin[i] = 0.0;
+    if (!d.ec) for (int i = 0; i < S; ++i) ea[2].cfin[i] = 0.0;
+    if (!d.hs) ea[1].hs_on = 0;
+    const TableArgs* dta = (const TableArgs*)upload(ctx, ta, sizeof(ta), s);
+    const EvalArgs* dea = (const EvalArgs*)upload(ctx, ea, sizeof(ea), s);
+    if (!dta || !dea) return device_check(ctx, "argument upload");
+    op->tables(dta, 1, L.M, s);
+    if (d.sw) op->tables(dta + 1, 1, L.M, s);
+    op->zfwd(dea, 1, s);
+    op->ystep(dea, 1, 0, -1, true, s);
+    if (d.hs) {
+      op->xfwd(dea, 1, s);
+      op->ystep(dea, 1, 1, kFields, false, s);
+      op->zderiv(dea, 1, s);
+      op->ystep(dea, 1, 1, kFields, true, s);
+    }
+    for (int k = 1; k < 4; ++k) {
+      op->xback(dea + k, 1, ch, s);
+      op->ystep(dea + k, 1, 2, -1, false, s);
+      op->zinv(dea + k, 1, 2, s);
+    }
+    const long sn3 = (long)S * n3;
+    const int blocks = (int)std::min<long>((sn3 + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_sum_exp, dim3(blocks), dim3(256), 0, s, (const double*)mu, slot, sn3,
+                       (uint32_t*)(w + L.status));
+  }
+  st = device_check(ctx, "launch");
+  if (st != PNP_OK) return st;
+  if (p->flags & PNP_FLAG_ASYNC) return PNP_OK;
+  return read_status(ctx, w + L.status, s);
+}
+
+pnp_status pnp_weighted_densities(pnp_ctx ctx, const pnp_grid* g, int32_t S, const pnp_species* sp,
+                                  const double* rho, const pnp_params* p, double* n_out, void* ws,
+                                  size_t ws_bytes, void* stream) {
+  Derived d;
+  pnp_params q = *p;
+  q.terms = PNP_TERM_HS;
+  q.per_term = 0;
+  pnp_status st = validate(ctx, g, S, sp, 300.0, &q, d, false);
+  if (st != PNP_OK) return st;
+  if (!rho || !n_out || !ws) return fail(ctx, PNP_E_ARG, "null device pointer");
+  if ((uintptr_t)ws % kAlign) return fail(ctx, PNP_E_ARG, "workspace must be 256-byte aligned");
+  const Layout L = layout_of(d.n, S, d.precision, true, false, false);
+  if (ws_bytes < L.total) return fail(ctx, PNP_E_NOMEM, "workspace too small: need " + std::to_string(L.total));
+  if (hipSetDevice(ctx->device) != hipSuccess) return device_check(ctx, "set device");
+  hipStream_t s = (hipStream_t)stream;
+  const Ops* op = ops_for(d.precision, d.n);
+  char* w = (char*)ws;
+  TableArgs ta;
+  fill_table_args(ta, d, sp, g->h, 0.0, false, false, w + L.hs, w + L.rsq, nullptr, L.M);
+  EvalArgs ea;
+  fill_eval_args(ea, d, sp, L, w, rho);
+  ea.final_mode = 0;
+  ea.nreal = kFields;
+  ea.out = n_out;
+  const TableArgs* dta = (const TableArgs*)upload(ctx, &ta, sizeof(ta), s);
+  const EvalArgs* dea = (const EvalArgs*)upload(ctx, &ea, sizeof(ea), s);
+  if (!dta || !dea) return device_check(ctx, "argument upload");
+  op->tables(dta, 1, L.M, s);
+  op->zfwd(dea, 1, s);
+  op->ystep(dea, 1, 0, -1, true, s);
+  op->xfwd(dea, 1, s);
+  op->ystep(dea, 1, 1, kFields, false, s);
+  op->zinv(dea, 1, 1, s);
+  st = device_check(ctx, "launch");
+  if (st != PNP_OK) return st;
+  if (p->flags & PNP_FLAG_ASYNC) return PNP_OK;
+  return read_status(ctx, w + L.status, s);
+}
+
+pnp_status pnp_batch_mu_ex(pnp_ctx ctx, int32_t count, pnp_request* reqs, void* stream) {
+  if (!ctx) return PNP_E_ARG;
+  if (count < 0 || (count > 0 && !reqs)) return fail(ctx, PNP_E_ARG, "bad request array");
+  if (hipSetDevice(ctx->device) != hipSuccess) return device_check(ctx, "set device");
+  hipStream_t s = (hipStream_t)stream;
+  // validate each request; group the valid ones by (precision, n)
+  std::map<std::pair<int, int>, std::vector<int>> groups;
+  std::vector<Derived> der(count);
+  std::vector<Layout> lay(count);
+  for (int r = 0; r < count; ++r) {
+    pnp_request& q = reqs[r];
+    q.status = PNP_OK;
+    pnp_status st = validate(ctx, &q.grid, q.S, q.species, q.T, q.params, der[r], true);
+    if (st == PNP_OK && (!q.rho || !q.mu_ex || !q.workspace)) st = fail(ctx, PNP_E_ARG, "null device pointer");
+    if (st == PNP_OK && q.params->per_term) st = fail(ctx, PNP_E_ARG, "per_term is not available in batches");
+    if (st == PNP_OK && ((uintptr_t)q.workspace % kAlign)) st = fail(ctx, PNP_E_ARG, "workspace alignment");
+    if (st == PNP_OK) {
+      const Derived& d = der[r];
+      lay[r] = layout_of(d.n, q.S, d.precision, d.hs, d.ec || d.sw, false);
+      if (q.workspace_bytes < lay[r].total) st = fail(ctx, PNP_E_NOMEM, "workspace too small");
+    }
+    q.status = st;
+    if (st == PNP_OK) groups[{der[r].precision, der[r].n}].push_back(r);
+  }
+  for (auto& kv : groups) {
+    const std::vector<int>& ids = kv.second;
+    const int cnt = (int)ids.size();
+    std::vector<TableArgs> ta(cnt);
+    std::vector<EvalArgs> ea(cnt);
+    bool hs_any = false, pair_any = false;
+    int maxS = 1;
+    for (int k = 0; k < cnt; ++k) {
+      pnp_request& q = reqs[ids[k]];
+      const Derived& d = der[ids[k]];
+      const Layout& L = lay[ids[k]];
+      char* w = (char*)q.workspace;
+      const bool pairs = d.ec || d.sw;
+      fill_table_args(ta[k], d, q.species, q.grid.h, q.params->sw_prefactor, d.ec, d.sw, w + L.hs, w + L.rsq,
+                      pairs ? w + L.pair : nullptr, L.M);
+      fill_eval_args(ea[k], d, q.species, L, w, q.rho);
+      ea[k].out = q.mu_ex;
+      ea[k].slot = q.slotboom;
+      hs_any |= d.hs;
+      pair_any |= pairs;
+      maxS = std::max(maxS, q.S);
+    }
+    const TableArgs* dta = (const TableArgs*)upload(ctx, ta.data(), sizeof(TableArgs) * cnt, s);
+    const EvalArgs* dea = (const EvalArgs*)upload(ctx, ea.data(), sizeof(EvalArgs) * cnt, s);
+    if (!dta || !dea) return device_check(ctx, "argument upload");
+    const Ops* op = ops_for(kv.first.first, kv.first.second);
+    int M = 0;
+    for (int k = 0; k < cnt; ++k) M = std::max(M, lay[ids[k]].M);
+    run_sequence(op, dea, dta, cnt, M, hs_any, pair_any, std::min(maxS, 4), s);
+  }
+  pnp_status st = device_check(ctx, "batch launch");
+  if (st != PNP_OK) return st;
+  bool async = false;
+  for (int r = 0; r < count; ++r)
+    if (reqs[r].status == PNP_OK && (reqs[r].params->flags & PNP_FLAG_ASYNC)) async = true;
+  if (async) return PNP_OK;
+  // one synchronisation for the whole batch, then each request's own status
+  std::vector<uint32_t> words(2 * (size_t)count, 0u);
+  for (int r = 0; r < count; ++r)
+    if (reqs[r].status == PNP_OK)
+      if (hipMemcpyAsync(&words[2 * r], (char*)reqs[r].workspace + lay[r].status, 8, hipMemcpyDeviceToHost, s) !=
+          hipSuccess)
+        return device_check(ctx, "status read");
+  if (hipStreamSynchronize(s) != hipSuccess) return device_check(ctx, "batch sync");
+  for (int r = 0; r < count; ++r)
+    if (reqs[r].status == PNP_OK) reqs[r].status = status_of(ctx, &words[2 * r]);
+  return PNP_OK;
+}
+
+pnp_status pnp_read_status(pnp_ctx ctx, const void* ws, void* stream) {
+  if (!ctx || !ws) return fail(ctx, PNP_E_ARG, "null argument");
+  if (hipSetDevice(ctx->device) != hipSuccess) return device_check(ctx, "set device");
+  return read_status(ctx, ws, (hipStream_t)stream);
+}
+
+pnp_status pnp_relax_densities(pnp_ctx ctx, const pnp_grid* g, int32_t S, const pnp_species* sp, double* rho,
+                               const double* mu, const double* mu_bulk, double lambda, void* stream) {
+  if (!ctx) return PNP_E_ARG;
+  if (!g || !sp || !rho || !mu || !mu_bulk) return fail(ctx, PNP_E_ARG, "null argument");
+  if (g->nx != g->ny || g->ny != g->nz || !size_ok(g->nx)) return fail(ctx, PNP_E_UNSUPPORTED_SIZE, "bad grid");
+  if (S < 1 || S > kMaxSpecies) return fail(ctx, PNP_E_ARG, "species count");
+  if (!(lambda >= 0.0 && lambda <= 1.0)) return fail(ctx, PNP_E_ARG, "lambda must be in [0, 1]");
+  if (hipSetDevice(ctx->device) != hipSuccess) return device_check(ctx, "set device");
+  hipStream_t s = (hipStream_t)stream;
+  double rb[2 * kMaxSpecies];
+  for (int i = 0; i < S; ++i) { rb[2 * i] = sp[i].rho_bulk; rb[2 * i + 1] = mu_bulk[i]; }
+  const double* drb = (const double*)upload(ctx, rb, sizeof(double) * 2 * S, s);
+  if (!drb) return device_check(ctx, "argument upload");
+  const long n3 = (long)g->nx * g->ny * g->nz;
+  const int blocks = (int)std::min<long>((S * n3 + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_relax, dim3(blocks), dim3(256), 0, s, rho, mu, n3, (int)S, drb, lambda);
+  return device_check(ctx, "relax launch");
+}
+
+pnp_status pnp_debug_rfft3(pnp_ctx ctx, const pnp_grid* g, int32_t precision, int32_t count, int32_t inverse,
+                           const double* in, double* out, void* ws, size_t ws_bytes, void* stream) {
+  if (!ctx) return PNP_E_ARG;
+  if (!g || !in || !out || !ws) return fail(ctx, PNP_E_ARG, "null argument");
+  if (g->nx != g->ny || g->ny != g->nz || !size_ok(g->nx)) return fail(ctx, PNP_E_UNSUPPORTED_SIZE, "bad grid");
+  if (count < 1 || count > kMaxSpecies) return fail(ctx, PNP_E_ARG, "count must be in [1, 8]");
+  if (precision != PNP_FP64 && precision != PNP_MIXED) return fail(ctx, PNP_E_ARG, "bad precision");
+  const int n = g->nx;
+  const Layout L = layout_of(n, count, precision, false, false, false);
+  if (ws_bytes < L.total) return fail(ctx, PNP_E_NOMEM, "workspace too small: need " + std::to_string(L.total));
+  if (hipSetDevice(ctx->device) != hipSuccess) return device_check(ctx, "set device");
+  hipStream_t s = (hipStream_t)stream;
+  const Ops* op = ops_for(precision, n);
+  char* w = (char*)ws;
+  EvalArgs ea;
+  std::memset(&ea, 0, sizeof(ea));
+  ea.n = n; ea.S = count; ea.fstride = L.fstride; ea.specA = w + L.A; ea.specC = w + L.A;
+  ea.status = (uint32_t*)(w + L.status); ea.rho = in; ea.out = out; ea.nreal = count; ea.final_mode = 0;
+  const EvalArgs* dea = (const EvalArgs*)upload(ctx, &ea, sizeof(ea), s);
+  if (!dea) return device_check(ctx, "argument upload");
+  if (!inverse) {
+    op->zfwd(dea, 1, s);
+    op->ystep(dea, 1, 0, -1, true, s);
+    op->xplain(dea, 1, count, true, s);
+    op->xport(dea, count, out, 1, s);
+  } else {
+    op->xport(dea, count, (double*)in, 0, s);
+    op->xplain(dea, 1, count, false, s);
+    op->ystep(dea, 1, 0, -1, false, s);
+    op->zinv(dea, 1, 0, s);
+  }
+  pnp_status st = device_check(ctx, "launch");
+  if (st != PNP_OK) return st;
+  if (hipStreamSynchronize(s) != hipSuccess) return device_check(ctx, "sync");
+  return PNP_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,60 @@
+// Shared definitions between the HIP kernels and the host driver of the
+// cDFT excess-chemical-potential evaluator.
+#pragma once
+#include <stdint.h>
+
+namespace pnp {
+
+constexpr int kMaxSpecies = 8;
+constexpr int kMaxPairs = kMaxSpecies * (kMaxSpecies + 1) / 2;
+constexpr int kFields = 10;  // n0, n1, n2, n3, n1v(x,y,z), n2v(x,y,z)
+
+// status word bits (word 0); word 1 holds the smallest offending flat index
+enum : uint32_t { kStPacking = 1u, kStNonFinite = 2u, kStOverflow = 4u };
+
+// Per-instance description read by every pass kernel (device resident).
+struct EvalArgs {
+  int32_t n;          // grid points per axis
+  int32_t S;          // species
+  int32_t hs_on;      // hard-sphere term (passes x-forward, derivatives, back phase A)
+  int32_t pair_on;    // EC and/or SW pair term in the back pass
+  int32_t np;         // S (S + 1) / 2
+  int32_t nreal;      // fields written by the real-space output pass
+  int32_t final_mode; // 1: add constant, write mu and exp(-mu); 0: plain real output
+  int32_t pad0;
+  int64_t fstride;    // complex elements per spectral field (n*n*(n/2) + n*n)
+  double inv_n3;      // 1 / n^3
+  double R[kMaxSpecies];
+  double area[kMaxSpecies];     // 4 pi R^2
+  double inv4piR[kMaxSpecies];  // 1 / (4 pi R)
+  double cfin[kMaxSpecies];     // constant added to beta mu in the final pass
+  int8_t pidx[kMaxSpecies][kMaxSpecies];  // pair slot of (i, j)
+  const double* rho;  // [S][n^3] input densities
+  void* specA;        // S spectral fields (densities)
+  void* specB;        // 10 spectral fields (weighted densities, then derivatives)
+  void* specC;        // S spectral fields (chemical potentials)
+  const void* hs_tab;    // [M][3S]: j0(kR), 4 pi R^3 j1(kR)/(kR), 4 pi R^2 j1(kR)
+  const void* rsq_tab;   // [M]: 1/sqrt(m) (0 at m = 0)
+  const void* pair_tab;  // [M][np]: combined pair kernel
+  double* out;        // real output [nreal][n^3] (mu_ex or weighted densities)
+  double* slot;       // [S][n^3] exp(-mu) or null
+  uint32_t* status;   // two words
+};
+
+// Per-instance arguments of the radial table builder.
+struct TableArgs {
+  int32_t n, S, np, M;
+  double kscale;  // 2 pi / L
+  double R[kMaxSpecies];
+  double ec_pref[kMaxPairs];  // q_i q_j l_B (0 when EC is off)
+  double sigma[kMaxPairs];    // (d_i + d_j) / 2
+  double Bsig[kMaxPairs];     // B_ij / sigma_ij
+  double sw_pref[kMaxPairs];  // -beta c_sw eps_ij (0 when SW is off)
+  double rout[kMaxPairs];
+  void* hs_tab;
+  void* rsq_tab;
+  void* pair_tab;
+  int32_t single;  // 1: T = float tables, 0: double
+};
+
+}  // namespace pnp
