@@ -33,9 +33,10 @@
  *
  * Memory: every pointer marked "device" is caller-owned device memory (for
  * example allocated by PyTorch) on the context's device; the library never
- * allocates, frees or retains caller memory.  The context owns only a few
- * small host-side records.  Scratch space comes in through `workspace`,
- * sized by pnp_workspace_bytes().
+ * allocates, frees or retains caller memory.  The context owns a 4 MiB
+ * device ring for per-call argument records (allocated by pnp_create) and a
+ * few host records.  Scratch space comes in through `workspace`, sized by
+ * pnp_workspace_bytes().
  *
  * Errors: every function returns a pnp_status; nothing aborts or throws
  * across this boundary.  Outputs are unspecified when the return is not
@@ -208,6 +209,21 @@ pnp_status pnp_relax_densities(pnp_ctx ctx, const pnp_grid* grid, int32_t S,
 pnp_status pnp_debug_rfft3(pnp_ctx ctx, const pnp_grid* grid, int32_t precision,
                            int32_t count, int32_t inverse, const double* in, double* out,
                            void* workspace, size_t workspace_bytes, void* stream);
+
+/*
+ * Pass timing.  When enabled, every evaluation records HIP events around
+ * each of its passes on the caller's stream (no synchronisation is added).
+ * pnp_profile_read() waits for the recorded events, adds their durations to
+ * per-pass totals and returns, for pass ids 0..n-1, the summed milliseconds
+ * and the number of launches since the last reset (reset = 1 clears them).
+ * Pass ids: 0 radial tables, 1 z forward (densities), 2 y forward
+ * (densities), 3 x forward + weights, 4 y inverse (weighted densities),
+ * 5 z derivatives, 6 y forward (derivatives), 7 x back-convolution + pair
+ * kernels, 8 y inverse (chemical potentials), 9 z inverse + finalize.
+ */
+enum { PNP_NUM_PASSES = 10 };
+pnp_status pnp_profile_enable(pnp_ctx ctx, int32_t enable);
+pnp_status pnp_profile_read(pnp_ctx ctx, double* ms, int32_t* launches, int32_t n, int32_t reset);
 
 #ifdef __cplusplus
 }

@@ -25,8 +25,11 @@ STATUS_NAMES = {
 EXPORTED = [
     "pnp_create", "pnp_destroy", "pnp_last_error", "pnp_supported_size", "pnp_workspace_bytes",
     "pnp_cdft_mu_ex", "pnp_weighted_densities", "pnp_batch_mu_ex", "pnp_read_status",
-    "pnp_relax_densities", "pnp_debug_rfft3",
+    "pnp_relax_densities", "pnp_debug_rfft3", "pnp_profile_enable", "pnp_profile_read",
 ]
+
+PASS_NAMES = ["tables", "z_fwd_rho", "y_fwd_rho", "x_fwd_weights", "y_inv_n", "z_deriv",
+              "y_fwd_dphi", "x_back_pairs", "y_inv_mu", "z_inv_final"]
 
 
 class PnpError(RuntimeError):
@@ -99,6 +102,9 @@ def load_library():
                                         ctypes.POINTER(ctypes.c_double), ctypes.c_double, P]
     lib.pnp_debug_rfft3.argtypes = [P, ctypes.POINTER(Grid), ctypes.c_int32, ctypes.c_int32,
                                     ctypes.c_int32, P, P, P, ctypes.c_size_t, P]
+    lib.pnp_profile_enable.argtypes = [P, ctypes.c_int32]
+    lib.pnp_profile_read.argtypes = [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32),
+                                     ctypes.c_int32, ctypes.c_int32]
     for name in EXPORTED:
         f = getattr(lib, name)
         if name not in ("pnp_destroy", "pnp_last_error"):
@@ -260,6 +266,20 @@ class Evaluator:
         st = self.lib.pnp_batch_mu_ex(self.ctx, count, reqs, self._stream())
         self._check(st)
         return mus, sls, [int(reqs[r].status) for r in range(count)]
+
+    def profile(self, enable: bool = True):
+        self._check(self.lib.pnp_profile_enable(self.ctx, int(bool(enable))))
+
+    def profile_read(self, reset: bool = True):
+        """{pass name: (total ms, launches)} since the last reset."""
+        ms = (ctypes.c_double * 10)()
+        cnt = (ctypes.c_int32 * 10)()
+        self._check(self.lib.pnp_profile_read(self.ctx, ms, cnt, 10, int(bool(reset))))
+        return {PASS_NAMES[i]: (float(ms[i]), int(cnt[i])) for i in range(10)}
+
+    def read_status(self, workspace=None):
+        ws = self._ws["default"] if workspace is None else workspace
+        self._check(self.lib.pnp_read_status(self.ctx, ctypes.c_void_p(ws.data_ptr()), self._stream()))
 
     def relax(self, problem, rho, mu, mu_bulk, lam=0.1):
         m = _Marshal(problem)

@@ -17,9 +17,13 @@
 
 namespace pnp {
 
+// builtin two-element vectors (assignable in every address space; loaded and
+// stored as one 8- or 16-byte access)
+typedef float cf32 __attribute__((ext_vector_type(2)));
+typedef double cf64 __attribute__((ext_vector_type(2)));
 template <typename T> struct cvec;
-template <> struct cvec<float> { using type = float2; };
-template <> struct cvec<double> { using type = double2; };
+template <> struct cvec<float> { using type = cf32; };
+template <> struct cvec<double> { using type = cf64; };
 template <typename T> using cx = typename cvec<T>::type;
 
 template <typename T>

@@ -26,6 +26,12 @@ struct pnp_ctx_s {
   char* arena = nullptr;      // device ring for argument tables
   size_t arena_bytes = 0;
   size_t arena_pos = 0;
+  // pass timing
+  bool prof = false;
+  std::vector<hipEvent_t> ev_pool;                 // free events
+  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_open;  // recorded, unread
+  double prof_ms[PNP_NUM_PASSES] = {0};
+  int32_t prof_n[PNP_NUM_PASSES] = {0};
 };
 
 namespace {
@@ -44,6 +50,42 @@ pnp_status fail(pnp_ctx c, pnp_status s, const std::string& m) {
   if (c) c->err = m;
   return s;
 }
+
+hipEvent_t take_event(pnp_ctx c) {
+  if (!c->ev_pool.empty()) {
+    hipEvent_t e = c->ev_pool.back();
+    c->ev_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Brackets one pass with two events on the stream when timing is on.
+struct PassTimer {
+  pnp_ctx c;
+  hipStream_t s;
+  int id = -1;
+  hipEvent_t e0 = nullptr;
+  void begin(int pass) {
+    if (!c || !c->prof) return;
+    id = pass;
+    e0 = take_event(c);
+    if (e0) hipEventRecord(e0, s);
+  }
+  void end() {
+    if (!c || !c->prof || !e0) return;
+    hipEvent_t e1 = take_event(c);
+    if (e1) {
+      hipEventRecord(e1, s);
+      c->ev_open.push_back({id, {e0, e1}});
+    } else {
+      c->ev_pool.push_back(e0);
+    }
+    e0 = nullptr;
+  }
+};
 
 bool size_ok(int n) {
   switch (n) {
@@ -262,7 +304,7 @@ template <typename T, int N> struct Launch {
     hipLaunchKernelGGL((k_xfwd<T, N>), dim3(count * G::tiles_x), dim3(G::PX * G::TX), 0, s, a);
   }
   static void zderiv(const EvalArgs* a, int count, hipStream_t s) {
-    hipLaunchKernelGGL((k_zderiv<T, N>), dim3(count * G::tiles_d), dim3(G::RD * G::TZ), 0, s, a);
+    hipLaunchKernelGGL((k_zderiv<T, N>), dim3(count * GeoD<T, N>::tiles), dim3(GeoD<T, N>::RDD * GeoD<T, N>::TZD), 0, s, a);
   }
   static void xback(const EvalArgs* a, int count, int ch, hipStream_t s) {
     const dim3 g(count * G::tiles_x), b(G::PX * G::TX);
@@ -314,21 +356,21 @@ const Ops* ops_for(int precision, int n) {
 // The full launch sequence for `count` instances of one size and precision.
 // ea: device arg tables; hs_any: some instance has the HS term on;
 // pair_any likewise; ch: output chunk of the back pass.
-void run_sequence(const Ops* op, const EvalArgs* ea, const TableArgs* ta, int count, int M, bool hs_any,
-                  bool pair_any, int ch, hipStream_t s) {
-  op->tables(ta, count, M, s);
-  op->zfwd(ea, count, s);
-  op->ystep(ea, count, 0, -1, true, s);
+void run_sequence(pnp_ctx c, const Ops* op, const EvalArgs* ea, const TableArgs* ta, int count, int M,
+                  bool hs_any, int ch, hipStream_t s) {
+  PassTimer pt{c, s};
+  pt.begin(0); op->tables(ta, count, M, s); pt.end();
+  pt.begin(1); op->zfwd(ea, count, s); pt.end();
+  pt.begin(2); op->ystep(ea, count, 0, -1, true, s); pt.end();
   if (hs_any) {
-    op->xfwd(ea, count, s);
-    op->ystep(ea, count, 1, kFields, false, s);
-    op->zderiv(ea, count, s);
-    op->ystep(ea, count, 1, kFields, true, s);
+    pt.begin(3); op->xfwd(ea, count, s); pt.end();
+    pt.begin(4); op->ystep(ea, count, 1, kFields, false, s); pt.end();
+    pt.begin(5); op->zderiv(ea, count, s); pt.end();
+    pt.begin(6); op->ystep(ea, count, 1, kFields, true, s); pt.end();
   }
-  (void)pair_any;
-  op->xback(ea, count, ch, s);
-  op->ystep(ea, count, 2, -1, false, s);
-  op->zinv(ea, count, 2, s);
+  pt.begin(7); op->xback(ea, count, ch, s); pt.end();
+  pt.begin(8); op->ystep(ea, count, 2, -1, false, s); pt.end();
+  pt.begin(9); op->zinv(ea, count, 2, s); pt.end();
 }
 
 }  // namespace
@@ -356,12 +398,43 @@ pnp_status pnp_create(int device, pnp_ctx* out) {
 
 void pnp_destroy(pnp_ctx c) {
   if (!c) return;
+  hipSetDevice(c->device);
   if (c->arena) {
-    hipSetDevice(c->device);
     hipDeviceSynchronize();
     hipFree(c->arena);
   }
+  for (auto& o : c->ev_open) { hipEventDestroy(o.second.first); hipEventDestroy(o.second.second); }
+  for (hipEvent_t e : c->ev_pool) hipEventDestroy(e);
   delete c;
+}
+
+pnp_status pnp_profile_enable(pnp_ctx c, int32_t enable) {
+  if (!c) return PNP_E_ARG;
+  c->prof = enable != 0;
+  return PNP_OK;
+}
+
+pnp_status pnp_profile_read(pnp_ctx c, double* ms, int32_t* launches, int32_t n, int32_t reset) {
+  if (!c) return PNP_E_ARG;
+  if (hipSetDevice(c->device) != hipSuccess) return device_check(c, "set device");
+  for (auto& o : c->ev_open) {
+    float t = 0.f;
+    if (hipEventSynchronize(o.second.second) != hipSuccess ||
+        hipEventElapsedTime(&t, o.second.first, o.second.second) != hipSuccess)
+      return device_check(c, "event read");
+    c->prof_ms[o.first] += (double)t;
+    c->prof_n[o.first] += 1;
+    c->ev_pool.push_back(o.second.first);
+    c->ev_pool.push_back(o.second.second);
+  }
+  c->ev_open.clear();
+  for (int i = 0; i < n && i < PNP_NUM_PASSES; ++i) {
+    if (ms) ms[i] = c->prof_ms[i];
+    if (launches) launches[i] = c->prof_n[i];
+  }
+  if (reset)
+    for (int i = 0; i < PNP_NUM_PASSES; ++i) { c->prof_ms[i] = 0.0; c->prof_n[i] = 0; }
+  return PNP_OK;
 }
 
 const char* pnp_last_error(pnp_ctx c) { return c ? c->err.c_str() : "null context"; }
@@ -408,7 +481,7 @@ pnp_status pnp_cdft_mu_ex(pnp_ctx ctx, const pnp_grid* g, int32_t S, const pnp_s
     const TableArgs* dta = (const TableArgs*)upload(ctx, &ta, sizeof(ta), s);
     const EvalArgs* dea = (const EvalArgs*)upload(ctx, &ea, sizeof(ea), s);
     if (!dta || !dea) return device_check(ctx, "argument upload");
-    run_sequence(op, dea, dta, 1, L.M, d.hs, pairs, ch, s);
+    run_sequence(ctx, op, dea, dta, 1, L.M, d.hs, ch, s);
   } else {
     // tables: HS (+ EC pairs into pair), SW pairs into pair2
     TableArgs ta[2];
@@ -432,20 +505,23 @@ pnp_status pnp_cdft_mu_ex(pnp_ctx ctx, const pnp_grid* g, int32_t S, const pnp_s
     const TableArgs* dta = (const TableArgs*)upload(ctx, ta, sizeof(ta), s);
     const EvalArgs* dea = (const EvalArgs*)upload(ctx, ea, sizeof(ea), s);
     if (!dta || !dea) return device_check(ctx, "argument upload");
+    PassTimer pt{ctx, s};
+    pt.begin(0);
     op->tables(dta, 1, L.M, s);
     if (d.sw) op->tables(dta + 1, 1, L.M, s);
-    op->zfwd(dea, 1, s);
-    op->ystep(dea, 1, 0, -1, true, s);
+    pt.end();
+    pt.begin(1); op->zfwd(dea, 1, s); pt.end();
+    pt.begin(2); op->ystep(dea, 1, 0, -1, true, s); pt.end();
     if (d.hs) {
-      op->xfwd(dea, 1, s);
-      op->ystep(dea, 1, 1, kFields, false, s);
-      op->zderiv(dea, 1, s);
-      op->ystep(dea, 1, 1, kFields, true, s);
+      pt.begin(3); op->xfwd(dea, 1, s); pt.end();
+      pt.begin(4); op->ystep(dea, 1, 1, kFields, false, s); pt.end();
+      pt.begin(5); op->zderiv(dea, 1, s); pt.end();
+      pt.begin(6); op->ystep(dea, 1, 1, kFields, true, s); pt.end();
     }
     for (int k = 1; k < 4; ++k) {
-      op->xback(dea + k, 1, ch, s);
-      op->ystep(dea + k, 1, 2, -1, false, s);
-      op->zinv(dea + k, 1, 2, s);
+      pt.begin(7); op->xback(dea + k, 1, ch, s); pt.end();
+      pt.begin(8); op->ystep(dea + k, 1, 2, -1, false, s); pt.end();
+      pt.begin(9); op->zinv(dea + k, 1, 2, s); pt.end();
     }
     const long sn3 = (long)S * n3;
     const int blocks = (int)std::min<long>((sn3 + 255) / 256, 4096);
@@ -526,7 +602,7 @@ pnp_status pnp_batch_mu_ex(pnp_ctx ctx, int32_t count, pnp_request* reqs, void* 
     const int cnt = (int)ids.size();
     std::vector<TableArgs> ta(cnt);
     std::vector<EvalArgs> ea(cnt);
-    bool hs_any = false, pair_any = false;
+    bool hs_any = false;
     int maxS = 1;
     for (int k = 0; k < cnt; ++k) {
       pnp_request& q = reqs[ids[k]];
@@ -540,7 +616,7 @@ pnp_status pnp_batch_mu_ex(pnp_ctx ctx, int32_t count, pnp_request* reqs, void* 
       ea[k].out = q.mu_ex;
       ea[k].slot = q.slotboom;
       hs_any |= d.hs;
-      pair_any |= pairs;
+
       maxS = std::max(maxS, q.S);
     }
     const TableArgs* dta = (const TableArgs*)upload(ctx, ta.data(), sizeof(TableArgs) * cnt, s);
@@ -549,7 +625,7 @@ pnp_status pnp_batch_mu_ex(pnp_ctx ctx, int32_t count, pnp_request* reqs, void* 
     const Ops* op = ops_for(kv.first.first, kv.first.second);
     int M = 0;
     for (int k = 0; k < cnt; ++k) M = std::max(M, lay[ids[k]].M);
-    run_sequence(op, dea, dta, cnt, M, hs_any, pair_any, std::min(maxS, 4), s);
+    run_sequence(ctx, op, dea, dta, cnt, M, hs_any, std::min(maxS, 4), s);
   }
   pnp_status st = device_check(ctx, "batch launch");
   if (st != PNP_OK) return st;

@@ -71,6 +71,16 @@ __device__ __forceinline__ void init_twiddles(cx<T>* tw) {
   }
 }
 
+// Pointers read from the device-resident argument tables are generic; this
+// cast tells the compiler they address global memory so that it emits
+// global_load / global_store instead of flat accesses.
+template <typename X>
+using gp = __attribute__((address_space(1))) X*;
+template <typename X>
+__device__ __forceinline__ gp<X> gbl(X* p) {
+  return (gp<X>)p;
+}
+
 __device__ __forceinline__ int inst_of(int tiles, int& tile) {
   const int b = blockIdx.x;
   tile = b % tiles;
@@ -148,9 +158,9 @@ __global__ void __launch_bounds__(256) k_tables(const TableArgs* __restrict__ ta
   const int m = (blockIdx.x % blocks_per) * blockDim.x + threadIdx.x;
   if (m >= a.M) return;
   const double k = a.kscale * sqrt((double)m);
-  T* hs = (T*)a.hs_tab;
-  T* rs = (T*)a.rsq_tab;
-  T* pr = (T*)a.pair_tab;
+  auto hs = gbl((T*)a.hs_tab);
+  auto rs = gbl((T*)a.rsq_tab);
+  gp<T> pr = a.pair_tab ? gbl((T*)a.pair_tab) : (gp<T>)nullptr;
   rs[m] = (T)(m == 0 ? 0.0 : 1.0 / sqrt((double)m));
   for (int i = 0; i < a.S; ++i) {
     const double R = a.R[i];
@@ -181,9 +191,9 @@ __global__ void __launch_bounds__(256) k_tables(const TableArgs* __restrict__ ta
 // DFT_H(c), and X[k] = E[k] + W^k O[k] with E = (C[k] + conj C[H-k]) / 2,
 // O = (C[k] - conj C[H-k]) / (2i), W = exp(-2 pi i / n).
 // ---------------------------------------------------------------------------
-template <typename T, int N>
-__device__ __forceinline__ void r2c_post(cx<T>* v, int t, const cx<T>* twN, cx<T>* row,
-                                         cx<T>* main_out, cx<T>* nyq_out) {
+template <typename T, int N, typename PO>
+__device__ __forceinline__ void r2c_post(cx<T>* v, int t, const cx<T>* twN, cx<T>* row, PO main_out,
+                                         PO nyq_out) {
   using G = Geo<T, N>;
   constexpr int H = G::H, TZ = G::TZ, EZ = G::EZ;
 #pragma unroll
@@ -207,9 +217,8 @@ __device__ __forceinline__ void r2c_post(cx<T>* v, int t, const cx<T>* twN, cx<T
 // inverse: from X[k] (k < H) and X[H] build C[k] = (X[k] + conj X[H-k]) +
 // i (X[k] - conj X[H-k]) W^-k (times 2: the result of the unnormalised
 // length-H inverse is n (a[2j] + i a[2j+1]))
-template <typename T, int N>
-__device__ __forceinline__ void c2r_pre(cx<T>* v, int t, const cx<T>* twN, const cx<T>* main_in,
-                                        const cx<T>* nyq_in) {
+template <typename T, int N, typename PI>
+__device__ __forceinline__ void c2r_pre(cx<T>* v, int t, const cx<T>* twN, PI main_in, PI nyq_in) {
   using G = Geo<T, N>;
   constexpr int H = G::H, TZ = G::TZ, EZ = G::EZ;
 #pragma unroll
@@ -239,23 +248,27 @@ __global__ void __launch_bounds__((Geo<T, N>::RZ * Geo<T, N>::TZ))
   const EvalArgs& a = args[inst_of(G::tiles_z, tile)];
   init_twiddles<T, H>(twH);
   init_twiddles<T, N>(twN);
-  if (tile == 0 && threadIdx.x == 0) { a.status[0] = 0u; a.status[1] = 0xffffffffu; }
+  if (tile == 0 && threadIdx.x == 0) {
+    gp<uint32_t> st = gbl(a.status);
+    st[0] = 0u;
+    st[1] = 0xffffffffu;
+  }
   __syncthreads();
   const int t = threadIdx.x % TZ, r = threadIdx.x / TZ;
   const long row = (long)tile * RZ + r;
   cx<T>* lrow = xch + r * H;
   const LdsPencil<T> lp{lrow, 1};
-  cx<T>* A = (cx<T>*)a.specA;
+  auto A = gbl((cx<T>*)a.specA);
   for (int s = 0; s < a.S; ++s) {
-    const double* src = a.rho + (long)s * N * N * N + row * N;
+    auto src = gbl(a.rho) + (long)s * N * N * N + row * N;
     cx<T> v[EZ];
 #pragma unroll
     for (int m = 0; m < EZ; ++m) {
-      const double2 p = *(const double2*)(src + 2 * (t + TZ * m));
+      const cf64 p = *(gp<const cf64>)(src + 2 * (t + TZ * m));
       v[m] = mk<T>((T)p.x, (T)p.y);
     }
     fft_pencil<T, H, EZ, true>(v, t, twH, lp);
-    cx<T>* f = A + (long)s * a.fstride;
+    auto f = A + (long)s * a.fstride;
     r2c_post<T, N>(v, t, twN, lrow, f + row * H, f + (long)N * N * H + row);
   }
 }
@@ -279,23 +292,23 @@ __global__ void __launch_bounds__((Geo<T, N>::RZ * Geo<T, N>::TZ))
   const int t = threadIdx.x % TZ, r = threadIdx.x / TZ;
   const long row = (long)tile * RZ + r;
   const LdsPencil<T> lp{xch + r * H, 1};
-  const cx<T>* src = (const cx<T>*)(sel == 0 ? a.specA : sel == 1 ? a.specB : a.specC);
+  auto src = gbl((const cx<T>*)(sel == 0 ? a.specA : sel == 1 ? a.specB : a.specC));
   const long n3 = (long)N * N * N;
   uint32_t bad = 0u, badidx = 0xffffffffu;
   for (int s = 0; s < a.nreal; ++s) {
-    const cx<T>* f = src + (long)s * a.fstride;
+    auto f = src + (long)s * a.fstride;
     cx<T> v[EZ];
     c2r_pre<T, N>(v, t, twN, f + row * H, f + (long)N * N * H + row);
     fft_pencil<T, H, EZ, false>(v, t, twH, lp);
-    double* o = a.out + (long)s * n3 + row * N;
+    auto o = gbl(a.out) + (long)s * n3 + row * N;
     if (a.final_mode) {
       const double c = a.cfin[s];
-      double* so = a.slot ? a.slot + (long)s * n3 + row * N : nullptr;
+      gp<double> so = a.slot ? gbl(a.slot) + (long)s * n3 + row * N : (gp<double>)nullptr;
 #pragma unroll
       for (int m = 0; m < EZ; ++m) {
         const int j = t + TZ * m;
         const double m0 = (double)v[m].x + c, m1 = (double)v[m].y + c;
-        *(double2*)(o + 2 * j) = make_double2(m0, m1);
+        *(gp<cf64>)(o + 2 * j) = cf64{m0, m1};
         if (!(isfinite(m0) && isfinite(m1))) {
           bad |= kStNonFinite;
           badidx = min(badidx, (uint32_t)(s * n3 + row * N + 2 * j));
@@ -306,14 +319,14 @@ __global__ void __launch_bounds__((Geo<T, N>::RZ * Geo<T, N>::TZ))
             bad |= kStOverflow;
             badidx = min(badidx, (uint32_t)(s * n3 + row * N + 2 * j));
           }
-          *(double2*)(so + 2 * j) = make_double2(exp(-m0), exp(-m1));
+          *(gp<cf64>)(so + 2 * j) = cf64{exp(-m0), exp(-m1)};
         }
       }
     } else {
 #pragma unroll
       for (int m = 0; m < EZ; ++m) {
         const int j = t + TZ * m;
-        *(double2*)(o + 2 * j) = make_double2((double)v[m].x, (double)v[m].y);
+        *(gp<cf64>)(o + 2 * j) = cf64{(double)v[m].x, (double)v[m].y};
       }
     }
   }
@@ -322,17 +335,81 @@ __global__ void __launch_bounds__((Geo<T, N>::RZ * Geo<T, N>::TZ))
 
 // P5: z c2r of the 10 weighted densities, the FMT derivatives in float64
 // (Sec. 2.3.1), z r2c of the 10 derivative fields; in place on specB.
+// Every thread keeps its EZD elements of all ten fields in registers, so the
+// ten values at a grid point meet in one thread without an LDS round trip.
+template <typename T, int N> struct GeoD {
+  static constexpr int H = N / 2;
+  static constexpr int EZD = (H % 3 == 0) ? 6
+                                          : (H >= (sizeof(T) == 4 ? 4 : 2) ? (sizeof(T) == 4 ? 4 : 2) : H);
+  static constexpr int TZD = H / EZD;
+  static constexpr int RDD = pow2_divisor_le((long)N * N, 256 / TZD < 1 ? 1 : 256 / TZD);
+  static constexpr int tiles = (N * N) / RDD;
+};
+
+template <typename T, int N, int F>
+__device__ __forceinline__ void zd_load(cx<T>* val, int t, const cx<T>* twN,
+                                        const cx<T>* twH, const LdsPencil<T>& lp, gp<cx<T>> B, long fstride,
+                                        long row) {
+  if constexpr (F < kFields) {
+    using D = GeoD<T, N>;
+    constexpr int H = D::H;
+    auto fb = B + (long)F * fstride;
+#pragma unroll
+    for (int m = 0; m < D::EZD; ++m) {
+      const int k = t + D::TZD * m;
+      cx<T> xk = fb[row * H + k];
+      cx<T> xm = (k == 0) ? fb[(long)N * N * H + row] : fb[row * H + H - k];
+      if (k == 0) { xk.y = (T)0; xm.y = (T)0; }
+      const cx<T> cm = cconj<T>(xm);
+      const cx<T> sm = cadd<T>(xk, cm);
+      const cx<T> d = csub<T>(xk, cm);
+      const cx<T> o = cmulc<T>(d, twN[k]);
+      val[F * D::EZD + m] = cadd<T>(sm, cmuli<T>(o));
+    }
+    fft_pencil<T, H, D::EZD, false>(val + F * D::EZD, t, twH, lp);
+    __builtin_amdgcn_sched_barrier(0);  // keep the next field's loads after this FFT
+    zd_load<T, N, F + 1>(val, t, twN, twH, lp, B, fstride, row);
+  }
+}
+
+template <typename T, int N, int F>
+__device__ __forceinline__ void zd_store(cx<T>* val, int t, const cx<T>* twN,
+                                         const cx<T>* twH, const LdsPencil<T>& lp, cx<T>* lrow, gp<cx<T>> B,
+                                         long fstride, long row) {
+  if constexpr (F < kFields) {
+    using D = GeoD<T, N>;
+    constexpr int H = D::H;
+    auto fb = B + (long)F * fstride;
+    fft_pencil<T, H, D::EZD, true>(val + F * D::EZD, t, twH, lp);
+#pragma unroll
+    for (int m = 0; m < D::EZD; ++m) lrow[t + D::TZD * m] = val[F * D::EZD + m];
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < D::EZD; ++m) {
+      const int k = t + D::TZD * m;
+      const cx<T> c = val[F * D::EZD + m];
+      const cx<T> cm = cconj<T>(lrow[k == 0 ? 0 : H - k]);
+      const cx<T> e = mk<T>((T)0.5 * (c.x + cm.x), (T)0.5 * (c.y + cm.y));
+      const cx<T> d = mk<T>((T)0.5 * (c.x - cm.x), (T)0.5 * (c.y - cm.y));
+      fb[row * H + k] = cadd<T>(e, cmul<T>(twN[k], cmulmi<T>(d)));
+      if (k == 0) fb[(long)N * N * H + row] = mk<T>(c.x - c.y, (T)0);
+    }
+    __syncthreads();
+    __builtin_amdgcn_sched_barrier(0);
+    zd_store<T, N, F + 1>(val, t, twN, twH, lp, lrow, B, fstride, row);
+  }
+}
+
 template <typename T, int N>
-__global__ void __launch_bounds__((Geo<T, N>::RD * Geo<T, N>::TZ))
+__global__ void __launch_bounds__((GeoD<T, N>::RDD * GeoD<T, N>::TZD))
     k_zderiv(const EvalArgs* __restrict__ args) {
-  using G = Geo<T, N>;
-  constexpr int H = G::H, TZ = G::TZ, EZ = G::EZ, RD = G::RD;
+  using D = GeoD<T, N>;
+  constexpr int H = D::H, TZ = D::TZD, EZ = D::EZD, RD = D::RDD;
   __shared__ cx<T> twH[H];
   __shared__ cx<T> twN[N];
   __shared__ cx<T> xch[RD * H];
-  __shared__ T stage[kFields][RD][N];
   int tile;
-  const EvalArgs& a = args[inst_of(G::tiles_d, tile)];
+  const EvalArgs& a = args[inst_of(D::tiles, tile)];
   if (!a.hs_on) return;  // uniform per block
   init_twiddles<T, H>(twH);
   init_twiddles<T, N>(twN);
@@ -341,63 +418,48 @@ __global__ void __launch_bounds__((Geo<T, N>::RD * Geo<T, N>::TZ))
   const long row = (long)tile * RD + r;
   cx<T>* lrow = xch + r * H;
   const LdsPencil<T> lp{lrow, 1};
-  cx<T>* B = (cx<T>*)a.specB;
-  const long nyq0 = (long)N * N * H;
-  for (int f = 0; f < kFields; ++f) {
-    cx<T>* fb = B + (long)f * a.fstride;
-    cx<T> v[EZ];
-    c2r_pre<T, N>(v, t, twN, fb + row * H, fb + nyq0 + row);
-    fft_pencil<T, H, EZ, false>(v, t, twH, lp);
-#pragma unroll
-    for (int m = 0; m < EZ; ++m) {
-      const int j = t + TZ * m;
-      stage[f][r][2 * j] = v[m].x;
-      stage[f][r][2 * j + 1] = v[m].y;
-    }
-  }
-  __syncthreads();
+  auto B = gbl((cx<T>*)a.specB);
+  cx<T> val[kFields * EZ];
+  zd_load<T, N, 0>(val, t, twN, twH, lp, B, a.fstride, row);
   uint32_t bad = 0u, badidx = 0xffffffffu;
   const double inv8pi = 1.0 / (8.0 * kPi), inv12pi = 1.0 / (12.0 * kPi), inv4pi = 1.0 / (4.0 * kPi);
-  for (int z = t; z < N; z += TZ) {
-    const double n0 = stage[0][r][z], n1 = stage[1][r][z], n2 = stage[2][r][z], n3 = stage[3][r][z];
-    const double a1x = stage[4][r][z], a1y = stage[5][r][z], a1z = stage[6][r][z];
-    const double a2x = stage[7][r][z], a2y = stage[8][r][z], a2z = stage[9][r][z];
-    if (!(n3 < 1.0)) {
-      bad |= isfinite(n3) ? kStPacking : kStNonFinite;
-      badidx = min(badidx, (uint32_t)(row * N + z));
-    }
-    const double one = 1.0 - n3;
-    const double inv = 1.0 / one, inv2 = inv * inv, inv3 = inv2 * inv;
-    const double v12 = a1x * a2x + a1y * a2y + a1z * a2z;
-    const double v22 = a2x * a2x + a2y * a2y + a2z * a2z;
-    const double d0 = -log1p(-n3);
-    const double d1 = n2 * inv;
-    const double d2 = n1 * inv + (n2 * n2 - v22) * inv2 * inv8pi;
-    const double d3 = n0 * inv + (n1 * n2 - v12) * inv2 + (n2 * n2 * n2 - 3.0 * n2 * v22) * inv3 * inv12pi;
-    const double c2 = n2 * inv2 * inv4pi;
-    stage[0][r][z] = (T)d0;
-    stage[1][r][z] = (T)d1;
-    stage[2][r][z] = (T)d2;
-    stage[3][r][z] = (T)d3;
-    stage[4][r][z] = (T)(-a2x * inv);
-    stage[5][r][z] = (T)(-a2y * inv);
-    stage[6][r][z] = (T)(-a2z * inv);
-    stage[7][r][z] = (T)(-a1x * inv - c2 * a2x);
-    stage[8][r][z] = (T)(-a1y * inv - c2 * a2y);
-    stage[9][r][z] = (T)(-a1z * inv - c2 * a2z);
-  }
-  __syncthreads();
-  for (int f = 0; f < kFields; ++f) {
-    cx<T>* fb = B + (long)f * a.fstride;
-    cx<T> v[EZ];
 #pragma unroll
-    for (int m = 0; m < EZ; ++m) {
-      const int j = t + TZ * m;
-      v[m] = mk<T>(stage[f][r][2 * j], stage[f][r][2 * j + 1]);
+  for (int m = 0; m < EZ; ++m) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {  // the two real points z = 2j, 2j+1 of element j
+      double f[kFields];
+#pragma unroll
+      for (int q = 0; q < kFields; ++q) f[q] = h ? (double)val[q * EZ + m].y : (double)val[q * EZ + m].x;
+      const double n0 = f[0], n1 = f[1], n2 = f[2], n3 = f[3];
+      const double a1x = f[4], a1y = f[5], a1z = f[6], a2x = f[7], a2y = f[8], a2z = f[9];
+      if (!(n3 < 1.0)) {
+        bad |= isfinite(n3) ? kStPacking : kStNonFinite;
+        badidx = min(badidx, (uint32_t)(row * N + 2 * (t + TZ * m) + h));
+      }
+      const double inv = 1.0 / (1.0 - n3), inv2 = inv * inv, inv3 = inv2 * inv;
+      const double v12 = a1x * a2x + a1y * a2y + a1z * a2z;
+      const double v22 = a2x * a2x + a2y * a2y + a2z * a2z;
+      const double c2 = n2 * inv2 * inv4pi;
+      double d[kFields];
+      d[0] = -log1p(-n3);
+      d[1] = n2 * inv;
+      d[2] = n1 * inv + (n2 * n2 - v22) * inv2 * inv8pi;
+      d[3] = n0 * inv + (n1 * n2 - v12) * inv2 + (n2 * n2 * n2 - 3.0 * n2 * v22) * inv3 * inv12pi;
+      d[4] = -a2x * inv;
+      d[5] = -a2y * inv;
+      d[6] = -a2z * inv;
+      d[7] = -a1x * inv - c2 * a2x;
+      d[8] = -a1y * inv - c2 * a2y;
+      d[9] = -a1z * inv - c2 * a2z;
+#pragma unroll
+      for (int q = 0; q < kFields; ++q) {
+        if (h) val[q * EZ + m].y = (T)d[q];
+        else val[q * EZ + m].x = (T)d[q];
+      }
+      __builtin_amdgcn_sched_barrier(0);  // one grid point at a time: bounded live range
     }
-    fft_pencil<T, H, EZ, true>(v, t, twH, lp);
-    r2c_post<T, N>(v, t, twN, lrow, fb + row * H, fb + nyq0 + row);
   }
+  zd_store<T, N, 0>(val, t, twN, twH, lp, lrow, B, a.fstride, row);
   if (bad) raise_status(a.status, bad, badidx);
 }
 
@@ -417,7 +479,7 @@ __global__ void __launch_bounds__((Geo<T, N>::PY * Geo<T, N>::TY))
   if (sel == 1 && !a.hs_on) return;  // uniform per block
   init_twiddles<T, N>(tw);
   __syncthreads();
-  cx<T>* base = (cx<T>*)(sel == 0 ? a.specA : sel == 1 ? a.specB : a.specC);
+  auto base = gbl((cx<T>*)(sel == 0 ? a.specA : sel == 1 ? a.specB : a.specC));
   const int nf = nf_code == -1 ? a.S : nf_code;
   constexpr int tiles_main = (N * H) / PY;
   long off, es;
@@ -439,7 +501,7 @@ __global__ void __launch_bounds__((Geo<T, N>::PY * Geo<T, N>::TY))
     lp = LdsPencil<T>{xch + p * N, 1};
   }
   for (int f = 0; f < nf; ++f) {
-    cx<T>* fb = base + (long)f * a.fstride + off;
+    auto fb = base + (long)f * a.fstride + off;
     cx<T> v[EY];
 #pragma unroll
     for (int m = 0; m < EY; ++m) v[m] = fb[(long)(t + TY * m) * es];
@@ -494,8 +556,8 @@ __global__ void __launch_bounds__((Geo<T, N>::PX * Geo<T, N>::TX))
   const LdsPencil<T> lp{xch + p, PX};
   const int S = a.S;
   const int sy = sgn_idx(pc.ky, N), sz = pc.kz;
-  const T* hs = (const T*)a.hs_tab;
-  const T* rsq = (const T*)a.rsq_tab;
+  auto hs = gbl((const T*)a.hs_tab);
+  auto rsq = gbl((const T*)a.rsq_tab);
   int mm[EX];
 #pragma unroll
   for (int m = 0; m < EX; ++m) {
@@ -507,9 +569,9 @@ __global__ void __launch_bounds__((Geo<T, N>::PX * Geo<T, N>::TX))
   for (int q = 0; q < 6; ++q)
 #pragma unroll
     for (int m = 0; m < EX; ++m) acc[q][m] = mk<T>((T)0, (T)0);
-  const cx<T>* A = (const cx<T>*)a.specA;
+  auto A = gbl((const cx<T>*)a.specA);
   for (int i = 0; i < S; ++i) {
-    const cx<T>* src = A + (long)i * a.fstride + pc.off;
+    auto src = A + (long)i * a.fstride + pc.off;
     cx<T> v[EX];
 #pragma unroll
     for (int m = 0; m < EX; ++m) v[m] = src[(long)(t + TX * m) * pc.es];
@@ -517,7 +579,7 @@ __global__ void __launch_bounds__((Geo<T, N>::PX * Geo<T, N>::TX))
     const T R = (T)a.R[i], ar = (T)a.area[i], i4 = (T)a.inv4piR[i];
 #pragma unroll
     for (int m = 0; m < EX; ++m) {
-      const T* w = hs + (long)mm[m] * 3 * S + 3 * i;
+      auto w = hs + (long)mm[m] * 3 * S + 3 * i;
       const T j0 = w[0], s3 = w[1], vv = w[2];
       cfma<T>(acc[0][m], v[m], j0);
       cfma<T>(acc[1][m], v[m], j0 * R);
@@ -528,7 +590,7 @@ __global__ void __launch_bounds__((Geo<T, N>::PX * Geo<T, N>::TX))
     }
   }
   const T sc = (T)a.inv_n3;
-  cx<T>* B = (cx<T>*)a.specB;
+  auto B = gbl((cx<T>*)a.specB);
   // scalar weighted densities n0..n3
 #pragma unroll 1
   for (int o = 0; o < 4; ++o) {
@@ -545,7 +607,7 @@ __global__ void __launch_bounds__((Geo<T, N>::PX * Geo<T, N>::TX))
       v[m] = cscale<T>(s0, sc);
     }
     fft_pencil<T, N, EX, false>(v, t, tw, lp);
-    cx<T>* dst = B + (long)o * a.fstride + pc.off;
+    auto dst = B + (long)o * a.fstride + pc.off;
 #pragma unroll
     for (int m = 0; m < EX; ++m) dst[(long)(t + TX * m) * pc.es] = v[m];
   }
@@ -566,7 +628,7 @@ __global__ void __launch_bounds__((Geo<T, N>::PX * Geo<T, N>::TX))
         v[m] = cscale<T>(cmuli<T>(acc[4 + b][m]), u);
       }
       fft_pencil<T, N, EX, false>(v, t, tw, lp);
-      cx<T>* dst = B + (long)(4 + 3 * b + c) * a.fstride + pc.off;
+      auto dst = B + (long)(4 + 3 * b + c) * a.fstride + pc.off;
 #pragma unroll
       for (int m = 0; m < EX; ++m) dst[(long)(t + TX * m) * pc.es] = v[m];
     }
@@ -594,9 +656,9 @@ __global__ void __launch_bounds__((Geo<T, N>::PX * Geo<T, N>::TX))
   const LdsPencil<T> lp{xch + p, PX};
   const int S = a.S;
   const int sy = sgn_idx(pc.ky, N), sz = pc.kz;
-  const T* hs = (const T*)a.hs_tab;
-  const T* rsq = (const T*)a.rsq_tab;
-  const T* pt = (const T*)a.pair_tab;
+  auto hs = gbl((const T*)a.hs_tab);
+  auto rsq = gbl((const T*)a.rsq_tab);
+  auto pt = gbl((const T*)a.pair_tab);
   int mm[EX];
 #pragma unroll
   for (int m = 0; m < EX; ++m) {
@@ -608,11 +670,11 @@ __global__ void __launch_bounds__((Geo<T, N>::PX * Geo<T, N>::TX))
   for (int q = 0; q < 6; ++q)
 #pragma unroll
     for (int m = 0; m < EX; ++m) F[q][m] = mk<T>((T)0, (T)0);
-  const cx<T>* B = (const cx<T>*)a.specB;
+  auto B = gbl((const cx<T>*)a.specB);
   if (a.hs_on) {
 #pragma unroll 1
     for (int f = 0; f < 4; ++f) {
-      const cx<T>* src = B + (long)f * a.fstride + pc.off;
+      auto src = B + (long)f * a.fstride + pc.off;
       cx<T> v[EX];
 #pragma unroll
       for (int m = 0; m < EX; ++m) v[m] = src[(long)(t + TX * m) * pc.es];
@@ -631,7 +693,7 @@ __global__ void __launch_bounds__((Geo<T, N>::PX * Geo<T, N>::TX))
     for (int b = 0; b < 2; ++b) {
 #pragma unroll 1
       for (int c = 0; c < 3; ++c) {
-        const cx<T>* src = B + (long)(4 + 3 * b + c) * a.fstride + pc.off;
+        auto src = B + (long)(4 + 3 * b + c) * a.fstride + pc.off;
         cx<T> v[EX];
 #pragma unroll
         for (int m = 0; m < EX; ++m) v[m] = src[(long)(t + TX * m) * pc.es];
@@ -648,8 +710,8 @@ __global__ void __launch_bounds__((Geo<T, N>::PX * Geo<T, N>::TX))
       }
     }
   }
-  const cx<T>* A = (const cx<T>*)a.specA;
-  cx<T>* C = (cx<T>*)a.specC;
+  auto A = gbl((const cx<T>*)a.specA);
+  auto C = gbl((cx<T>*)a.specC);
   const T sc = (T)a.inv_n3;
 #pragma unroll 1
   for (int i0 = 0; i0 < S; i0 += CH) {
@@ -661,7 +723,7 @@ __global__ void __launch_bounds__((Geo<T, N>::PX * Geo<T, N>::TX))
     if (a.pair_on) {
 #pragma unroll 1
       for (int j = 0; j < S; ++j) {
-        const cx<T>* src = A + (long)j * a.fstride + pc.off;
+        auto src = A + (long)j * a.fstride + pc.off;
         cx<T> v[EX];
 #pragma unroll
         for (int m = 0; m < EX; ++m) v[m] = src[(long)(t + TX * m) * pc.es];
@@ -687,7 +749,7 @@ __global__ void __launch_bounds__((Geo<T, N>::PX * Geo<T, N>::TX))
         for (int m = 0; m < EX; ++m) {
           cx<T> u = out[c][m];
           if (a.hs_on) {
-            const T* w = hs + (long)mm[m] * 3 * S + 3 * i;
+            auto w = hs + (long)mm[m] * 3 * S + 3 * i;
             const T j0 = w[0], s3 = w[1], vv = w[2];
             cx<T> sc0 = F[0][m];
             cfma<T>(sc0, F[1][m], R);
@@ -701,7 +763,7 @@ __global__ void __launch_bounds__((Geo<T, N>::PX * Geo<T, N>::TX))
           v[m] = cscale<T>(u, sc);
         }
         fft_pencil<T, N, EX, false>(v, t, tw, lp);
-        cx<T>* dst = C + (long)i * a.fstride + pc.off;
+        auto dst = C + (long)i * a.fstride + pc.off;
 #pragma unroll
         for (int m = 0; m < EX; ++m) dst[(long)(t + TX * m) * pc.es] = v[m];
       }
@@ -724,9 +786,9 @@ __global__ void __launch_bounds__((Geo<T, N>::PX * Geo<T, N>::TX))
   const int p = threadIdx.x % PX, t = threadIdx.x / PX;
   const XPencil<T, N> pc(tile, p);
   const LdsPencil<T> lp{xch + p, PX};
-  cx<T>* base = (cx<T>*)(sel == 0 ? a.specA : sel == 1 ? a.specB : a.specC);
+  auto base = gbl((cx<T>*)(sel == 0 ? a.specA : sel == 1 ? a.specB : a.specC));
   for (int f = 0; f < nf; ++f) {
-    cx<T>* fb = base + (long)f * a.fstride + pc.off;
+    auto fb = base + (long)f * a.fstride + pc.off;
     cx<T> v[EX];
 #pragma unroll
     for (int m = 0; m < EX; ++m) v[m] = fb[(long)(t + TX * m) * pc.es];
@@ -742,14 +804,14 @@ __global__ void k_export(const EvalArgs* __restrict__ args, int nf, double* buf,
   constexpr int H = N / 2;
   const EvalArgs& a = args[0];
   const long total = (long)nf * N * N * (H + 1);
-  cx<T>* A = (cx<T>*)a.specA;
+  auto A = gbl((cx<T>*)a.specA);
   for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (long)gridDim.x * blockDim.x) {
     const long f = e / ((long)N * N * (H + 1));
     const long rem = e % ((long)N * N * (H + 1));
     const long kx = rem / ((long)N * (H + 1));
     const long ky = (rem / (H + 1)) % N;
     const long kz = rem % (H + 1);
-    cx<T>* s = A + f * a.fstride + (kz < H ? (kx * N + ky) * H + kz : (long)N * N * H + kx * N + ky);
+    auto s = A + f * a.fstride + (kz < H ? (kx * N + ky) * H + kz : (long)N * N * H + kx * N + ky);
     if (to_numpy) {
       buf[2 * e] = (double)s->x;
       buf[2 * e + 1] = (double)s->y;
