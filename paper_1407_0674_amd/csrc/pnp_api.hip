@@ -107,10 +107,12 @@ struct Derived {
 };
 
 struct Layout {
-  size_t status, hs, rsq, pair, pair2, A, B, C, total;
+  size_t status, hs, pair, pair2, A, B, C, total;
   long fstride;
   int M;
 };
+
+inline int padded_species(int S) { return (S + 3) / 4 * 4; }
 
 Layout layout_of(int n, int S, int precision, bool hs, bool pairs, bool per_term) {
   Layout L{};
@@ -118,13 +120,12 @@ Layout layout_of(int n, int S, int precision, bool hs, bool pairs, bool per_term
   const long H = n / 2;
   L.M = (int)(3 * H * H + 1);
   L.fstride = (long)n * n * H + (long)n * n;
-  const int np = S * (S + 1) / 2;
+  const size_t prow = (size_t)S * padded_species(S);
   size_t o = 0;
   L.status = o; o = up(o + 64);
-  L.hs = o; o = up(o + (size_t)L.M * 3 * S * ts);
-  L.rsq = o; o = up(o + (size_t)L.M * ts);
-  L.pair = o; if (pairs) o = up(o + (size_t)L.M * np * ts);
-  L.pair2 = o; if (pairs && per_term) o = up(o + (size_t)L.M * np * ts);
+  L.hs = o; o = up(o + (size_t)L.M * 4 * S * ts);
+  L.pair = o; if (pairs) o = up(o + (size_t)L.M * prow * ts);
+  L.pair2 = o; if (pairs && per_term) o = up(o + (size_t)L.M * prow * ts);
   L.A = o; o = up(o + (size_t)S * L.fstride * 2 * ts);
   L.B = o; if (hs) o = up(o + (size_t)kFields * L.fstride * 2 * ts);
   L.C = o; o = up(o + (size_t)S * L.fstride * 2 * ts);
@@ -193,7 +194,7 @@ pnp_status validate(pnp_ctx ctx, const pnp_grid* g, int S, const pnp_species* sp
 }
 
 void fill_table_args(TableArgs& t, const Derived& d, const pnp_species* sp, double h, double sw_pref_scale,
-                     bool ec, bool sw, void* hs, void* rsq, void* pair, int M) {
+                     bool ec, bool sw, void* hs, void* pair, int M) {
   std::memset(&t, 0, sizeof(t));
   t.n = d.n; t.S = d.S; t.np = d.np; t.M = M;
   t.kscale = 2.0 * M_PI / (d.n * h);
@@ -207,8 +208,10 @@ void fill_table_args(TableArgs& t, const Derived& d, const pnp_species* sp, doub
       t.sw_pref[q] = sw ? -d.beta * sw_pref_scale * d.eps[q] : 0.0;
       t.rout[q] = d.rout[q];
     }
-  t.hs_tab = hs; t.rsq_tab = rsq; t.pair_tab = pair;
-  t.single = d.precision == PNP_MIXED;
+  for (int i = 0; i < d.S; ++i)
+    for (int j = 0; j < d.S; ++j) t.pidx[i][j] = (int8_t)d.pi[i][j];
+  t.Sp = padded_species(d.S);
+  t.hs_tab = hs; t.pair_tab = pair;
 }
 
 void fill_eval_args(EvalArgs& e, const Derived& d, const pnp_species* sp, const Layout& L, char* ws,
@@ -224,14 +227,13 @@ void fill_eval_args(EvalArgs& e, const Derived& d, const pnp_species* sp, const 
     e.area[i] = 4.0 * M_PI * R * R;
     e.inv4piR[i] = 1.0 / (4.0 * M_PI * R);
     e.cfin[i] = d.cfin_ec[i];
-    for (int j = 0; j < d.S; ++j) e.pidx[i][j] = (int8_t)d.pi[i][j];
   }
+  e.Sp = padded_species(d.S);
   e.rho = rho;
   e.specA = ws + L.A;
   e.specB = ws + L.B;
   e.specC = ws + L.C;
   e.hs_tab = ws + L.hs;
-  e.rsq_tab = ws + L.rsq;
   e.pair_tab = ws + L.pair;
   e.status = (uint32_t*)(ws + L.status);
   e.final_mode = 1;
@@ -473,7 +475,7 @@ pnp_status pnp_cdft_mu_ex(pnp_ctx ctx, const pnp_grid* g, int32_t S, const pnp_s
 
   if (!p->per_term) {
     TableArgs ta;
-    fill_table_args(ta, d, sp, g->h, sw_c, d.ec, d.sw, w + L.hs, w + L.rsq, pairs ? w + L.pair : nullptr, L.M);
+    fill_table_args(ta, d, sp, g->h, sw_c, d.ec, d.sw, w + L.hs, pairs ? w + L.pair : nullptr, L.M);
     EvalArgs ea;
     fill_eval_args(ea, d, sp, L, w, rho);
     ea.out = mu;
@@ -485,8 +487,8 @@ pnp_status pnp_cdft_mu_ex(pnp_ctx ctx, const pnp_grid* g, int32_t S, const pnp_s
   } else {
     // tables: HS (+ EC pairs into pair), SW pairs into pair2
     TableArgs ta[2];
-    fill_table_args(ta[0], d, sp, g->h, sw_c, d.ec, false, w + L.hs, w + L.rsq, pairs ? w + L.pair : nullptr, L.M);
-    fill_table_args(ta[1], d, sp, g->h, sw_c, false, d.sw, w + L.hs, w + L.rsq, pairs ? w + L.pair2 : nullptr,
+    fill_table_args(ta[0], d, sp, g->h, sw_c, d.ec, false, w + L.hs, pairs ? w + L.pair : nullptr, L.M);
+    fill_table_args(ta[1], d, sp, g->h, sw_c, false, d.sw, w + L.hs, pairs ? w + L.pair2 : nullptr,
                     L.M);
     // four argument records: forward half, hs-only, el-only, sh-only
     EvalArgs ea[4];
@@ -552,7 +554,7 @@ pnp_status pnp_weighted_densities(pnp_ctx ctx, const pnp_grid* g, int32_t S, con
   const Ops* op = ops_for(d.precision, d.n);
   char* w = (char*)ws;
   TableArgs ta;
-  fill_table_args(ta, d, sp, g->h, 0.0, false, false, w + L.hs, w + L.rsq, nullptr, L.M);
+  fill_table_args(ta, d, sp, g->h, 0.0, false, false, w + L.hs, nullptr, L.M);
   EvalArgs ea;
   fill_eval_args(ea, d, sp, L, w, rho);
   ea.final_mode = 0;
@@ -610,7 +612,7 @@ pnp_status pnp_batch_mu_ex(pnp_ctx ctx, int32_t count, pnp_request* reqs, void* 
       const Layout& L = lay[ids[k]];
       char* w = (char*)q.workspace;
       const bool pairs = d.ec || d.sw;
-      fill_table_args(ta[k], d, q.species, q.grid.h, q.params->sw_prefactor, d.ec, d.sw, w + L.hs, w + L.rsq,
+      fill_table_args(ta[k], d, q.species, q.grid.h, q.params->sw_prefactor, d.ec, d.sw, w + L.hs,
                       pairs ? w + L.pair : nullptr, L.M);
       fill_eval_args(ea[k], d, q.species, L, w, q.rho);
       ea[k].out = q.mu_ex;

@@ -20,6 +20,10 @@
 //   P7 x forward, back-convolution, pair kernels, x inverse   k_xback (10 + S -> S)
 //   P8 y inverse                       k_ystep<INV>
 //   P9 z c2r, + constants, exp(-mu)    k_zinv
+//
+// Addressing: every global access is a uniform (scalar) field base plus a
+// per-lane 32-bit byte offset that is computed once per block, which maps to
+// the saddr + voffset form of global_load / global_store.
 #include <hip/hip_runtime.h>
 #include <math.h>
 
@@ -40,12 +44,10 @@ constexpr int pow2_divisor_le(long v, int cap) {
 template <typename T, int N> struct Geo {
   static constexpr int H = N / 2;
   static constexpr bool R3 = (N % 3 == 0);
-  // z passes: complex FFT of length H, EZ elements per thread
+  // z passes (P1, P9): complex FFT of length H, EZ elements per thread
   static constexpr int EZ = R3 ? 12 : (H >= 16 ? 16 : H);
   static constexpr int TZ = H / EZ;
-  static constexpr int RZ = pow2_divisor_le((long)N * N, 256 / TZ);  // rows per block (P1, P9)
-  static constexpr int RD0 = (48 * 1024) / (kFields * N * (int)sizeof(T));
-  static constexpr int RD = pow2_divisor_le((long)N * N, RD0 < 1 ? 1 : (RD0 > 256 / TZ ? 256 / TZ : RD0));
+  static constexpr int RZ = pow2_divisor_le((long)N * N, 256 / TZ);  // rows per block
   // y passes
   static constexpr int EY = R3 ? 12 : (N >= 16 ? 16 : N);
   static constexpr int TY = N / EY;
@@ -56,7 +58,6 @@ template <typename T, int N> struct Geo {
   static constexpr int PX = pow2_divisor_le(N, sizeof(T) == 4 ? 16 : 8);
   // tiles per instance
   static constexpr int tiles_z = (N * N) / RZ;
-  static constexpr int tiles_d = (N * N) / RD;
   static constexpr int tiles_y = (N * H) / PY + N / PY;
   static constexpr int tiles_x = (N * H) / PX + N / PX;
 };
@@ -71,14 +72,61 @@ __device__ __forceinline__ void init_twiddles(cx<T>* tw) {
   }
 }
 
-// Pointers read from the device-resident argument tables are generic; this
-// cast tells the compiler they address global memory so that it emits
-// global_load / global_store instead of flat accesses.
+// Global-memory pointers (used for the status word and the test hook).
 template <typename X>
 using gp = __attribute__((address_space(1))) X*;
 template <typename X>
 __device__ __forceinline__ gp<X> gbl(X* p) {
   return (gp<X>)p;
+}
+
+// Buffer-resource access: a scalar descriptor for one array, a per-lane
+// 32-bit byte offset and a uniform 32-bit byte offset (the field).  The
+// descriptor's record count is the array size, so an access past the end
+// reads 0 / is dropped instead of touching other memory.
+constexpr int kBufWord3 = 0x00020000;  // raw (untyped) 32-bit data on gfx9-family parts
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+struct Buf {
+  __amdgpu_buffer_rsrc_t r;
+  template <typename X>
+  __device__ __forceinline__ X ld(uint32_t voff, uint32_t soff = 0) const {
+    if constexpr (sizeof(X) == 4) {
+      return __builtin_bit_cast(X, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+    } else if constexpr (sizeof(X) == 8) {
+      return __builtin_bit_cast(X, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+    } else if constexpr (sizeof(X) == 16) {
+      return __builtin_bit_cast(X, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
+    } else {
+      static_assert(sizeof(X) == 32, "buffer access size");
+      const u32x4 a = __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0);
+      const u32x4 b = __builtin_amdgcn_raw_buffer_load_b128(r, voff + 16, soff, 0);
+      struct P { u32x4 a, b; } pr{a, b};
+      return __builtin_bit_cast(X, pr);
+    }
+  }
+  template <typename X>
+  __device__ __forceinline__ void st(X v, uint32_t voff, uint32_t soff = 0) const {
+    if constexpr (sizeof(X) == 4) {
+      __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, voff, soff, 0);
+    } else if constexpr (sizeof(X) == 8) {
+      __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, voff, soff, 0);
+    } else if constexpr (sizeof(X) == 16) {
+      __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, v), r, voff, soff, 0);
+    } else {
+      static_assert(sizeof(X) == 32, "buffer access size");
+      struct P { u32x4 a, b; };
+      const P pr = __builtin_bit_cast(P, v);
+      __builtin_amdgcn_raw_buffer_store_b128(pr.a, r, voff, soff, 0);
+      __builtin_amdgcn_raw_buffer_store_b128(pr.b, r, voff + 16, soff, 0);
+    }
+  }
+};
+
+__device__ __forceinline__ Buf make_buf(const void* p, uint64_t bytes) {
+  const uint32_t n = bytes >= 0xffffffffull ? 0xffffffffu : (uint32_t)bytes;
+  return Buf{__builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)n, kBufWord3)};
 }
 
 __device__ __forceinline__ int inst_of(int tiles, int& tile) {
@@ -91,6 +139,11 @@ __device__ __forceinline__ void raise_status(uint32_t* st, uint32_t bits, uint32
   atomicOr(st, bits);
   atomicMin(st + 1, idx);
 }
+
+template <typename T> struct vec4;
+template <> struct vec4<float> { typedef float type __attribute__((ext_vector_type(4))); };
+template <> struct vec4<double> { typedef double type __attribute__((ext_vector_type(4))); };
+template <typename T> using v4 = typename vec4<T>::type;
 
 // ---------------------------------------------------------------------------
 // radial tables: the analytic transforms of Sec. 2.3.1 (weights), Sec. 2.3.2
@@ -151,6 +204,8 @@ __device__ double d_invrball(double k, double a) {
   return 4.0 * kPi * a * a * f;
 }
 
+// hs table [m][S][4] = (j0(kR), 4 pi R^3 j1(kR)/(kR), 4 pi R^2 j1(kR), 0);
+// pair table [m][j][i] (row length Sp) = G_ij, the combined pair kernel.
 template <typename T>
 __global__ void __launch_bounds__(256) k_tables(const TableArgs* __restrict__ targs, int blocks_per) {
   const int inst = blockIdx.x / blocks_per;
@@ -158,30 +213,35 @@ __global__ void __launch_bounds__(256) k_tables(const TableArgs* __restrict__ ta
   const int m = (blockIdx.x % blocks_per) * blockDim.x + threadIdx.x;
   if (m >= a.M) return;
   const double k = a.kscale * sqrt((double)m);
-  auto hs = gbl((T*)a.hs_tab);
-  auto rs = gbl((T*)a.rsq_tab);
-  gp<T> pr = a.pair_tab ? gbl((T*)a.pair_tab) : (gp<T>)nullptr;
-  rs[m] = (T)(m == 0 ? 0.0 : 1.0 / sqrt((double)m));
+  const Buf hs = make_buf(a.hs_tab, (uint64_t)a.M * a.S * 4 * sizeof(T));
   for (int i = 0; i < a.S; ++i) {
     const double R = a.R[i];
     const double x = k * R;
     const double j1x = d_j1x(x);
     const double j0 = (x == 0.0) ? 1.0 : sin(x) / x;
-    hs[(long)m * 3 * a.S + 3 * i + 0] = (T)j0;
-    hs[(long)m * 3 * a.S + 3 * i + 1] = (T)(4.0 * kPi * R * R * R * j1x);
-    hs[(long)m * 3 * a.S + 3 * i + 2] = (T)(4.0 * kPi * R * R * x * j1x);
+    v4<T> w;
+    w.x = (T)j0;
+    w.y = (T)(4.0 * kPi * R * R * R * j1x);
+    w.z = (T)(4.0 * kPi * R * R * x * j1x);
+    w.w = (T)0;
+    hs.st<v4<T>>(w, (uint32_t)((m * a.S + i) * sizeof(v4<T>)));
   }
-  if (pr) {
-    for (int p = 0; p < a.np; ++p) {
-      double g = 0.0;
+  if (a.pair_tab) {
+    const Buf pr = make_buf(a.pair_tab, (uint64_t)a.M * a.S * a.Sp * sizeof(T));
+    double g[kMaxPairs];
+    for (int p = 0; p < (a.S * (a.S + 1)) / 2; ++p) {
+      double v = 0.0;
       const double s = a.sigma[p];
       if (a.ec_pref[p] != 0.0) {
         const double b = a.Bsig[p];
-        g += a.ec_pref[p] * (2.0 * b * d_ball(k, s) - b * b * d_rball(k, s) - d_invrball(k, s));
+        v += a.ec_pref[p] * (2.0 * b * d_ball(k, s) - b * b * d_rball(k, s) - d_invrball(k, s));
       }
-      if (a.sw_pref[p] != 0.0) g += a.sw_pref[p] * (d_ball(k, a.rout[p]) - d_ball(k, s));
-      pr[(long)m * a.np + p] = (T)g;
+      if (a.sw_pref[p] != 0.0) v += a.sw_pref[p] * (d_ball(k, a.rout[p]) - d_ball(k, s));
+      g[p] = v;
     }
+    for (int j = 0; j < a.S; ++j)
+      for (int i = 0; i < a.Sp; ++i)
+        pr.st<T>((T)(i < a.S ? g[a.pidx[i][j]] : 0.0), (uint32_t)(((m * a.S + j) * a.Sp + i) * sizeof(T)));
   }
 }
 
@@ -190,12 +250,14 @@ __global__ void __launch_bounds__(256) k_tables(const TableArgs* __restrict__ ta
 // A row of n reals a[z] is packed as c[j] = a[2j] + i a[2j+1] (j < H), C =
 // DFT_H(c), and X[k] = E[k] + W^k O[k] with E = (C[k] + conj C[H-k]) / 2,
 // O = (C[k] - conj C[H-k]) / (2i), W = exp(-2 pi i / n).
+// Spectral element e of a field sits at byte e * sizeof(cx<T>) + soff.
 // ---------------------------------------------------------------------------
-template <typename T, int N, typename PO>
-__device__ __forceinline__ void r2c_post(cx<T>* v, int t, const cx<T>* twN, cx<T>* row, PO main_out,
-                                         PO nyq_out) {
-  using G = Geo<T, N>;
-  constexpr int H = G::H, TZ = G::TZ, EZ = G::EZ;
+// v holds C[k] at k = t + TZ m; writes X[k] (k < H) and X[H] of one row
+template <typename T, int N, int TZ, int EZ>
+__device__ __forceinline__ void r2c_post(cx<T>* v, int t, const cx<T>* twN, cx<T>* row, const Buf& f,
+                                         uint32_t soff, uint32_t row_id) {
+  constexpr int H = N / 2;
+  constexpr uint32_t cs = sizeof(cx<T>);
 #pragma unroll
   for (int m = 0; m < EZ; ++m) row[t + TZ * m] = v[m];
   __syncthreads();
@@ -206,33 +268,36 @@ __device__ __forceinline__ void r2c_post(cx<T>* v, int t, const cx<T>* twN, cx<T
     const cx<T> cm = cconj<T>(row[k == 0 ? 0 : H - k]);
     const cx<T> e = mk<T>((T)0.5 * (c.x + cm.x), (T)0.5 * (c.y + cm.y));
     const cx<T> d = mk<T>((T)0.5 * (c.x - cm.x), (T)0.5 * (c.y - cm.y));  // O = d / i
-    const cx<T> o = cmulmi<T>(d);
-    const cx<T> x = cadd<T>(e, cmul<T>(twN[k], o));
-    main_out[k] = x;
-    if (k == 0) *nyq_out = mk<T>(c.x - c.y, (T)0);
+    f.st<cx<T>>(cadd<T>(e, cmul<T>(twN[k], cmulmi<T>(d))), (row_id * H + k) * cs, soff);
+    if (k == 0) f.st<cx<T>>(mk<T>(c.x - c.y, (T)0), ((uint32_t)(N * N * H) + row_id) * cs, soff);
   }
   __syncthreads();
 }
 
 // inverse: from X[k] (k < H) and X[H] build C[k] = (X[k] + conj X[H-k]) +
-// i (X[k] - conj X[H-k]) W^-k (times 2: the result of the unnormalised
-// length-H inverse is n (a[2j] + i a[2j+1]))
-template <typename T, int N, typename PI>
-__device__ __forceinline__ void c2r_pre(cx<T>* v, int t, const cx<T>* twN, PI main_in, PI nyq_in) {
-  using G = Geo<T, N>;
-  constexpr int H = G::H, TZ = G::TZ, EZ = G::EZ;
+// i (X[k] - conj X[H-k]) W^-k; the unnormalised length-H inverse of C is
+// then n (a[2j] + i a[2j+1])
+template <typename T, int N, int TZ, int EZ>
+__device__ __forceinline__ void c2r_pre(cx<T>* v, int t, const cx<T>* twN, const Buf& f, uint32_t soff,
+                                        uint32_t row_id) {
+  constexpr int H = N / 2;
+  constexpr uint32_t cs = sizeof(cx<T>);
 #pragma unroll
   for (int m = 0; m < EZ; ++m) {
     const int k = t + TZ * m;
-    cx<T> xk = main_in[k];
-    cx<T> xm = (k == 0) ? *nyq_in : main_in[H - k];
+    cx<T> xk = f.ld<cx<T>>((row_id * H + k) * cs, soff);
+    cx<T> xm = f.ld<cx<T>>((k == 0 ? (uint32_t)(N * N * H) + row_id : row_id * H + (H - k)) * cs, soff);
     if (k == 0) { xk.y = (T)0; xm.y = (T)0; }
     const cx<T> cm = cconj<T>(xm);
     const cx<T> s = cadd<T>(xk, cm);
     const cx<T> d = csub<T>(xk, cm);
-    const cx<T> o = cmulc<T>(d, twN[k]);  // d * W^-k
-    v[m] = cadd<T>(s, cmuli<T>(o));
+    v[m] = cadd<T>(s, cmuli<T>(cmulc<T>(d, twN[k])));
   }
+}
+
+template <typename T>
+__device__ __forceinline__ uint64_t spec_bytes(const EvalArgs& a, int nf) {
+  return (uint64_t)nf * a.fstride * sizeof(cx<T>);
 }
 
 // P1: z r2c of the S input densities (float64) into specA
@@ -255,25 +320,25 @@ __global__ void __launch_bounds__((Geo<T, N>::RZ * Geo<T, N>::TZ))
   }
   __syncthreads();
   const int t = threadIdx.x % TZ, r = threadIdx.x / TZ;
-  const long row = (long)tile * RZ + r;
+  const uint32_t row = (uint32_t)(tile * RZ + r);
   cx<T>* lrow = xch + r * H;
   const LdsPencil<T> lp{lrow, 1};
-  auto A = gbl((cx<T>*)a.specA);
+  constexpr uint32_t n3b = (uint32_t)N * N * N * sizeof(double);
+  const Buf rho = make_buf(a.rho, (uint64_t)a.S * n3b);
+  const Buf A = make_buf(a.specA, spec_bytes<T>(a, a.S));
   for (int s = 0; s < a.S; ++s) {
-    auto src = gbl(a.rho) + (long)s * N * N * N + row * N;
     cx<T> v[EZ];
 #pragma unroll
     for (int m = 0; m < EZ; ++m) {
-      const cf64 p = *(gp<const cf64>)(src + 2 * (t + TZ * m));
+      const cf64 p = rho.ld<cf64>((row * H + t + TZ * m) * (uint32_t)sizeof(cf64), (uint32_t)s * n3b);
       v[m] = mk<T>((T)p.x, (T)p.y);
     }
     fft_pencil<T, H, EZ, true>(v, t, twH, lp);
-    auto f = A + (long)s * a.fstride;
-    r2c_post<T, N>(v, t, twN, lrow, f + row * H, f + (long)N * N * H + row);
+    r2c_post<T, N, TZ, EZ>(v, t, twN, lrow, A, (uint32_t)(s * a.fstride * sizeof(cx<T>)), row);
   }
 }
 
-// P9 (final_mode = 1): z c2r of the S chemical-potential spectra in specC,
+// P9 (final_mode = 1): z c2r of the S chemical-potential spectra in `sel`,
 // + constants, write beta mu_ex and exp(-beta mu_ex) in float64.
 // final_mode = 0: z c2r of `nreal` spectra of `sel` into out (no constant).
 template <typename T, int N>
@@ -290,44 +355,43 @@ __global__ void __launch_bounds__((Geo<T, N>::RZ * Geo<T, N>::TZ))
   init_twiddles<T, N>(twN);
   __syncthreads();
   const int t = threadIdx.x % TZ, r = threadIdx.x / TZ;
-  const long row = (long)tile * RZ + r;
+  const uint32_t row = (uint32_t)(tile * RZ + r);
   const LdsPencil<T> lp{xch + r * H, 1};
-  auto src = gbl((const cx<T>*)(sel == 0 ? a.specA : sel == 1 ? a.specB : a.specC));
-  const long n3 = (long)N * N * N;
+  const Buf src = make_buf(sel == 0 ? a.specA : sel == 1 ? a.specB : a.specC, spec_bytes<T>(a, a.nreal));
+  constexpr uint32_t n3 = (uint32_t)N * N * N;
+  constexpr uint32_t n3b = n3 * sizeof(double);
+  const Buf out = make_buf(a.out, (uint64_t)a.nreal * n3b);
+  const Buf slot = make_buf(a.slot, a.slot ? (uint64_t)a.nreal * n3b : 0);
   uint32_t bad = 0u, badidx = 0xffffffffu;
   for (int s = 0; s < a.nreal; ++s) {
-    auto f = src + (long)s * a.fstride;
     cx<T> v[EZ];
-    c2r_pre<T, N>(v, t, twN, f + row * H, f + (long)N * N * H + row);
+    c2r_pre<T, N, TZ, EZ>(v, t, twN, src, (uint32_t)(s * a.fstride * sizeof(cx<T>)), row);
     fft_pencil<T, H, EZ, false>(v, t, twH, lp);
-    auto o = gbl(a.out) + (long)s * n3 + row * N;
+    const uint32_t so = (uint32_t)s * n3b;
     if (a.final_mode) {
       const double c = a.cfin[s];
-      gp<double> so = a.slot ? gbl(a.slot) + (long)s * n3 + row * N : (gp<double>)nullptr;
 #pragma unroll
       for (int m = 0; m < EZ; ++m) {
-        const int j = t + TZ * m;
+        const uint32_t j = row * H + t + TZ * m;  // index of the point pair (2j, 2j+1)
         const double m0 = (double)v[m].x + c, m1 = (double)v[m].y + c;
-        *(gp<cf64>)(o + 2 * j) = cf64{m0, m1};
+        out.st<cf64>(cf64{m0, m1}, j * (uint32_t)sizeof(cf64), so);
         if (!(isfinite(m0) && isfinite(m1))) {
           bad |= kStNonFinite;
-          badidx = min(badidx, (uint32_t)(s * n3 + row * N + 2 * j));
+          badidx = min(badidx, (uint32_t)s * n3 + 2 * j);
         }
-        if (so) {
+        if (a.slot) {
           // exp(-mu) overflows a double once -mu exceeds ln(DBL_MAX)
           if (-m0 > 709.782712893384 || -m1 > 709.782712893384) {
             bad |= kStOverflow;
-            badidx = min(badidx, (uint32_t)(s * n3 + row * N + 2 * j));
+            badidx = min(badidx, (uint32_t)s * n3 + 2 * j);
           }
-          *(gp<cf64>)(so + 2 * j) = cf64{exp(-m0), exp(-m1)};
+          slot.st<cf64>(cf64{exp(-m0), exp(-m1)}, j * (uint32_t)sizeof(cf64), so);
         }
       }
     } else {
 #pragma unroll
-      for (int m = 0; m < EZ; ++m) {
-        const int j = t + TZ * m;
-        *(gp<cf64>)(o + 2 * j) = cf64{(double)v[m].x, (double)v[m].y};
-      }
+      for (int m = 0; m < EZ; ++m)
+        out.st<cf64>(cf64{(double)v[m].x, (double)v[m].y}, (row * H + t + TZ * m) * (uint32_t)sizeof(cf64), so);
     }
   }
   if (bad) raise_status(a.status, bad, badidx);
@@ -347,56 +411,27 @@ template <typename T, int N> struct GeoD {
 };
 
 template <typename T, int N, int F>
-__device__ __forceinline__ void zd_load(cx<T>* val, int t, const cx<T>* twN,
-                                        const cx<T>* twH, const LdsPencil<T>& lp, gp<cx<T>> B, long fstride,
-                                        long row) {
+__device__ __forceinline__ void zd_load(cx<T>* val, int t, const cx<T>* twN, const cx<T>* twH,
+                                        const LdsPencil<T>& lp, const Buf& B, uint32_t fbytes, uint32_t row) {
   if constexpr (F < kFields) {
     using D = GeoD<T, N>;
-    constexpr int H = D::H;
-    auto fb = B + (long)F * fstride;
-#pragma unroll
-    for (int m = 0; m < D::EZD; ++m) {
-      const int k = t + D::TZD * m;
-      cx<T> xk = fb[row * H + k];
-      cx<T> xm = (k == 0) ? fb[(long)N * N * H + row] : fb[row * H + H - k];
-      if (k == 0) { xk.y = (T)0; xm.y = (T)0; }
-      const cx<T> cm = cconj<T>(xm);
-      const cx<T> sm = cadd<T>(xk, cm);
-      const cx<T> d = csub<T>(xk, cm);
-      const cx<T> o = cmulc<T>(d, twN[k]);
-      val[F * D::EZD + m] = cadd<T>(sm, cmuli<T>(o));
-    }
-    fft_pencil<T, H, D::EZD, false>(val + F * D::EZD, t, twH, lp);
+    c2r_pre<T, N, D::TZD, D::EZD>(val + F * D::EZD, t, twN, B, F * fbytes, row);
+    fft_pencil<T, N / 2, D::EZD, false>(val + F * D::EZD, t, twH, lp);
     __builtin_amdgcn_sched_barrier(0);  // keep the next field's loads after this FFT
-    zd_load<T, N, F + 1>(val, t, twN, twH, lp, B, fstride, row);
+    zd_load<T, N, F + 1>(val, t, twN, twH, lp, B, fbytes, row);
   }
 }
 
 template <typename T, int N, int F>
-__device__ __forceinline__ void zd_store(cx<T>* val, int t, const cx<T>* twN,
-                                         const cx<T>* twH, const LdsPencil<T>& lp, cx<T>* lrow, gp<cx<T>> B,
-                                         long fstride, long row) {
+__device__ __forceinline__ void zd_store(cx<T>* val, int t, const cx<T>* twN, const cx<T>* twH,
+                                         const LdsPencil<T>& lp, cx<T>* lrow, const Buf& B, uint32_t fbytes,
+                                         uint32_t row) {
   if constexpr (F < kFields) {
     using D = GeoD<T, N>;
-    constexpr int H = D::H;
-    auto fb = B + (long)F * fstride;
-    fft_pencil<T, H, D::EZD, true>(val + F * D::EZD, t, twH, lp);
-#pragma unroll
-    for (int m = 0; m < D::EZD; ++m) lrow[t + D::TZD * m] = val[F * D::EZD + m];
-    __syncthreads();
-#pragma unroll
-    for (int m = 0; m < D::EZD; ++m) {
-      const int k = t + D::TZD * m;
-      const cx<T> c = val[F * D::EZD + m];
-      const cx<T> cm = cconj<T>(lrow[k == 0 ? 0 : H - k]);
-      const cx<T> e = mk<T>((T)0.5 * (c.x + cm.x), (T)0.5 * (c.y + cm.y));
-      const cx<T> d = mk<T>((T)0.5 * (c.x - cm.x), (T)0.5 * (c.y - cm.y));
-      fb[row * H + k] = cadd<T>(e, cmul<T>(twN[k], cmulmi<T>(d)));
-      if (k == 0) fb[(long)N * N * H + row] = mk<T>(c.x - c.y, (T)0);
-    }
-    __syncthreads();
+    fft_pencil<T, N / 2, D::EZD, true>(val + F * D::EZD, t, twH, lp);
+    r2c_post<T, N, D::TZD, D::EZD>(val + F * D::EZD, t, twN, lrow, B, F * fbytes, row);
     __builtin_amdgcn_sched_barrier(0);
-    zd_store<T, N, F + 1>(val, t, twN, twH, lp, lrow, B, fstride, row);
+    zd_store<T, N, F + 1>(val, t, twN, twH, lp, lrow, B, fbytes, row);
   }
 }
 
@@ -415,12 +450,13 @@ __global__ void __launch_bounds__((GeoD<T, N>::RDD * GeoD<T, N>::TZD))
   init_twiddles<T, N>(twN);
   __syncthreads();
   const int t = threadIdx.x % TZ, r = threadIdx.x / TZ;
-  const long row = (long)tile * RD + r;
+  const uint32_t row = (uint32_t)(tile * RD + r);
   cx<T>* lrow = xch + r * H;
   const LdsPencil<T> lp{lrow, 1};
-  auto B = gbl((cx<T>*)a.specB);
+  const Buf B = make_buf(a.specB, spec_bytes<T>(a, kFields));
+  const uint32_t fbytes = (uint32_t)(a.fstride * sizeof(cx<T>));
   cx<T> val[kFields * EZ];
-  zd_load<T, N, 0>(val, t, twN, twH, lp, B, a.fstride, row);
+  zd_load<T, N, 0>(val, t, twN, twH, lp, B, fbytes, row);
   uint32_t bad = 0u, badidx = 0xffffffffu;
   const double inv8pi = 1.0 / (8.0 * kPi), inv12pi = 1.0 / (12.0 * kPi), inv4pi = 1.0 / (4.0 * kPi);
 #pragma unroll
@@ -434,7 +470,7 @@ __global__ void __launch_bounds__((GeoD<T, N>::RDD * GeoD<T, N>::TZD))
       const double a1x = f[4], a1y = f[5], a1z = f[6], a2x = f[7], a2y = f[8], a2z = f[9];
       if (!(n3 < 1.0)) {
         bad |= isfinite(n3) ? kStPacking : kStNonFinite;
-        badidx = min(badidx, (uint32_t)(row * N + 2 * (t + TZ * m) + h));
+        badidx = min(badidx, row * N + 2 * (t + TZ * m) + h);
       }
       const double inv = 1.0 / (1.0 - n3), inv2 = inv * inv, inv3 = inv2 * inv;
       const double v12 = a1x * a2x + a1y * a2y + a1z * a2z;
@@ -459,7 +495,7 @@ __global__ void __launch_bounds__((GeoD<T, N>::RDD * GeoD<T, N>::TZD))
       __builtin_amdgcn_sched_barrier(0);  // one grid point at a time: bounded live range
     }
   }
-  zd_store<T, N, 0>(val, t, twN, twH, lp, lrow, B, a.fstride, row);
+  zd_store<T, N, 0>(val, t, twN, twH, lp, lrow, B, fbytes, row);
   if (bad) raise_status(a.status, bad, badidx);
 }
 
@@ -479,35 +515,39 @@ __global__ void __launch_bounds__((Geo<T, N>::PY * Geo<T, N>::TY))
   if (sel == 1 && !a.hs_on) return;  // uniform per block
   init_twiddles<T, N>(tw);
   __syncthreads();
-  auto base = gbl((cx<T>*)(sel == 0 ? a.specA : sel == 1 ? a.specB : a.specC));
   const int nf = nf_code == -1 ? a.S : nf_code;
+  const Buf base = make_buf(sel == 0 ? a.specA : sel == 1 ? a.specB : a.specC, spec_bytes<T>(a, nf));
   constexpr int tiles_main = (N * H) / PY;
-  long off, es;
+  uint32_t off, es;
   int t;
   LdsPencil<T> lp;
   if (tile < tiles_main) {
     const int p = threadIdx.x % PY;
     t = threadIdx.x / PY;
-    const long pen = (long)tile * PY + p;  // (x, kz)
-    off = (pen / H) * ((long)N * H) + (pen % H);
+    const uint32_t pen = (uint32_t)(tile * PY + p);  // (x, kz)
+    off = (pen / H) * (N * H) + (pen % H);
     es = H;
     lp = LdsPencil<T>{xch + p, PY};
   } else {
     const int p = threadIdx.x / TY;
     t = threadIdx.x % TY;
-    const long x = (long)(tile - tiles_main) * PY + p;
-    off = (long)N * N * H + x * N;
+    const uint32_t x = (uint32_t)((tile - tiles_main) * PY + p);
+    off = N * N * H + x * N;
     es = 1;
     lp = LdsPencil<T>{xch + p * N, 1};
   }
+  uint32_t eo[EY];
+#pragma unroll
+  for (int m = 0; m < EY; ++m) eo[m] = (off + (uint32_t)(t + TY * m) * es) * (uint32_t)sizeof(cx<T>);
+  const uint32_t fbytes = (uint32_t)(a.fstride * sizeof(cx<T>));
   for (int f = 0; f < nf; ++f) {
-    auto fb = base + (long)f * a.fstride + off;
+    const uint32_t so = (uint32_t)f * fbytes;
     cx<T> v[EY];
 #pragma unroll
-    for (int m = 0; m < EY; ++m) v[m] = fb[(long)(t + TY * m) * es];
+    for (int m = 0; m < EY; ++m) v[m] = base.ld<cx<T>>(eo[m], so);
     fft_pencil<T, N, EY, FWD>(v, t, tw, lp);
 #pragma unroll
-    for (int m = 0; m < EY; ++m) fb[(long)(t + TY * m) * es] = v[m];
+    for (int m = 0; m < EY; ++m) base.st<cx<T>>(v[m], eo[m], so);
   }
 }
 
@@ -515,72 +555,101 @@ __global__ void __launch_bounds__((Geo<T, N>::PY * Geo<T, N>::TY))
 // x direction helpers: pencil (ky, kz) of the main array or ky of the Nyquist
 // plane, element kx at stride es.
 // ---------------------------------------------------------------------------
-template <typename T, int N>
+template <int N, int PX>
 struct XPencil {
-  long off, es;
+  uint32_t off, es;  // element kx of the pencil at off + kx * es
   int ky, kz;
   __device__ __forceinline__ XPencil(int tile, int p) {
     constexpr int H = N / 2;
-    constexpr int PX = Geo<T, N>::PX;
-    const long pen = (long)tile * PX + p;
-    const long nmain = (long)N * H;
+    const int pen = tile * PX + p;
+    constexpr int nmain = N * H;
     if (pen < nmain) {
-      off = pen; es = nmain; ky = (int)(pen / H); kz = (int)(pen % H);
+      off = (uint32_t)pen; es = nmain; ky = pen / H; kz = pen % H;
     } else {
-      const long q = pen - nmain;
-      off = nmain * N + q; es = N; ky = (int)q; kz = H;
+      const int q = pen - nmain;
+      off = (uint32_t)(nmain * N + q); es = N; ky = q; kz = H;
     }
   }
 };
 
+template <int N, int PX> constexpr int x_tiles() { return (N * (N / 2)) / PX + N / PX; }
+
 __device__ __forceinline__ int sgn_idx(int j, int n) { return j < n / 2 ? j : j - n; }
+
+template <typename T>
+__device__ __forceinline__ T inv_sqrt_m(int m) {
+  if constexpr (sizeof(T) == 4) return m == 0 ? 0.0f : __builtin_amdgcn_rsqf((float)m);
+  else return m == 0 ? 0.0 : 1.0 / sqrt((double)m);
+}
+
+// per-lane k-space data of the EX elements a thread owns
+template <typename T, int N, int EX, int TX>
+struct XKs {
+  int mm[EX];   // integer |j|^2
+  T ux[EX];     // unit-vector components (0 on that axis's Nyquist plane)
+  T uy[EX];
+  T uz[EX];
+  __device__ __forceinline__ XKs(int t, int ky, int kz) {
+    constexpr int H = N / 2;
+    const int sy = sgn_idx(ky, N), sz = kz;
+#pragma unroll
+    for (int m = 0; m < EX; ++m) {
+      const int kx = t + TX * m;
+      const int sx = sgn_idx(kx, N);
+      mm[m] = sx * sx + sy * sy + sz * sz;
+      const T r = inv_sqrt_m<T>(mm[m]);
+      ux[m] = kx == H ? (T)0 : (T)sx * r;
+      uy[m] = ky == H ? (T)0 : (T)sy * r;
+      uz[m] = kz == H ? (T)0 : (T)sz * r;
+    }
+  }
+};
+
+template <typename T, int N>
+__device__ __forceinline__ uint64_t table_m(int /*unused*/) { return 3ull * (N / 2) * (N / 2) + 1; }
 
 // P3: forward weights.  For every k: n^_a(k) = sum_i rho^_i(k) conj(w^_i^a(k))
 // (correlation, Sec. 2.3.1); scalars w0 = j0, w1 = R j0, w2 = 4 pi R^2 j0,
 // w3 = 4 pi R^3 j1(kR)/(kR); vectors conj(-i khat V) = +i khat V with
 // V2 = 4 pi R^2 j1(kR), V1 = V2 / (4 pi R).
-template <typename T, int N>
-__global__ void __launch_bounds__((Geo<T, N>::PX * Geo<T, N>::TX))
+template <typename T, int N, int EX = Geo<T, N>::EX, int PX = Geo<T, N>::PX>
+__global__ void __launch_bounds__((PX * (N / EX)))
     k_xfwd(const EvalArgs* __restrict__ args) {
-  using G = Geo<T, N>;
-  constexpr int H = G::H, TX = G::TX, EX = G::EX, PX = G::PX;
+  constexpr int TX = N / EX;
   __shared__ cx<T> tw[N];
   __shared__ cx<T> xch[PX * N];
   int tile;
-  const EvalArgs& a = args[inst_of(G::tiles_x, tile)];
+  const EvalArgs& a = args[inst_of(x_tiles<N, PX>(), tile)];
   if (!a.hs_on) return;  // uniform per block
   init_twiddles<T, N>(tw);
   __syncthreads();
   const int p = threadIdx.x % PX, t = threadIdx.x / PX;
-  const XPencil<T, N> pc(tile, p);
+  const XPencil<N, PX> pc(tile, p);
   const LdsPencil<T> lp{xch + p, PX};
   const int S = a.S;
-  const int sy = sgn_idx(pc.ky, N), sz = pc.kz;
-  auto hs = gbl((const T*)a.hs_tab);
-  auto rsq = gbl((const T*)a.rsq_tab);
-  int mm[EX];
+  const Buf hs = make_buf(a.hs_tab, table_m<T, N>(0) * S * sizeof(v4<T>));
+  const Buf A = make_buf(a.specA, spec_bytes<T>(a, S));
+  const Buf B = make_buf(a.specB, spec_bytes<T>(a, kFields));
+  const uint32_t fbytes = (uint32_t)(a.fstride * sizeof(cx<T>));
+  const XKs<T, N, EX, TX> ks(t, pc.ky, pc.kz);
+  uint32_t eo[EX];
 #pragma unroll
-  for (int m = 0; m < EX; ++m) {
-    const int sx = sgn_idx(t + TX * m, N);
-    mm[m] = sx * sx + sy * sy + sz * sz;
-  }
+  for (int m = 0; m < EX; ++m) eo[m] = (pc.off + (uint32_t)(t + TX * m) * pc.es) * (uint32_t)sizeof(cx<T>);
   cx<T> acc[6][EX];
 #pragma unroll
   for (int q = 0; q < 6; ++q)
 #pragma unroll
     for (int m = 0; m < EX; ++m) acc[q][m] = mk<T>((T)0, (T)0);
-  auto A = gbl((const cx<T>*)a.specA);
   for (int i = 0; i < S; ++i) {
-    auto src = A + (long)i * a.fstride + pc.off;
     cx<T> v[EX];
 #pragma unroll
-    for (int m = 0; m < EX; ++m) v[m] = src[(long)(t + TX * m) * pc.es];
+    for (int m = 0; m < EX; ++m) v[m] = A.ld<cx<T>>(eo[m], (uint32_t)i * fbytes);
     fft_pencil<T, N, EX, true>(v, t, tw, lp);
     const T R = (T)a.R[i], ar = (T)a.area[i], i4 = (T)a.inv4piR[i];
 #pragma unroll
     for (int m = 0; m < EX; ++m) {
-      auto w = hs + (long)mm[m] * 3 * S + 3 * i;
-      const T j0 = w[0], s3 = w[1], vv = w[2];
+      const v4<T> w = hs.ld<v4<T>>((uint32_t)(ks.mm[m] * S + i) * (uint32_t)sizeof(v4<T>));
+      const T j0 = w.x, s3 = w.y, vv = w.z;
       cfma<T>(acc[0][m], v[m], j0);
       cfma<T>(acc[1][m], v[m], j0 * R);
       cfma<T>(acc[2][m], v[m], j0 * ar);
@@ -590,7 +659,6 @@ __global__ void __launch_bounds__((Geo<T, N>::PX * Geo<T, N>::TX))
     }
   }
   const T sc = (T)a.inv_n3;
-  auto B = gbl((cx<T>*)a.specB);
   // scalar weighted densities n0..n3
 #pragma unroll 1
   for (int o = 0; o < 4; ++o) {
@@ -607,9 +675,8 @@ __global__ void __launch_bounds__((Geo<T, N>::PX * Geo<T, N>::TX))
       v[m] = cscale<T>(s0, sc);
     }
     fft_pencil<T, N, EX, false>(v, t, tw, lp);
-    auto dst = B + (long)o * a.fstride + pc.off;
 #pragma unroll
-    for (int m = 0; m < EX; ++m) dst[(long)(t + TX * m) * pc.es] = v[m];
+    for (int m = 0; m < EX; ++m) B.st<cx<T>>(v[m], eo[m], (uint32_t)o * fbytes);
   }
   // vector weighted densities: n1v_c = +i khat_c V1, n2v_c = +i khat_c V2
 #pragma unroll
@@ -619,18 +686,12 @@ __global__ void __launch_bounds__((Geo<T, N>::PX * Geo<T, N>::TX))
       cx<T> v[EX];
 #pragma unroll
       for (int m = 0; m < EX; ++m) {
-        const int kx = t + TX * m;
-        int s;
-        if (c == 0) s = (kx == H) ? 0 : sgn_idx(kx, N);
-        else if (c == 1) s = (pc.ky == H) ? 0 : sy;
-        else s = (pc.kz == H) ? 0 : sz;
-        const T u = (T)s * rsq[mm[m]] * sc;
+        const T u = (c == 0 ? ks.ux[m] : c == 1 ? ks.uy[m] : ks.uz[m]) * sc;
         v[m] = cscale<T>(cmuli<T>(acc[4 + b][m]), u);
       }
       fft_pencil<T, N, EX, false>(v, t, tw, lp);
-      auto dst = B + (long)(4 + 3 * b + c) * a.fstride + pc.off;
 #pragma unroll
-      for (int m = 0; m < EX; ++m) dst[(long)(t + TX * m) * pc.es] = v[m];
+      for (int m = 0; m < EX; ++m) B.st<cx<T>>(v[m], eo[m], (uint32_t)(4 + 3 * b + c) * fbytes);
     }
   }
 }
@@ -640,44 +701,43 @@ __global__ void __launch_bounds__((Geo<T, N>::PX * Geo<T, N>::TX))
 //   mu^_i = j0_i (F0 + R_i F1 + 4 pi R_i^2 F2) + w3_i F3
 //           - i V2_i (D1 / (4 pi R_i) + D2) + sum_j G_ij rho^_j,
 // with F_a the derivative spectra and D_b = khat . (vector derivative b).
-template <typename T, int N, int CH>
-__global__ void __launch_bounds__((Geo<T, N>::PX * Geo<T, N>::TX))
+// Output species are processed in chunks of CH (<= 4).
+template <typename T, int N, int CH, int EX = Geo<T, N>::EX, int PX = Geo<T, N>::PX>
+__global__ void __launch_bounds__((PX * (N / EX)))
     k_xback(const EvalArgs* __restrict__ args) {
-  using G = Geo<T, N>;
-  constexpr int H = G::H, TX = G::TX, EX = G::EX, PX = G::PX;
+  static_assert(CH >= 1 && CH <= 4, "output chunk");
+  constexpr int TX = N / EX;
   __shared__ cx<T> tw[N];
   __shared__ cx<T> xch[PX * N];
   int tile;
-  const EvalArgs& a = args[inst_of(G::tiles_x, tile)];
+  const EvalArgs& a = args[inst_of(x_tiles<N, PX>(), tile)];
   init_twiddles<T, N>(tw);
   __syncthreads();
   const int p = threadIdx.x % PX, t = threadIdx.x / PX;
-  const XPencil<T, N> pc(tile, p);
+  const XPencil<N, PX> pc(tile, p);
   const LdsPencil<T> lp{xch + p, PX};
   const int S = a.S;
-  const int sy = sgn_idx(pc.ky, N), sz = pc.kz;
-  auto hs = gbl((const T*)a.hs_tab);
-  auto rsq = gbl((const T*)a.rsq_tab);
-  auto pt = gbl((const T*)a.pair_tab);
-  int mm[EX];
+  const Buf hs = make_buf(a.hs_tab, table_m<T, N>(0) * S * sizeof(v4<T>));
+  const Buf pt = make_buf(a.pair_tab, a.pair_on ? table_m<T, N>(0) * S * a.Sp * sizeof(T) : 0);
+  const Buf A = make_buf(a.specA, spec_bytes<T>(a, S));
+  const Buf B = make_buf(a.specB, a.hs_on ? spec_bytes<T>(a, kFields) : 0);
+  const Buf C = make_buf(a.specC, spec_bytes<T>(a, S));
+  const uint32_t fbytes = (uint32_t)(a.fstride * sizeof(cx<T>));
+  const XKs<T, N, EX, TX> ks(t, pc.ky, pc.kz);
+  uint32_t eo[EX];
 #pragma unroll
-  for (int m = 0; m < EX; ++m) {
-    const int sx = sgn_idx(t + TX * m, N);
-    mm[m] = sx * sx + sy * sy + sz * sz;
-  }
+  for (int m = 0; m < EX; ++m) eo[m] = (pc.off + (uint32_t)(t + TX * m) * pc.es) * (uint32_t)sizeof(cx<T>);
   cx<T> F[6][EX];
 #pragma unroll
   for (int q = 0; q < 6; ++q)
 #pragma unroll
     for (int m = 0; m < EX; ++m) F[q][m] = mk<T>((T)0, (T)0);
-  auto B = gbl((const cx<T>*)a.specB);
   if (a.hs_on) {
 #pragma unroll 1
     for (int f = 0; f < 4; ++f) {
-      auto src = B + (long)f * a.fstride + pc.off;
       cx<T> v[EX];
 #pragma unroll
-      for (int m = 0; m < EX; ++m) v[m] = src[(long)(t + TX * m) * pc.es];
+      for (int m = 0; m < EX; ++m) v[m] = B.ld<cx<T>>(eo[m], (uint32_t)f * fbytes);
       fft_pencil<T, N, EX, true>(v, t, tw, lp);
 #pragma unroll
       for (int m = 0; m < EX; ++m) {
@@ -693,25 +753,16 @@ __global__ void __launch_bounds__((Geo<T, N>::PX * Geo<T, N>::TX))
     for (int b = 0; b < 2; ++b) {
 #pragma unroll 1
       for (int c = 0; c < 3; ++c) {
-        auto src = B + (long)(4 + 3 * b + c) * a.fstride + pc.off;
         cx<T> v[EX];
 #pragma unroll
-        for (int m = 0; m < EX; ++m) v[m] = src[(long)(t + TX * m) * pc.es];
+        for (int m = 0; m < EX; ++m) v[m] = B.ld<cx<T>>(eo[m], (uint32_t)(4 + 3 * b + c) * fbytes);
         fft_pencil<T, N, EX, true>(v, t, tw, lp);
 #pragma unroll
-        for (int m = 0; m < EX; ++m) {
-          const int kx = t + TX * m;
-          int s;
-          if (c == 0) s = (kx == H) ? 0 : sgn_idx(kx, N);
-          else if (c == 1) s = (pc.ky == H) ? 0 : sy;
-          else s = (pc.kz == H) ? 0 : sz;
-          cfma<T>(F[4 + b][m], v[m], (T)s * rsq[mm[m]]);
-        }
+        for (int m = 0; m < EX; ++m)
+          cfma<T>(F[4 + b][m], v[m], c == 0 ? ks.ux[m] : c == 1 ? ks.uy[m] : ks.uz[m]);
       }
     }
   }
-  auto A = gbl((const cx<T>*)a.specA);
-  auto C = gbl((cx<T>*)a.specC);
   const T sc = (T)a.inv_n3;
 #pragma unroll 1
   for (int i0 = 0; i0 < S; i0 += CH) {
@@ -723,19 +774,18 @@ __global__ void __launch_bounds__((Geo<T, N>::PX * Geo<T, N>::TX))
     if (a.pair_on) {
 #pragma unroll 1
       for (int j = 0; j < S; ++j) {
-        auto src = A + (long)j * a.fstride + pc.off;
         cx<T> v[EX];
 #pragma unroll
-        for (int m = 0; m < EX; ++m) v[m] = src[(long)(t + TX * m) * pc.es];
+        for (int m = 0; m < EX; ++m) v[m] = A.ld<cx<T>>(eo[m], (uint32_t)j * fbytes);
         fft_pencil<T, N, EX, true>(v, t, tw, lp);
 #pragma unroll
-        for (int c = 0; c < CH; ++c) {
-          const int i = i0 + c;
-          if (i < S) {
-            const int pi = a.pidx[i][j];
-#pragma unroll
-            for (int m = 0; m < EX; ++m) cfma<T>(out[c][m], v[m], pt[(long)mm[m] * a.np + pi]);
-          }
+        for (int m = 0; m < EX; ++m) {
+          // G_{i0..i0+3, j} in one gather: row [m][j][.] of the pair table
+          const v4<T> g = pt.ld<v4<T>>((uint32_t)((ks.mm[m] * S + j) * a.Sp + i0) * (uint32_t)sizeof(T));
+          cfma<T>(out[0][m], v[m], g.x);
+          if constexpr (CH > 1) cfma<T>(out[1][m], v[m], g.y);
+          if constexpr (CH > 2) cfma<T>(out[2][m], v[m], g.z);
+          if constexpr (CH > 3) cfma<T>(out[3][m], v[m], g.w);
         }
       }
     }
@@ -749,52 +799,52 @@ __global__ void __launch_bounds__((Geo<T, N>::PX * Geo<T, N>::TX))
         for (int m = 0; m < EX; ++m) {
           cx<T> u = out[c][m];
           if (a.hs_on) {
-            auto w = hs + (long)mm[m] * 3 * S + 3 * i;
-            const T j0 = w[0], s3 = w[1], vv = w[2];
+            const v4<T> w = hs.ld<v4<T>>((uint32_t)(ks.mm[m] * S + i) * (uint32_t)sizeof(v4<T>));
             cx<T> sc0 = F[0][m];
             cfma<T>(sc0, F[1][m], R);
             cfma<T>(sc0, F[2][m], ar);
-            cfma<T>(u, sc0, j0);
-            cfma<T>(u, F[3][m], s3);
+            cfma<T>(u, sc0, w.x);
+            cfma<T>(u, F[3][m], w.y);
             cx<T> dv = F[5][m];
             cfma<T>(dv, F[4][m], i4);
-            cfma<T>(u, cmulmi<T>(dv), vv);
+            cfma<T>(u, cmulmi<T>(dv), w.z);
           }
           v[m] = cscale<T>(u, sc);
         }
         fft_pencil<T, N, EX, false>(v, t, tw, lp);
-        auto dst = C + (long)i * a.fstride + pc.off;
 #pragma unroll
-        for (int m = 0; m < EX; ++m) dst[(long)(t + TX * m) * pc.es] = v[m];
+        for (int m = 0; m < EX; ++m) C.st<cx<T>>(v[m], eo[m], (uint32_t)i * fbytes);
       }
     }
   }
 }
 
 // plain x-direction c2c on `nf` fields of `sel` (used by the FFT test hook)
-template <typename T, int N, bool FWD>
-__global__ void __launch_bounds__((Geo<T, N>::PX * Geo<T, N>::TX))
+template <typename T, int N, bool FWD, int EX = Geo<T, N>::EX, int PX = Geo<T, N>::PX>
+__global__ void __launch_bounds__((PX * (N / EX)))
     k_xplain(const EvalArgs* __restrict__ args, int sel, int nf) {
-  using G = Geo<T, N>;
-  constexpr int TX = G::TX, EX = G::EX, PX = G::PX;
+  constexpr int TX = N / EX;
   __shared__ cx<T> tw[N];
   __shared__ cx<T> xch[PX * N];
   int tile;
-  const EvalArgs& a = args[inst_of(G::tiles_x, tile)];
+  const EvalArgs& a = args[inst_of(x_tiles<N, PX>(), tile)];
   init_twiddles<T, N>(tw);
   __syncthreads();
   const int p = threadIdx.x % PX, t = threadIdx.x / PX;
-  const XPencil<T, N> pc(tile, p);
+  const XPencil<N, PX> pc(tile, p);
   const LdsPencil<T> lp{xch + p, PX};
-  auto base = gbl((cx<T>*)(sel == 0 ? a.specA : sel == 1 ? a.specB : a.specC));
+  const Buf base = make_buf(sel == 0 ? a.specA : sel == 1 ? a.specB : a.specC, spec_bytes<T>(a, nf));
+  const uint32_t fbytes = (uint32_t)(a.fstride * sizeof(cx<T>));
+  uint32_t eo[EX];
+#pragma unroll
+  for (int m = 0; m < EX; ++m) eo[m] = (pc.off + (uint32_t)(t + TX * m) * pc.es) * (uint32_t)sizeof(cx<T>);
   for (int f = 0; f < nf; ++f) {
-    auto fb = base + (long)f * a.fstride + pc.off;
     cx<T> v[EX];
 #pragma unroll
-    for (int m = 0; m < EX; ++m) v[m] = fb[(long)(t + TX * m) * pc.es];
+    for (int m = 0; m < EX; ++m) v[m] = base.ld<cx<T>>(eo[m], (uint32_t)f * fbytes);
     fft_pencil<T, N, EX, FWD>(v, t, tw, lp);
 #pragma unroll
-    for (int m = 0; m < EX; ++m) fb[(long)(t + TX * m) * pc.es] = v[m];
+    for (int m = 0; m < EX; ++m) base.st<cx<T>>(v[m], eo[m], (uint32_t)f * fbytes);
   }
 }
 
@@ -804,19 +854,21 @@ __global__ void k_export(const EvalArgs* __restrict__ args, int nf, double* buf,
   constexpr int H = N / 2;
   const EvalArgs& a = args[0];
   const long total = (long)nf * N * N * (H + 1);
-  auto A = gbl((cx<T>*)a.specA);
+  const gp<cx<T>> A = gbl((cx<T>*)a.specA);
+  const gp<double> bb = gbl(buf);
   for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (long)gridDim.x * blockDim.x) {
     const long f = e / ((long)N * N * (H + 1));
     const long rem = e % ((long)N * N * (H + 1));
     const long kx = rem / ((long)N * (H + 1));
     const long ky = (rem / (H + 1)) % N;
     const long kz = rem % (H + 1);
-    auto s = A + f * a.fstride + (kz < H ? (kx * N + ky) * H + kz : (long)N * N * H + kx * N + ky);
+    const gp<cx<T>> s =
+        A + f * a.fstride + (kz < H ? (kx * N + ky) * H + kz : (long)N * N * H + kx * N + ky);
     if (to_numpy) {
-      buf[2 * e] = (double)s->x;
-      buf[2 * e + 1] = (double)s->y;
+      bb[2 * e] = (double)s->x;
+      bb[2 * e + 1] = (double)s->y;
     } else {
-      *s = mk<T>((T)buf[2 * e], (T)buf[2 * e + 1]);
+      *s = mk<T>((T)bb[2 * e], (T)bb[2 * e + 1]);
     }
   }
 }

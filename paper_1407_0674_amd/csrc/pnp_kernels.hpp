@@ -28,14 +28,14 @@ struct EvalArgs {
   double area[kMaxSpecies];     // 4 pi R^2
   double inv4piR[kMaxSpecies];  // 1 / (4 pi R)
   double cfin[kMaxSpecies];     // constant added to beta mu in the final pass
-  int8_t pidx[kMaxSpecies][kMaxSpecies];  // pair slot of (i, j)
+  int32_t Sp;         // S rounded up to a multiple of 4 (row length of the pair table)
+  int32_t pad1;
   const double* rho;  // [S][n^3] input densities
   void* specA;        // S spectral fields (densities)
   void* specB;        // 10 spectral fields (weighted densities, then derivatives)
   void* specC;        // S spectral fields (chemical potentials)
-  const void* hs_tab;    // [M][3S]: j0(kR), 4 pi R^3 j1(kR)/(kR), 4 pi R^2 j1(kR)
-  const void* rsq_tab;   // [M]: 1/sqrt(m) (0 at m = 0)
-  const void* pair_tab;  // [M][np]: combined pair kernel
+  const void* hs_tab;    // [M][S][4]: j0(kR), 4 pi R^3 j1(kR)/(kR), 4 pi R^2 j1(kR), 0
+  const void* pair_tab;  // [M][S][Sp]: entry [m][j][i] = combined pair kernel G_ij
   double* out;        // real output [nreal][n^3] (mu_ex or weighted densities)
   double* slot;       // [S][n^3] exp(-mu) or null
   uint32_t* status;   // two words
@@ -51,10 +51,10 @@ struct TableArgs {
   double Bsig[kMaxPairs];     // B_ij / sigma_ij
   double sw_pref[kMaxPairs];  // -beta c_sw eps_ij (0 when SW is off)
   double rout[kMaxPairs];
+  int8_t pidx[kMaxSpecies][kMaxSpecies];  // pair slot of (i, j)
+  int32_t Sp;
   void* hs_tab;
-  void* rsq_tab;
   void* pair_tab;
-  int32_t single;  // 1: T = float tables, 0: double
 };
 
 }  // namespace pnp
