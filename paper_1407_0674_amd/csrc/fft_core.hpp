@@ -203,12 +203,29 @@ constexpr int pick_radix(int rem, int ept) {
   return 1;
 }
 
+// Ordering of an LDS exchange.  WAVE = true when every lane that reads an
+// element belongs to the wavefront that wrote it: LDS operations of one
+// wavefront execute in issue order, so only compiler reordering has to be
+// prevented (no s_barrier).  Otherwise the whole workgroup synchronises.
+template <bool WAVE>
+__device__ __forceinline__ void lds_sync() {
+  if constexpr (WAVE) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  } else {
+    __syncthreads();
+  }
+}
+
 // LDS view of one pencil: element pos lives at base[pos * es]
-template <typename T> struct LdsPencil {
+template <typename T, bool WAVE = false> struct LdsPencil {
   cx<T>* base;
   int es;
+  static constexpr bool wave = WAVE;
   __device__ __forceinline__ void st(int pos, cx<T> v) const { base[pos * es] = v; }
   __device__ __forceinline__ cx<T> ld(int pos) const { return base[pos * es]; }
+  __device__ __forceinline__ void sync() const { lds_sync<WAVE>(); }
 };
 
 // twiddle table tw[i] = exp(-2 pi i * i / N), i in [0, N), in LDS
@@ -218,9 +235,8 @@ __device__ __forceinline__ cx<T> twiddle(const cx<T>* tw, int idx) {
   return FWD ? w : cconj<T>(w);
 }
 
-template <typename T, int N, int EPT, int R, int NS, bool FWD>
-__device__ __forceinline__ void stockham_stage(cx<T>* v, int t, const cx<T>* tw,
-                                               const LdsPencil<T>& lds) {
+template <typename T, int N, int EPT, int R, int NS, bool FWD, class L>
+__device__ __forceinline__ void stockham_stage(cx<T>* v, int t, const cx<T>* tw, const L& lds) {
   constexpr int TPP = N / EPT;
   constexpr int B = EPT / R;
   static_assert(EPT % R == 0 && N % (NS * R) == 0, "bad radix plan");
@@ -253,16 +269,15 @@ __device__ __forceinline__ void stockham_stage(cx<T>* v, int t, const cx<T>* tw,
 #pragma unroll
       for (int r = 0; r < R; ++r) lds.st(base + r * NS, out[b + r * B]);
     }
-    __syncthreads();
+    lds.sync();
 #pragma unroll
     for (int m = 0; m < EPT; ++m) v[m] = lds.ld(t + TPP * m);
-    __syncthreads();
+    lds.sync();
   }
 }
 
-template <typename T, int N, int EPT, int NS, bool FWD>
-__device__ __forceinline__ void stockham_run(cx<T>* v, int t, const cx<T>* tw,
-                                             const LdsPencil<T>& lds) {
+template <typename T, int N, int EPT, int NS, bool FWD, class L>
+__device__ __forceinline__ void stockham_run(cx<T>* v, int t, const cx<T>* tw, const L& lds) {
   if constexpr (NS < N) {
     constexpr int R = pick_radix(N / NS, EPT);
     static_assert(R > 1, "unsupported length / elements-per-thread pair");
@@ -272,10 +287,10 @@ __device__ __forceinline__ void stockham_run(cx<T>* v, int t, const cx<T>* tw,
 }
 
 // Unnormalised DFT of one pencil held as v[m] = x[t + (N/EPT) m].
-// Every thread of the workgroup must call this (it contains barriers).
-template <typename T, int N, int EPT, bool FWD>
-__device__ __forceinline__ void fft_pencil(cx<T>* v, int t, const cx<T>* tw,
-                                           const LdsPencil<T>& lds) {
+// Every thread of the workgroup (or of the wavefront, for a wave-local LDS
+// view) must call this: it contains the exchange synchronisation.
+template <typename T, int N, int EPT, bool FWD, class L>
+__device__ __forceinline__ void fft_pencil(cx<T>* v, int t, const cx<T>* tw, const L& lds) {
   stockham_run<T, N, EPT, 1, FWD>(v, t, tw, lds);
 }
 

@@ -252,6 +252,11 @@ __global__ void __launch_bounds__(256) k_tables(const TableArgs* __restrict__ ta
 // O = (C[k] - conj C[H-k]) / (2i), W = exp(-2 pi i / n).
 // Spectral element e of a field sits at byte e * sizeof(cx<T>) + soff.
 // ---------------------------------------------------------------------------
+// A z-pass row is owned by TZ consecutive lanes; when TZ divides the
+// wavefront every row lies inside one wavefront and its exchanges are
+// wave-local.
+template <int TZ> constexpr bool row_in_wave() { return TZ <= 64 && 64 % TZ == 0; }
+
 // v holds C[k] at k = t + TZ m; writes X[k] (k < H) and X[H] of one row
 template <typename T, int N, int TZ, int EZ>
 __device__ __forceinline__ void r2c_post(cx<T>* v, int t, const cx<T>* twN, cx<T>* row, const Buf& f,
@@ -260,7 +265,7 @@ __device__ __forceinline__ void r2c_post(cx<T>* v, int t, const cx<T>* twN, cx<T
   constexpr uint32_t cs = sizeof(cx<T>);
 #pragma unroll
   for (int m = 0; m < EZ; ++m) row[t + TZ * m] = v[m];
-  __syncthreads();
+  lds_sync<row_in_wave<TZ>()>();
 #pragma unroll
   for (int m = 0; m < EZ; ++m) {
     const int k = t + TZ * m;
@@ -271,7 +276,7 @@ __device__ __forceinline__ void r2c_post(cx<T>* v, int t, const cx<T>* twN, cx<T
     f.st<cx<T>>(cadd<T>(e, cmul<T>(twN[k], cmulmi<T>(d))), (row_id * H + k) * cs, soff);
     if (k == 0) f.st<cx<T>>(mk<T>(c.x - c.y, (T)0), ((uint32_t)(N * N * H) + row_id) * cs, soff);
   }
-  __syncthreads();
+  lds_sync<row_in_wave<TZ>()>();
 }
 
 // inverse: from X[k] (k < H) and X[H] build C[k] = (X[k] + conj X[H-k]) +
@@ -322,7 +327,7 @@ __global__ void __launch_bounds__((Geo<T, N>::RZ * Geo<T, N>::TZ))
   const int t = threadIdx.x % TZ, r = threadIdx.x / TZ;
   const uint32_t row = (uint32_t)(tile * RZ + r);
   cx<T>* lrow = xch + r * H;
-  const LdsPencil<T> lp{lrow, 1};
+  const LdsPencil<T, row_in_wave<TZ>()> lp{lrow, 1};
   constexpr uint32_t n3b = (uint32_t)N * N * N * sizeof(double);
   const Buf rho = make_buf(a.rho, (uint64_t)a.S * n3b);
   const Buf A = make_buf(a.specA, spec_bytes<T>(a, a.S));
@@ -356,7 +361,7 @@ __global__ void __launch_bounds__((Geo<T, N>::RZ * Geo<T, N>::TZ))
   __syncthreads();
   const int t = threadIdx.x % TZ, r = threadIdx.x / TZ;
   const uint32_t row = (uint32_t)(tile * RZ + r);
-  const LdsPencil<T> lp{xch + r * H, 1};
+  const LdsPencil<T, row_in_wave<TZ>()> lp{xch + r * H, 1};
   const Buf src = make_buf(sel == 0 ? a.specA : sel == 1 ? a.specB : a.specC, spec_bytes<T>(a, a.nreal));
   constexpr uint32_t n3 = (uint32_t)N * N * N;
   constexpr uint32_t n3b = n3 * sizeof(double);
@@ -401,44 +406,48 @@ __global__ void __launch_bounds__((Geo<T, N>::RZ * Geo<T, N>::TZ))
 // (Sec. 2.3.1), z r2c of the 10 derivative fields; in place on specB.
 // Every thread keeps its EZD elements of all ten fields in registers, so the
 // ten values at a grid point meet in one thread without an LDS round trip.
-template <typename T, int N> struct GeoD {
+template <typename T, int N>
+constexpr int default_ezd() {
+  return ((N / 2) % 3 == 0) ? 6 : ((N / 2) >= (sizeof(T) == 4 ? 4 : 2) ? (sizeof(T) == 4 ? 4 : 2) : N / 2);
+}
+
+template <typename T, int N, int EZ = default_ezd<T, N>()> struct GeoD {
   static constexpr int H = N / 2;
-  static constexpr int EZD = (H % 3 == 0) ? 6
-                                          : (H >= (sizeof(T) == 4 ? 4 : 2) ? (sizeof(T) == 4 ? 4 : 2) : H);
+  static constexpr int EZD = EZ;
   static constexpr int TZD = H / EZD;
   static constexpr int RDD = pow2_divisor_le((long)N * N, 256 / TZD < 1 ? 1 : 256 / TZD);
   static constexpr int tiles = (N * N) / RDD;
 };
 
-template <typename T, int N, int F>
+template <typename T, int N, int EZ, bool BAR, int F, class L>
 __device__ __forceinline__ void zd_load(cx<T>* val, int t, const cx<T>* twN, const cx<T>* twH,
-                                        const LdsPencil<T>& lp, const Buf& B, uint32_t fbytes, uint32_t row) {
+                                        const L& lp, const Buf& B, uint32_t fbytes, uint32_t row) {
   if constexpr (F < kFields) {
-    using D = GeoD<T, N>;
-    c2r_pre<T, N, D::TZD, D::EZD>(val + F * D::EZD, t, twN, B, F * fbytes, row);
-    fft_pencil<T, N / 2, D::EZD, false>(val + F * D::EZD, t, twH, lp);
-    __builtin_amdgcn_sched_barrier(0);  // keep the next field's loads after this FFT
-    zd_load<T, N, F + 1>(val, t, twN, twH, lp, B, fbytes, row);
+    using D = GeoD<T, N, EZ>;
+    c2r_pre<T, N, D::TZD, EZ>(val + F * EZ, t, twN, B, F * fbytes, row);
+    fft_pencil<T, N / 2, EZ, false>(val + F * EZ, t, twH, lp);
+    if constexpr (BAR) __builtin_amdgcn_sched_barrier(0);  // keep the next field's loads after this FFT
+    zd_load<T, N, EZ, BAR, F + 1>(val, t, twN, twH, lp, B, fbytes, row);
   }
 }
 
-template <typename T, int N, int F>
+template <typename T, int N, int EZ, bool BAR, int F, class L>
 __device__ __forceinline__ void zd_store(cx<T>* val, int t, const cx<T>* twN, const cx<T>* twH,
-                                         const LdsPencil<T>& lp, cx<T>* lrow, const Buf& B, uint32_t fbytes,
+                                         const L& lp, cx<T>* lrow, const Buf& B, uint32_t fbytes,
                                          uint32_t row) {
   if constexpr (F < kFields) {
-    using D = GeoD<T, N>;
-    fft_pencil<T, N / 2, D::EZD, true>(val + F * D::EZD, t, twH, lp);
-    r2c_post<T, N, D::TZD, D::EZD>(val + F * D::EZD, t, twN, lrow, B, F * fbytes, row);
-    __builtin_amdgcn_sched_barrier(0);
-    zd_store<T, N, F + 1>(val, t, twN, twH, lp, lrow, B, fbytes, row);
+    using D = GeoD<T, N, EZ>;
+    fft_pencil<T, N / 2, EZ, true>(val + F * EZ, t, twH, lp);
+    r2c_post<T, N, D::TZD, EZ>(val + F * EZ, t, twN, lrow, B, F * fbytes, row);
+    if constexpr (BAR) __builtin_amdgcn_sched_barrier(0);
+    zd_store<T, N, EZ, BAR, F + 1>(val, t, twN, twH, lp, lrow, B, fbytes, row);
   }
 }
 
-template <typename T, int N>
-__global__ void __launch_bounds__((GeoD<T, N>::RDD * GeoD<T, N>::TZD))
+template <typename T, int N, int EZD = default_ezd<T, N>(), bool BAR = true>
+__global__ void __launch_bounds__((GeoD<T, N, EZD>::RDD * GeoD<T, N, EZD>::TZD))
     k_zderiv(const EvalArgs* __restrict__ args) {
-  using D = GeoD<T, N>;
+  using D = GeoD<T, N, EZD>;
   constexpr int H = D::H, TZ = D::TZD, EZ = D::EZD, RD = D::RDD;
   __shared__ cx<T> twH[H];
   __shared__ cx<T> twN[N];
@@ -452,11 +461,11 @@ __global__ void __launch_bounds__((GeoD<T, N>::RDD * GeoD<T, N>::TZD))
   const int t = threadIdx.x % TZ, r = threadIdx.x / TZ;
   const uint32_t row = (uint32_t)(tile * RD + r);
   cx<T>* lrow = xch + r * H;
-  const LdsPencil<T> lp{lrow, 1};
+  const LdsPencil<T, row_in_wave<TZ>()> lp{lrow, 1};
   const Buf B = make_buf(a.specB, spec_bytes<T>(a, kFields));
   const uint32_t fbytes = (uint32_t)(a.fstride * sizeof(cx<T>));
   cx<T> val[kFields * EZ];
-  zd_load<T, N, 0>(val, t, twN, twH, lp, B, fbytes, row);
+  zd_load<T, N, EZ, BAR, 0>(val, t, twN, twH, lp, B, fbytes, row);
   uint32_t bad = 0u, badidx = 0xffffffffu;
   const double inv8pi = 1.0 / (8.0 * kPi), inv12pi = 1.0 / (12.0 * kPi), inv4pi = 1.0 / (4.0 * kPi);
 #pragma unroll
@@ -492,10 +501,10 @@ __global__ void __launch_bounds__((GeoD<T, N>::RDD * GeoD<T, N>::TZD))
         if (h) val[q * EZ + m].y = (T)d[q];
         else val[q * EZ + m].x = (T)d[q];
       }
-      __builtin_amdgcn_sched_barrier(0);  // one grid point at a time: bounded live range
+      if constexpr (BAR) __builtin_amdgcn_sched_barrier(0);  // one grid point at a time
     }
   }
-  zd_store<T, N, 0>(val, t, twN, twH, lp, lrow, B, fbytes, row);
+  zd_store<T, N, EZ, BAR, 0>(val, t, twN, twH, lp, lrow, B, fbytes, row);
   if (bad) raise_status(a.status, bad, badidx);
 }
 
