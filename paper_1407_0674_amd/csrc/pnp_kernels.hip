@@ -106,6 +106,12 @@ struct Buf {
       return __builtin_bit_cast(X, pr);
     }
   }
+  // Stores wider than 64 bits take the whole offset in the lane offset and a
+  // zero scalar offset: the store reads its data registers one instruction
+  // after issue, and the compiler inserts the wait that protects them from an
+  // immediate overwrite only for this form of the instruction (with a
+  // register scalar offset it emits none, and the low half of the stored
+  // data can be replaced by the next value written to those registers).
   template <typename X>
   __device__ __forceinline__ void st(X v, uint32_t voff, uint32_t soff = 0) const {
     if constexpr (sizeof(X) == 4) {
@@ -113,13 +119,13 @@ struct Buf {
     } else if constexpr (sizeof(X) == 8) {
       __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, voff, soff, 0);
     } else if constexpr (sizeof(X) == 16) {
-      __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, v), r, voff, soff, 0);
+      __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, v), r, voff + soff, 0, 0);
     } else {
       static_assert(sizeof(X) == 32, "buffer access size");
       struct P { u32x4 a, b; };
       const P pr = __builtin_bit_cast(P, v);
-      __builtin_amdgcn_raw_buffer_store_b128(pr.a, r, voff, soff, 0);
-      __builtin_amdgcn_raw_buffer_store_b128(pr.b, r, voff + 16, soff, 0);
+      __builtin_amdgcn_raw_buffer_store_b128(pr.a, r, voff + soff, 0, 0);
+      __builtin_amdgcn_raw_buffer_store_b128(pr.b, r, voff + soff + 16, 0, 0);
     }
   }
 };
@@ -880,6 +886,20 @@ __global__ void k_export(const EvalArgs* __restrict__ args, int nf, double* buf,
       *s = mk<T>((T)bb[2 * e], (T)bb[2 * e + 1]);
     }
   }
+}
+
+// plain device copy of 16-byte words (bandwidth and counter calibration)
+__global__ void __launch_bounds__(256) k_copy(const uint4* __restrict__ src, uint4* __restrict__ dst, long words) {
+  const long stride = (long)gridDim.x * blockDim.x;
+  long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  for (; e + 3 * stride < words; e += 4 * stride) {
+    const uint4 a = src[e], b = src[e + stride], c = src[e + 2 * stride], d = src[e + 3 * stride];
+    dst[e] = a;
+    dst[e + stride] = b;
+    dst[e + 2 * stride] = c;
+    dst[e + 3 * stride] = d;
+  }
+  for (; e < words; e += stride) dst[e] = src[e];
 }
 
 // relaxation of the consumer stub: rho <- (1 - l) rho + l rho_b exp(mu_b - mu)
