@@ -91,24 +91,61 @@ def latencies(ev, prob, rho_d, out, slot, reps, precision):
     return lat
 
 
-def cpu_baseline(name):
-    """The oracle (numpy FFT route, as written) on a bounded sample of the
-    workload: the same recipe on a 128^3 grid, one evaluation."""
-    import numpy as np
+def cpu_baseline(prob, rho):
+    """The oracle (numpy FFT route, as written, FP64) timed on one evaluation
+    of the benchmark's own problem, limited to one thread."""
     import oracle
-    import pnp_inputs as P
-    n = 128 if name == "cfg3" else 64
-    if name == "cfg3":
-        prob, rho = P.config3(n=n)
-    else:
-        prob, rho = P.config2(n=n)
-    t0 = time.perf_counter()
-    oracle.mu_ex(prob, rho, "fft")
-    dt = time.perf_counter() - t0
+    from threadpoolctl import threadpool_limits
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        oracle.mu_ex(prob, rho, "fft")
+        dt = time.perf_counter() - t0
     return {"value": prob.n ** 3 * prob.S / dt, "unit": "grid-pt*species/s", "cores": 1,
             "kind": "oracle",
-            "sample": f"one evaluation of the same recipe at {n}^3 (S={prob.S}) with the "
-                      f"oracle's numpy-FFT route in FP64, {dt:.1f} s, single-threaded pocketfft"}
+            "sample": f"one full evaluation of the same problem ({prob.n}^3, S={prob.S}, all terms) "
+                      f"with the oracle's numpy-FFT route in FP64 on one host thread, {dt:.1f} s"}
+
+
+def copy_bandwidth(ev, gib=1.0, reps=10):
+    """Achievable HBM bandwidth: the library's streaming copy kernel over a
+    buffer of `gib` GiB, read once and written once per launch (HIP events on
+    the launching stream)."""
+    import torch
+    words = int(gib * (1 << 30)) // 8
+    a = torch.ones(words, dtype=torch.float64, device="cuda:0")
+    b = torch.empty_like(a)
+    ev.copy(a, b)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        ev.copy(a, b)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    ok = bool(torch.equal(a, b))
+    del a, b
+    return {"GBps": 2 * words * 8 / 1e9 / (ms / 1e3), "bytes_per_launch": 2 * words * 8, "ms": ms, "verified": ok}
+
+
+def traffic_from_profile(kernel, launches_per_step):
+    """HBM bytes per launch of `kernel` measured by the memory counters, as
+    recorded with the hash of the kernel sources they were taken on; null when
+    the sources have changed since."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    h = hashlib.sha256()
+    for rel in rec.get("sources", []):
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    if h.hexdigest() != rec.get("sha256"):
+        return None
+    k = rec.get("kernels", {}).get(kernel)
+    return None if k is None else k["bytes_per_launch"]
 
 
 def main():
@@ -120,6 +157,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--latency-reps", type=int, default=20)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run the copy kernel (reference for the memory counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build evaluates on one GPU; --gpus must be 1 "
@@ -130,9 +169,13 @@ def main():
     import torch
     from paper_1407_0674_amd import Evaluator, PASS_NAMES
 
-    prob, rho, desc = workload(args.workload)
     dev = torch.device("cuda:0")
     ev = Evaluator(0)
+    if args.calibrate_copy:
+        print(json.dumps({"copy_kernel": copy_bandwidth(ev, 1.0, 5)}), flush=True)
+        ev.close()
+        return
+    prob, rho, desc = workload(args.workload)
     rho_d = torch.from_numpy(rho).to(dev).contiguous()
     S, n = prob.S, prob.n
     n3 = n ** 3
@@ -189,7 +232,9 @@ def main():
         del m3, r3
         torch.cuda.synchronize()
 
-    cpu = None if args.no_cpu else cpu_baseline(args.workload)
+    copy = copy_bandwidth(ev)
+    torch.cuda.synchronize()
+    cpu = None if args.no_cpu else cpu_baseline(prob, rho)
 
     value = n3 * S / (ms / 1e3)
     line = {
@@ -209,9 +254,12 @@ def main():
                    "precision": "mixed" if prec == 1 else "fp64"},
         "hbm": {"model_bytes_per_step": total_bytes, "GBps": total_bytes / 1e9 / (ms / 1e3),
                 "pct_peak": 100.0 * total_bytes / 1e9 / (ms / 1e3) / HBM_PEAK_GBS,
-                "kernel_ms_per_step": kernel_ms},
+                "kernel_ms_per_step": kernel_ms, "copy_kernel_GBps": copy["GBps"],
+                "pct_of_copy": 100.0 * total_bytes / 1e9 / (ms / 1e3) / copy["GBps"]},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": per_pass[dom]["GBps"], "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": per_pass[dom]["GBps"] / HBM_PEAK_GBS, "traffic": None},
+                     "unit": "GB/s", "frac": per_pass[dom]["GBps"] / HBM_PEAK_GBS,
+                     "traffic": traffic_from_profile(dom, 1),
+                     "alg_bytes_per_launch": per_pass[dom]["alg_GB"] * 1e9},
         "latency_ms": {"p50": percentile(lat, 50), "p99": percentile(lat, 99)},
         "fp64_path": result_fp64,
         "speedup_vs_fp64": (result_fp64["ms_per_step"] / ms) if result_fp64 else None,

@@ -35,7 +35,8 @@
  * example allocated by PyTorch) on the context's device; the library never
  * allocates, frees or retains caller memory.  The context owns a 4 MiB
  * device ring for per-call argument records (allocated by pnp_create) and a
- * few host records.  Scratch space comes in through `workspace`, sized by
+ * few host records; when the ring wraps (after thousands of calls) the call
+ * that wraps it waits for the device to drain.  Scratch space comes in through `workspace`, sized by
  * pnp_workspace_bytes().
  *
  * Errors: every function returns a pnp_status; nothing aborts or throws
@@ -209,6 +210,15 @@ pnp_status pnp_relax_densities(pnp_ctx ctx, const pnp_grid* grid, int32_t S,
 pnp_status pnp_debug_rfft3(pnp_ctx ctx, const pnp_grid* grid, int32_t precision,
                            int32_t count, int32_t inverse, const double* in, double* out,
                            void* workspace, size_t workspace_bytes, void* stream);
+
+/*
+ * Calibration hook: plain device-to-device copy of `bytes` bytes (a multiple
+ * of 16, both pointers 16-byte aligned, buffers must not overlap) with one
+ * streaming kernel.  Gives the achievable HBM bandwidth next to which the
+ * passes are judged, and the reference reading of the memory counters.
+ * Asynchronous on `stream`; PNP_E_ARG on a bad size or alignment.
+ */
+pnp_status pnp_debug_copy(pnp_ctx ctx, const void* src, void* dst, size_t bytes, void* stream);
 
 /*
  * Pass timing.  When enabled, every evaluation records HIP events around

@@ -31,6 +31,7 @@ from .discrete import (Operator, build_operator, real_space_kernel, wavevectors)
 from .fmt import phi_hs, dphi_hs
 from .direct import correlate_direct, convolve_direct
 from .mu_ex import mu_ex, weighted_densities, free_energy
+from .relax import relax_densities
 
 STATUS = {
     "units": "pinned: tests/test_oracle_units.py (Table 1 beta and l_B)",
@@ -39,6 +40,7 @@ STATUS = {
     "fmt": "pinned: tests/test_oracle_fmt.py (finite differences of Phi, PY bulk)",
     "direct": "pinned: tests/test_oracle_direct.py (brute-force loops, FFT route)",
     "mu_ex": "pinned: tests/test_oracle_mu_ex.py (bulk closed forms, FD consistency, symmetry)",
+    "relax": "pinned: tests/test_oracle_relax.py (lambda 0 and 1, bulk fixed point)",
 }
 
 __all__ = [
@@ -46,5 +48,5 @@ __all__ = [
     "ball_ft", "shell_ft", "shell_vec_ft", "r_ball_ft", "inv_r_ball_ft", "j0", "j1",
     "j1_over_x", "Operator", "build_operator", "real_space_kernel", "wavevectors",
     "phi_hs", "dphi_hs", "correlate_direct", "convolve_direct", "mu_ex",
-    "weighted_densities", "free_energy", "STATUS",
+    "weighted_densities", "free_energy", "relax_densities", "STATUS",
 ]

@@ -1,0 +1,25 @@
+"""Density update of the consumer stub (oracle side).
+
+Test infrastructure (see the package docstring).
+
+Between two evaluations of mu_ex a PNP loop changes the densities.  Here the
+change is a relaxation toward the equilibrium of the current excess chemical
+potential: the equilibrium density of species i in the grand ensemble is
+rho_i^bulk exp(beta mu_i^bulk - beta mu_ex_i(r)) (no potential, no ideal-gas
+constant beyond the bulk reference), and the new density mixes it with the
+old one as the relaxation step of Sec. 3.2 mixes new and old iterates:
+
+    rho_i <- (1 - lambda) rho_i + lambda rho_i^bulk exp(beta mu_i^bulk - beta mu_ex_i).
+"""
+import numpy as np
+
+
+def relax_densities(rho, mu_ex, rho_bulk, mu_bulk, lam):
+    """rho, mu_ex: float64 [S][...]; rho_bulk, mu_bulk: S values; lam in [0, 1]."""
+    rho = np.asarray(rho, dtype=np.float64)
+    mu_ex = np.asarray(mu_ex, dtype=np.float64)
+    out = np.empty_like(rho)
+    for i in range(rho.shape[0]):
+        target = rho_bulk[i] * np.exp(mu_bulk[i] - mu_ex[i])
+        out[i] = (1.0 - lam) * rho[i] + lam * target
+    return out

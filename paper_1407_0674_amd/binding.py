@@ -25,7 +25,8 @@ STATUS_NAMES = {
 EXPORTED = [
     "pnp_create", "pnp_destroy", "pnp_last_error", "pnp_supported_size", "pnp_workspace_bytes",
     "pnp_cdft_mu_ex", "pnp_weighted_densities", "pnp_batch_mu_ex", "pnp_read_status",
-    "pnp_relax_densities", "pnp_debug_rfft3", "pnp_profile_enable", "pnp_profile_read",
+    "pnp_relax_densities", "pnp_debug_rfft3", "pnp_debug_copy", "pnp_profile_enable",
+    "pnp_profile_read",
 ]
 
 PASS_NAMES = ["tables", "z_fwd_rho", "y_fwd_rho", "x_fwd_weights", "y_inv_n", "z_deriv",
@@ -102,6 +103,7 @@ def load_library():
                                         ctypes.POINTER(ctypes.c_double), ctypes.c_double, P]
     lib.pnp_debug_rfft3.argtypes = [P, ctypes.POINTER(Grid), ctypes.c_int32, ctypes.c_int32,
                                     ctypes.c_int32, P, P, P, ctypes.c_size_t, P]
+    lib.pnp_debug_copy.argtypes = [P, P, P, ctypes.c_size_t, P]
     lib.pnp_profile_enable.argtypes = [P, ctypes.c_int32]
     lib.pnp_profile_read.argtypes = [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32),
                                      ctypes.c_int32, ctypes.c_int32]
@@ -323,3 +325,16 @@ class Evaluator:
                                              ctypes.c_void_p(ws.data_ptr()), ctypes.c_size_t(ws.numel()),
                                              self._stream()))
         return out
+
+    def copy(self, src, dst):
+        """Device copy through the library's calibration kernel (asynchronous)."""
+        torch = _torch()
+        for t, nm in ((src, "src"), (dst, "dst")):
+            if not (isinstance(t, torch.Tensor) and t.is_cuda and t.is_contiguous()):
+                raise PnpError(-1, f"{nm} must be a contiguous CUDA tensor")
+        nbytes = src.numel() * src.element_size()
+        if dst.numel() * dst.element_size() != nbytes:
+            raise PnpError(-1, "copy: size mismatch")
+        self._check(self.lib.pnp_debug_copy(self.ctx, ctypes.c_void_p(src.data_ptr()),
+                                            ctypes.c_void_p(dst.data_ptr()), ctypes.c_size_t(nbytes),
+                                            self._stream()))

@@ -243,7 +243,12 @@ void fill_eval_args(EvalArgs& e, const Derived& d, const pnp_species* sp, const 
 // copy host bytes into the context's device ring (stream ordered)
 void* upload(pnp_ctx c, const void* src, size_t bytes, hipStream_t s) {
   const size_t need = up(bytes);
-  if (c->arena_pos + need > c->arena_bytes) c->arena_pos = 0;
+  if (c->arena_pos + need > c->arena_bytes) {
+    // the ring wraps: records written at its start may still be read by
+    // launches in flight on any stream, so let the device drain first
+    if (hipDeviceSynchronize() != hipSuccess) return nullptr;
+    c->arena_pos = 0;
+  }
   void* dst = c->arena + c->arena_pos;
   c->arena_pos += need;
   if (hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s) != hipSuccess) return nullptr;
@@ -708,6 +713,19 @@ pnp_status pnp_debug_rfft3(pnp_ctx ctx, const pnp_grid* g, int32_t precision, in
   if (st != PNP_OK) return st;
   if (hipStreamSynchronize(s) != hipSuccess) return device_check(ctx, "sync");
   return PNP_OK;
+}
+
+pnp_status pnp_debug_copy(pnp_ctx ctx, const void* src, void* dst, size_t bytes, void* stream) {
+  if (!ctx) return PNP_E_ARG;
+  if (!src || !dst) return fail(ctx, PNP_E_ARG, "null argument");
+  if (bytes % 16 || ((uintptr_t)src | (uintptr_t)dst) % 16)
+    return fail(ctx, PNP_E_ARG, "copy size and pointers must be multiples of 16 bytes");
+  if (bytes == 0) return PNP_OK;
+  if (hipSetDevice(ctx->device) != hipSuccess) return device_check(ctx, "set device");
+  const long words = (long)(bytes / 16);
+  const int blocks = (int)std::min<long>((words + 255) / 256, 8192);
+  hipLaunchKernelGGL(k_copy, dim3(blocks), dim3(256), 0, (hipStream_t)stream, (const uint4*)src, (uint4*)dst, words);
+  return device_check(ctx, "copy launch");
 }
 
 }  // extern "C"
