@@ -99,6 +99,7 @@ bool size_ok(int n) {
 // Derived quantities of one evaluation (host, double precision).
 struct Derived {
   int n = 0, S = 0, np = 0, precision = 0;
+  double h = 0;
   bool hs = false, ec = false, sw = false;
   double beta = 0, lB = 0, kappa = 0;
   double sigma[kMaxPairs], B[kMaxPairs], rout[kMaxPairs], eps[kMaxPairs];
@@ -123,7 +124,7 @@ Layout layout_of(int n, int S, int precision, bool hs, bool pairs, bool per_term
   const size_t prow = (size_t)S * padded_species(S);
   size_t o = 0;
   L.status = o; o = up(o + 64);
-  L.hs = o; o = up(o + (size_t)L.M * 4 * S * ts);
+  L.hs = o; if (precision == PNP_FP64) o = up(o + (size_t)L.M * 4 * S * ts);  // FP32 weights live in registers
   L.pair = o; if (pairs) o = up(o + (size_t)L.M * prow * ts);
   L.pair2 = o; if (pairs && per_term) o = up(o + (size_t)L.M * prow * ts);
   L.A = o; o = up(o + (size_t)S * L.fstride * 2 * ts);
@@ -149,7 +150,7 @@ pnp_status validate(pnp_ctx ctx, const pnp_grid* g, int S, const pnp_species* sp
     if (!(sp[i].d > 0.0) || !std::isfinite(sp[i].q) || !std::isfinite(sp[i].rho_bulk) ||
         !std::isfinite(sp[i].mu_el_bulk))
       return fail(ctx, PNP_E_ARG, "species " + std::to_string(i) + ": bad diameter, valence or bulk density");
-  d.n = g->nx; d.S = S; d.np = S * (S + 1) / 2; d.precision = p->precision;
+  d.n = g->nx; d.h = g->h; d.S = S; d.np = S * (S + 1) / 2; d.precision = p->precision;
   d.hs = p->terms & PNP_TERM_HS; d.ec = p->terms & PNP_TERM_EC; d.sw = p->terms & PNP_TERM_SW;
   if (need_T) {
     if (d.ec && !(p->eps_r > 0.0)) return fail(ctx, PNP_E_ARG, "eps_r must be > 0");
@@ -221,6 +222,7 @@ void fill_eval_args(EvalArgs& e, const Derived& d, const pnp_species* sp, const 
   e.hs_on = d.hs; e.pair_on = d.ec || d.sw;
   e.fstride = L.fstride;
   e.inv_n3 = 1.0 / ((double)d.n * d.n * d.n);
+  e.kscale = 2.0 * M_PI / (d.n * d.h);
   for (int i = 0; i < d.S; ++i) {
     const double R = 0.5 * sp[i].d;
     e.R[i] = R;
@@ -313,13 +315,18 @@ template <typename T, int N> struct Launch {
   static void zderiv(const EvalArgs* a, int count, hipStream_t s) {
     hipLaunchKernelGGL((k_zderiv<T, N>), dim3(count * GeoD<T, N>::tiles), dim3(GeoD<T, N>::RDD * GeoD<T, N>::TZD), 0, s, a);
   }
-  static void xback(const EvalArgs* a, int count, int ch, hipStream_t s) {
+  // maxS: the largest species count among the launch's instances
+  static void xback(const EvalArgs* a, int count, int maxS, hipStream_t s) {
     const dim3 g(count * G::tiles_x), b(G::PX * G::TX);
-    switch (ch) {
+    // FP64: the streamed kernel does not fit the register file; the chunked
+    // one keeps every spectrum in registers without spilling
+    if (sizeof(T) == 8) maxS = 5;
+    switch (maxS) {
       case 1: hipLaunchKernelGGL((k_xback<T, N, 1>), g, b, 0, s, a); break;
       case 2: hipLaunchKernelGGL((k_xback<T, N, 2>), g, b, 0, s, a); break;
       case 3: hipLaunchKernelGGL((k_xback<T, N, 3>), g, b, 0, s, a); break;
-      default: hipLaunchKernelGGL((k_xback<T, N, 4>), g, b, 0, s, a); break;
+      case 4: hipLaunchKernelGGL((k_xback<T, N, 4>), g, b, 0, s, a); break;
+      default: hipLaunchKernelGGL((k_xback_chunked<T, N, 4>), g, b, 0, s, a); break;
     }
   }
   static void zinv(const EvalArgs* a, int count, int sel, hipStream_t s) {
@@ -475,7 +482,7 @@ pnp_status pnp_cdft_mu_ex(pnp_ctx ctx, const pnp_grid* g, int32_t S, const pnp_s
   const Ops* op = ops_for(d.precision, d.n);
   char* w = (char*)ws;
   const double sw_c = p->sw_prefactor;
-  const int ch = std::min(S, 4);
+  const int ch = S;  // largest species count of the launch (selects the back-pass kernel)
   const long n3 = (long)d.n * d.n * d.n;
 
   if (!p->per_term) {
@@ -632,7 +639,7 @@ pnp_status pnp_batch_mu_ex(pnp_ctx ctx, int32_t count, pnp_request* reqs, void* 
     const Ops* op = ops_for(kv.first.first, kv.first.second);
     int M = 0;
     for (int k = 0; k < cnt; ++k) M = std::max(M, lay[ids[k]].M);
-    run_sequence(ctx, op, dea, dta, cnt, M, hs_any, std::min(maxS, 4), s);
+    run_sequence(ctx, op, dea, dta, cnt, M, hs_any, maxS, s);
   }
   pnp_status st = device_check(ctx, "batch launch");
   if (st != PNP_OK) return st;

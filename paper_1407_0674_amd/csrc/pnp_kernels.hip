@@ -219,8 +219,8 @@ __global__ void __launch_bounds__(256) k_tables(const TableArgs* __restrict__ ta
   const int m = (blockIdx.x % blocks_per) * blockDim.x + threadIdx.x;
   if (m >= a.M) return;
   const double k = a.kscale * sqrt((double)m);
-  const Buf hs = make_buf(a.hs_tab, (uint64_t)a.M * a.S * 4 * sizeof(T));
-  for (int i = 0; i < a.S; ++i) {
+  const Buf hs = make_buf(a.hs_tab, sizeof(T) == 8 ? (uint64_t)a.M * a.S * 4 * sizeof(T) : 0);
+  for (int i = 0; i < (sizeof(T) == 8 ? a.S : 0); ++i) {  // the FP32 path evaluates these in registers
     const double R = a.R[i];
     const double x = k * R;
     const double j1x = d_j1x(x);
@@ -623,10 +623,96 @@ struct XKs {
 template <typename T, int N>
 __device__ __forceinline__ uint64_t table_m(int /*unused*/) { return 3ull * (N / 2) * (N / 2) + 1; }
 
+// sin and cos of x >= 0 in FP32 for the arguments k R of a grid (x up to a
+// few hundred): Cody-Waite reduction by pi/2 with a three-part constant and
+// fused multiply-adds, then Taylor polynomials on [-pi/4, pi/4].  Absolute
+// error about 6e-8 up to x = 700.
+__device__ __forceinline__ void sincos_f32(float x, float& sn, float& cs) {
+  const float n = __builtin_rintf(x * 0.636619746685f);
+  float r = __builtin_fmaf(-n, 1.57079637050628662f, x);
+  r = __builtin_fmaf(-n, -4.37113882867379e-08f, r);
+  r = __builtin_fmaf(-n, -1.77635683940025e-15f, r);
+  const float r2 = r * r;
+  float ps = __builtin_fmaf(r2, 2.75573188446e-06f, -1.98412701138e-04f);
+  ps = __builtin_fmaf(r2, ps, 8.33333376795e-03f);
+  ps = __builtin_fmaf(r2, ps, -0.166666671634f);
+  const float s = __builtin_fmaf(r * r2, ps, r);  // sin r
+  float pc = __builtin_fmaf(r2, -2.75573199815e-07f, 2.48015876423e-05f);
+  pc = __builtin_fmaf(r2, pc, -1.38888892252e-03f);
+  pc = __builtin_fmaf(r2, pc, 4.16666679084e-02f);
+  pc = __builtin_fmaf(r2, pc, -0.5f);
+  const float c = __builtin_fmaf(r2, pc, 1.0f);  // cos r
+  const int q = (int)n & 3;
+  sn = q == 0 ? s : q == 1 ? c : q == 2 ? -s : -c;
+  cs = q == 0 ? c : q == 1 ? -s : q == 2 ? -c : s;
+}
+
+// Hard-sphere weights at |k| = k for radius R, in FP32 registers:
+// j0(kR), 4 pi R^3 j1(kR)/(kR) (ball) and 4 pi R^2 j1(kR) (shell magnitude).
+// j1(x)/x switches to its Taylor series below x = 1, where the closed form
+// loses digits to cancellation.
+__device__ __forceinline__ void hs_weights_f32(float k, float R, float& j0, float& w3, float& v2) {
+  const float x = k * R;
+  float sn, cs;
+  sincos_f32(x, sn, cs);
+  const float x2 = x * x;
+  // j1(x)/x = 1/3 - x^2/30 + x^4/840 - x^6/45360 + x^8/3991680 - x^10/518918400 + ...
+  const float ser =
+      0.333333333333f -
+      x2 * (3.33333333333e-2f - x2 * (1.19047619048e-3f - x2 * (2.20458553792e-5f - x2 * (2.50521083854e-7f -
+                                                                                           x2 * 1.92708526042e-9f))));
+  const float rx = 1.0f / x;
+  const float j1x = x < 1.0f ? ser : (sn - x * cs) * rx * rx * rx;
+  j0 = x < 1e-3f ? 1.0f - x2 * 0.166666667f : sn * rx;
+  const float a2 = 12.5663706144f * R * R;
+  w3 = a2 * R * j1x;
+  v2 = a2 * x * j1x;
+}
+
+// Weights of species i at the integer class m = |j|^2: computed in registers
+// for FP32, gathered from the FP64 table otherwise.
+template <typename T>
+__device__ __forceinline__ void hs_weights(const EvalArgs& a, const Buf& hs, int S, int i, int m, T& j0, T& w3,
+                                           T& v2) {
+  if constexpr (sizeof(T) == 4) {
+    hs_weights_f32((float)a.kscale * __builtin_sqrtf((float)m), (float)a.R[i], j0, w3, v2);
+  } else {
+    const v4<T> w = hs.ld<v4<T>>((uint32_t)(m * S + i) * (uint32_t)sizeof(v4<T>));
+    j0 = w.x;
+    w3 = w.y;
+    v2 = w.z;
+  }
+}
+
+// unit-vector component c of k at element kx of a pencil (0 on that axis's
+// Nyquist plane)
+template <typename T, int N>
+__device__ __forceinline__ T khat(int c, int kx, int ky, int kz, int m) {
+  const T r = inv_sqrt_m<T>(m);
+  if (c == 0) return kx == N / 2 ? (T)0 : (T)sgn_idx(kx, N) * r;
+  if (c == 1) return ky == N / 2 ? (T)0 : (T)sgn_idx(ky, N) * r;
+  return kz == N / 2 ? (T)0 : (T)kz * r;
+}
+
+// Per-lane addressing of an x tile: element m of the lane's pencil sits at
+// byte vo + m * mstride (+ the field offset).  Both strides are uniform over
+// the block, which keeps them in scalar registers.
+template <typename T, int N, int EX, int PX>
+struct XAddr {
+  uint32_t vo, mstride;
+  __device__ __forceinline__ XAddr(const XPencil<N, PX>& pc, int t) {
+    constexpr int TX = N / EX;
+    vo = (pc.off + (uint32_t)t * pc.es) * (uint32_t)sizeof(cx<T>);
+    mstride = __builtin_amdgcn_readfirstlane((uint32_t)TX * pc.es * (uint32_t)sizeof(cx<T>));
+  }
+};
+
 // P3: forward weights.  For every k: n^_a(k) = sum_i rho^_i(k) conj(w^_i^a(k))
 // (correlation, Sec. 2.3.1); scalars w0 = j0, w1 = R j0, w2 = 4 pi R^2 j0,
 // w3 = 4 pi R^3 j1(kR)/(kR); vectors conj(-i khat V) = +i khat V with
 // V2 = 4 pi R^2 j1(kR), V1 = V2 / (4 pi R).
+// The species pencils stream through two register buffers: the loads of
+// species i + 1 are in flight while species i is transformed.
 template <typename T, int N, int EX = Geo<T, N>::EX, int PX = Geo<T, N>::PX>
 __global__ void __launch_bounds__((PX * (N / EX)))
     k_xfwd(const EvalArgs* __restrict__ args) {
@@ -642,71 +728,80 @@ __global__ void __launch_bounds__((PX * (N / EX)))
   const XPencil<N, PX> pc(tile, p);
   const LdsPencil<T> lp{xch + p, PX};
   const int S = a.S;
-  const Buf hs = make_buf(a.hs_tab, table_m<T, N>(0) * S * sizeof(v4<T>));
+  const Buf hs = make_buf(a.hs_tab, sizeof(T) == 8 ? table_m<T, N>(0) * S * sizeof(v4<T>) : 0);
   const Buf A = make_buf(a.specA, spec_bytes<T>(a, S));
   const Buf B = make_buf(a.specB, spec_bytes<T>(a, kFields));
-  const uint32_t fbytes = (uint32_t)(a.fstride * sizeof(cx<T>));
-  const XKs<T, N, EX, TX> ks(t, pc.ky, pc.kz);
-  uint32_t eo[EX];
-#pragma unroll
-  for (int m = 0; m < EX; ++m) eo[m] = (pc.off + (uint32_t)(t + TX * m) * pc.es) * (uint32_t)sizeof(cx<T>);
-  cx<T> acc[6][EX];
-#pragma unroll
-  for (int q = 0; q < 6; ++q)
-#pragma unroll
-    for (int m = 0; m < EX; ++m) acc[q][m] = mk<T>((T)0, (T)0);
-  for (int i = 0; i < S; ++i) {
-    cx<T> v[EX];
-#pragma unroll
-    for (int m = 0; m < EX; ++m) v[m] = A.ld<cx<T>>(eo[m], (uint32_t)i * fbytes);
-    fft_pencil<T, N, EX, true>(v, t, tw, lp);
-    const T R = (T)a.R[i], ar = (T)a.area[i], i4 = (T)a.inv4piR[i];
+  const uint32_t fbytes = __builtin_amdgcn_readfirstlane((uint32_t)(a.fstride * sizeof(cx<T>)));
+  const XAddr<T, N, EX, PX> xa(pc, t);
+  int mm[EX];
+  {
+    const int sy = sgn_idx(pc.ky, N), sz = pc.kz;
 #pragma unroll
     for (int m = 0; m < EX; ++m) {
-      const v4<T> w = hs.ld<v4<T>>((uint32_t)(ks.mm[m] * S + i) * (uint32_t)sizeof(v4<T>));
-      const T j0 = w.x, s3 = w.y, vv = w.z;
-      cfma<T>(acc[0][m], v[m], j0);
-      cfma<T>(acc[1][m], v[m], j0 * R);
-      cfma<T>(acc[2][m], v[m], j0 * ar);
-      cfma<T>(acc[3][m], v[m], s3);
-      cfma<T>(acc[4][m], v[m], vv * i4);
-      cfma<T>(acc[5][m], v[m], vv);
+      const int sx = sgn_idx(t + TX * m, N);
+      mm[m] = sx * sx + sy * sy + sz * sz;
+    }
+  }
+  cx<T> acc[6][EX];
+  cx<T> b0[EX], b1[EX];
+#pragma unroll
+  for (int m = 0; m < EX; ++m) b0[m] = A.ld<cx<T>>(xa.vo, m * xa.mstride);
+#pragma unroll
+  for (int i = 0; i < kMaxSpecies; ++i) {
+    if (i < S) {  // uniform
+      cx<T>* cur = (i & 1) ? b1 : b0;
+      cx<T>* nxt = (i & 1) ? b0 : b1;
+      if (i + 1 < S) {
+#pragma unroll
+        for (int m = 0; m < EX; ++m) nxt[m] = A.ld<cx<T>>(xa.vo, (uint32_t)(i + 1) * fbytes + m * xa.mstride);
+      }
+      fft_pencil<T, N, EX, true>(cur, t, tw, lp);
+      const T R = (T)a.R[i], ar = (T)a.area[i], i4 = (T)a.inv4piR[i];
+#pragma unroll
+      for (int m = 0; m < EX; ++m) {
+        T j0, s3, vv;
+        hs_weights<T>(a, hs, S, i, mm[m], j0, s3, vv);
+        if (i == 0) {
+          acc[0][m] = cscale<T>(cur[m], j0);
+          acc[1][m] = cscale<T>(cur[m], j0 * R);
+          acc[2][m] = cscale<T>(cur[m], j0 * ar);
+          acc[3][m] = cscale<T>(cur[m], s3);
+          acc[4][m] = cscale<T>(cur[m], vv * i4);
+          acc[5][m] = cscale<T>(cur[m], vv);
+        } else {
+          cfma<T>(acc[0][m], cur[m], j0);
+          cfma<T>(acc[1][m], cur[m], j0 * R);
+          cfma<T>(acc[2][m], cur[m], j0 * ar);
+          cfma<T>(acc[3][m], cur[m], s3);
+          cfma<T>(acc[4][m], cur[m], vv * i4);
+          cfma<T>(acc[5][m], cur[m], vv);
+        }
+      }
     }
   }
   const T sc = (T)a.inv_n3;
   // scalar weighted densities n0..n3
-#pragma unroll 1
+#pragma unroll
   for (int o = 0; o < 4; ++o) {
     cx<T> v[EX];
 #pragma unroll
-    for (int m = 0; m < EX; ++m) {
-      cx<T> s0;
-      switch (o) {  // o is uniform: a scalar branch, no indexed registers
-        case 0: s0 = acc[0][m]; break;
-        case 1: s0 = acc[1][m]; break;
-        case 2: s0 = acc[2][m]; break;
-        default: s0 = acc[3][m]; break;
-      }
-      v[m] = cscale<T>(s0, sc);
-    }
+    for (int m = 0; m < EX; ++m) v[m] = cscale<T>(acc[o][m], sc);
     fft_pencil<T, N, EX, false>(v, t, tw, lp);
 #pragma unroll
-    for (int m = 0; m < EX; ++m) B.st<cx<T>>(v[m], eo[m], (uint32_t)o * fbytes);
+    for (int m = 0; m < EX; ++m) B.st<cx<T>>(v[m], xa.vo, (uint32_t)o * fbytes + m * xa.mstride);
   }
   // vector weighted densities: n1v_c = +i khat_c V1, n2v_c = +i khat_c V2
 #pragma unroll
   for (int b = 0; b < 2; ++b) {
-#pragma unroll 1
+#pragma unroll
     for (int c = 0; c < 3; ++c) {
       cx<T> v[EX];
 #pragma unroll
-      for (int m = 0; m < EX; ++m) {
-        const T u = (c == 0 ? ks.ux[m] : c == 1 ? ks.uy[m] : ks.uz[m]) * sc;
-        v[m] = cscale<T>(cmuli<T>(acc[4 + b][m]), u);
-      }
+      for (int m = 0; m < EX; ++m)
+        v[m] = cscale<T>(cmuli<T>(acc[4 + b][m]), khat<T, N>(c, t + TX * m, pc.ky, pc.kz, mm[m]) * sc);
       fft_pencil<T, N, EX, false>(v, t, tw, lp);
 #pragma unroll
-      for (int m = 0; m < EX; ++m) B.st<cx<T>>(v[m], eo[m], (uint32_t)(4 + 3 * b + c) * fbytes);
+      for (int m = 0; m < EX; ++m) B.st<cx<T>>(v[m], xa.vo, (uint32_t)(4 + 3 * b + c) * fbytes + m * xa.mstride);
     }
   }
 }
@@ -716,7 +811,10 @@ __global__ void __launch_bounds__((PX * (N / EX)))
 //   mu^_i = j0_i (F0 + R_i F1 + 4 pi R_i^2 F2) + w3_i F3
 //           - i V2_i (D1 / (4 pi R_i) + D2) + sum_j G_ij rho^_j,
 // with F_a the derivative spectra and D_b = khat . (vector derivative b).
-// Output species are processed in chunks of CH (<= 4).
+// For S <= CH <= 4: the ten derivative pencils and then the S density pencils
+// stream through two register buffers (the next pencil, and the next pair-
+// table row, are in flight during each transform); the derivative spectra
+// fold into the CH outputs before the density phase starts.
 template <typename T, int N, int CH, int EX = Geo<T, N>::EX, int PX = Geo<T, N>::PX>
 __global__ void __launch_bounds__((PX * (N / EX)))
     k_xback(const EvalArgs* __restrict__ args) {
@@ -732,7 +830,166 @@ __global__ void __launch_bounds__((PX * (N / EX)))
   const XPencil<N, PX> pc(tile, p);
   const LdsPencil<T> lp{xch + p, PX};
   const int S = a.S;
-  const Buf hs = make_buf(a.hs_tab, table_m<T, N>(0) * S * sizeof(v4<T>));
+  const bool hs_on = a.hs_on, pair_on = a.pair_on;
+  const Buf hs = make_buf(a.hs_tab, sizeof(T) == 8 ? table_m<T, N>(0) * S * sizeof(v4<T>) : 0);
+  const Buf pt = make_buf(a.pair_tab, pair_on ? table_m<T, N>(0) * S * a.Sp * sizeof(T) : 0);
+  const Buf A = make_buf(a.specA, spec_bytes<T>(a, S));
+  const Buf B = make_buf(a.specB, hs_on ? spec_bytes<T>(a, kFields) : 0);
+  const Buf C = make_buf(a.specC, spec_bytes<T>(a, S));
+  const uint32_t fbytes = __builtin_amdgcn_readfirstlane((uint32_t)(a.fstride * sizeof(cx<T>)));
+  const XAddr<T, N, EX, PX> xa(pc, t);
+  int mm[EX];
+  {
+    const int sy = sgn_idx(pc.ky, N), sz = pc.kz;
+#pragma unroll
+    for (int m = 0; m < EX; ++m) {
+      const int sx = sgn_idx(t + TX * m, N);
+      mm[m] = sx * sx + sy * sy + sz * sz;
+    }
+  }
+  cx<T> out[CH][EX];
+  cx<T> b0[EX], b1[EX];
+  if (hs_on) {
+    cx<T> F[6][EX];
+#pragma unroll
+    for (int m = 0; m < EX; ++m) b0[m] = B.ld<cx<T>>(xa.vo, m * xa.mstride);
+#pragma unroll
+    for (int q = 0; q < kFields; ++q) {
+      cx<T>* cur = (q & 1) ? b1 : b0;
+      cx<T>* nxt = (q & 1) ? b0 : b1;
+      if (q + 1 < kFields) {
+#pragma unroll
+        for (int m = 0; m < EX; ++m) nxt[m] = B.ld<cx<T>>(xa.vo, (uint32_t)(q + 1) * fbytes + m * xa.mstride);
+      }
+      fft_pencil<T, N, EX, true>(cur, t, tw, lp);
+      if (q < 4) {
+#pragma unroll
+        for (int m = 0; m < EX; ++m) F[q][m] = cur[m];
+      } else {
+        const int b = (q - 4) / 3, c = (q - 4) % 3;
+#pragma unroll
+        for (int m = 0; m < EX; ++m) {
+          const T u = khat<T, N>(c, t + TX * m, pc.ky, pc.kz, mm[m]);
+          if (c == 0) F[4 + b][m] = cscale<T>(cur[m], u);
+          else cfma<T>(F[4 + b][m], cur[m], u);
+        }
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < CH; ++c) {
+      const int i = c < S ? c : 0;
+      const T R = (T)a.R[i], ar = (T)a.area[i], i4 = (T)a.inv4piR[i];
+#pragma unroll
+      for (int m = 0; m < EX; ++m) {
+        T j0, w3, v2;
+        hs_weights<T>(a, hs, S, i, mm[m], j0, w3, v2);
+        cx<T> s0 = F[0][m];
+        cfma<T>(s0, F[1][m], R);
+        cfma<T>(s0, F[2][m], ar);
+        cx<T> u = cscale<T>(s0, j0);
+        cfma<T>(u, F[3][m], w3);
+        cx<T> dv = F[5][m];
+        cfma<T>(dv, F[4][m], i4);
+        cfma<T>(u, cmulmi<T>(dv), v2);
+        out[c][m] = u;
+      }
+    }
+  } else {
+#pragma unroll
+    for (int c = 0; c < CH; ++c)
+#pragma unroll
+      for (int m = 0; m < EX; ++m) out[c][m] = mk<T>((T)0, (T)0);
+  }
+  if (pair_on) {  // the density stream starts in b0
+#pragma unroll
+    for (int m = 0; m < EX; ++m) b0[m] = A.ld<cx<T>>(xa.vo, m * xa.mstride);
+  }
+  if (pair_on && sizeof(T) == 8) {
+    // FP64: pair-table rows gathered after each transform (two buffers of
+    // double rows would not fit the register budget)
+#pragma unroll
+    for (int j = 0; j < CH; ++j) {
+      if (j < S) {  // uniform
+        cx<T>* cur = (j & 1) ? b1 : b0;
+        cx<T>* nxt = (j & 1) ? b0 : b1;
+        if (j + 1 < S) {
+#pragma unroll
+          for (int m = 0; m < EX; ++m) nxt[m] = A.ld<cx<T>>(xa.vo, (uint32_t)(j + 1) * fbytes + m * xa.mstride);
+        }
+        fft_pencil<T, N, EX, true>(cur, t, tw, lp);
+#pragma unroll
+        for (int m = 0; m < EX; ++m) {
+          const v4<T> g = pt.ld<v4<T>>((uint32_t)((mm[m] * S + j) * a.Sp) * (uint32_t)sizeof(T));
+          cfma<T>(out[0][m], cur[m], g.x);
+          if constexpr (CH > 1) cfma<T>(out[1][m], cur[m], g.y);
+          if constexpr (CH > 2) cfma<T>(out[2][m], cur[m], g.z);
+          if constexpr (CH > 3) cfma<T>(out[3][m], cur[m], g.w);
+        }
+      }
+    }
+  } else if (pair_on) {
+    // G_{0..3, j} of row [m][j][.]: one gather per element, prefetched with the pencil
+    v4<T> g0[EX], g1[EX];
+#pragma unroll
+    for (int m = 0; m < EX; ++m) g0[m] = pt.ld<v4<T>>((uint32_t)(mm[m] * S * a.Sp) * (uint32_t)sizeof(T));
+#pragma unroll
+    for (int j = 0; j < CH; ++j) {
+      if (j < S) {  // uniform
+        cx<T>* cur = (j & 1) ? b1 : b0;
+        cx<T>* nxt = (j & 1) ? b0 : b1;
+        v4<T>* gc = (j & 1) ? g1 : g0;
+        v4<T>* gn = (j & 1) ? g0 : g1;
+        if (j + 1 < S) {
+#pragma unroll
+          for (int m = 0; m < EX; ++m) nxt[m] = A.ld<cx<T>>(xa.vo, (uint32_t)(j + 1) * fbytes + m * xa.mstride);
+#pragma unroll
+          for (int m = 0; m < EX; ++m)
+            gn[m] = pt.ld<v4<T>>((uint32_t)((mm[m] * S + j + 1) * a.Sp) * (uint32_t)sizeof(T));
+        }
+        fft_pencil<T, N, EX, true>(cur, t, tw, lp);
+#pragma unroll
+        for (int m = 0; m < EX; ++m) {
+          cfma<T>(out[0][m], cur[m], gc[m].x);
+          if constexpr (CH > 1) cfma<T>(out[1][m], cur[m], gc[m].y);
+          if constexpr (CH > 2) cfma<T>(out[2][m], cur[m], gc[m].z);
+          if constexpr (CH > 3) cfma<T>(out[3][m], cur[m], gc[m].w);
+        }
+      }
+    }
+  }
+  const T sc = (T)a.inv_n3;
+#pragma unroll
+  for (int c = 0; c < CH; ++c) {
+    if (c < S) {  // uniform
+      cx<T> v[EX];
+#pragma unroll
+      for (int m = 0; m < EX; ++m) v[m] = cscale<T>(out[c][m], sc);
+      fft_pencil<T, N, EX, false>(v, t, tw, lp);
+#pragma unroll
+      for (int m = 0; m < EX; ++m) C.st<cx<T>>(v[m], xa.vo, (uint32_t)c * fbytes + m * xa.mstride);
+    }
+  }
+}
+
+// P7 for S > 4 species: the same operator with the outputs in chunks of 4
+// (the derivative spectra stay in registers; each chunk re-streams the
+// density pencils).
+template <typename T, int N, int CH, int EX = Geo<T, N>::EX, int PX = Geo<T, N>::PX>
+__global__ void __launch_bounds__((PX * (N / EX)))
+    k_xback_chunked(const EvalArgs* __restrict__ args) {
+  static_assert(CH >= 1 && CH <= 4, "output chunk");
+  constexpr int TX = N / EX;
+  __shared__ cx<T> tw[N];
+  __shared__ cx<T> xch[PX * N];
+  int tile;
+  const EvalArgs& a = args[inst_of(x_tiles<N, PX>(), tile)];
+  init_twiddles<T, N>(tw);
+  __syncthreads();
+  const int p = threadIdx.x % PX, t = threadIdx.x / PX;
+  const XPencil<N, PX> pc(tile, p);
+  const LdsPencil<T> lp{xch + p, PX};
+  const int S = a.S;
+  const Buf hs = make_buf(a.hs_tab, sizeof(T) == 8 ? table_m<T, N>(0) * S * sizeof(v4<T>) : 0);
   const Buf pt = make_buf(a.pair_tab, a.pair_on ? table_m<T, N>(0) * S * a.Sp * sizeof(T) : 0);
   const Buf A = make_buf(a.specA, spec_bytes<T>(a, S));
   const Buf B = make_buf(a.specB, a.hs_on ? spec_bytes<T>(a, kFields) : 0);
@@ -814,15 +1071,16 @@ __global__ void __launch_bounds__((PX * (N / EX)))
         for (int m = 0; m < EX; ++m) {
           cx<T> u = out[c][m];
           if (a.hs_on) {
-            const v4<T> w = hs.ld<v4<T>>((uint32_t)(ks.mm[m] * S + i) * (uint32_t)sizeof(v4<T>));
+            T j0, w3, v2;
+            hs_weights<T>(a, hs, S, i, ks.mm[m], j0, w3, v2);
             cx<T> sc0 = F[0][m];
             cfma<T>(sc0, F[1][m], R);
             cfma<T>(sc0, F[2][m], ar);
-            cfma<T>(u, sc0, w.x);
-            cfma<T>(u, F[3][m], w.y);
+            cfma<T>(u, sc0, j0);
+            cfma<T>(u, F[3][m], w3);
             cx<T> dv = F[5][m];
             cfma<T>(dv, F[4][m], i4);
-            cfma<T>(u, cmulmi<T>(dv), w.z);
+            cfma<T>(u, cmulmi<T>(dv), v2);
           }
           v[m] = cscale<T>(u, sc);
         }

@@ -24,6 +24,7 @@ struct EvalArgs {
   int32_t pad0;
   int64_t fstride;    // complex elements per spectral field (n*n*(n/2) + n*n)
   double inv_n3;      // 1 / n^3
+  double kscale;      // 2 pi / L: |k| = kscale * sqrt(jx^2 + jy^2 + jz^2)
   double R[kMaxSpecies];
   double area[kMaxSpecies];     // 4 pi R^2
   double inv4piR[kMaxSpecies];  // 1 / (4 pi R)
@@ -35,6 +36,7 @@ struct EvalArgs {
   void* specB;        // 10 spectral fields (weighted densities, then derivatives)
   void* specC;        // S spectral fields (chemical potentials)
   const void* hs_tab;    // [M][S][4]: j0(kR), 4 pi R^3 j1(kR)/(kR), 4 pi R^2 j1(kR), 0
+                         // (FP64 path only; the FP32 path evaluates them in registers)
   const void* pair_tab;  // [M][S][Sp]: entry [m][j][i] = combined pair kernel G_ij
   double* out;        // real output [nreal][n^3] (mu_ex or weighted densities)
   double* slot;       // [S][n^3] exp(-mu) or null
