@@ -318,15 +318,18 @@ template <typename T, int N> struct Launch {
   // maxS: the largest species count among the launch's instances
   static void xback(const EvalArgs* a, int count, int maxS, hipStream_t s) {
     const dim3 g(count * G::tiles_x), b(G::PX * G::TX);
-    // FP64: the streamed kernel does not fit the register file; the chunked
-    // one keeps every spectrum in registers without spilling
-    if (sizeof(T) == 8) maxS = 5;
-    switch (maxS) {
-      case 1: hipLaunchKernelGGL((k_xback<T, N, 1>), g, b, 0, s, a); break;
-      case 2: hipLaunchKernelGGL((k_xback<T, N, 2>), g, b, 0, s, a); break;
-      case 3: hipLaunchKernelGGL((k_xback<T, N, 3>), g, b, 0, s, a); break;
-      case 4: hipLaunchKernelGGL((k_xback<T, N, 4>), g, b, 0, s, a); break;
-      default: hipLaunchKernelGGL((k_xback_chunked<T, N, 4>), g, b, 0, s, a); break;
+    if constexpr (sizeof(T) == 8) {
+      // FP64: the streamed kernel does not fit the register file; the chunked
+      // one keeps every spectrum in registers without spilling
+      hipLaunchKernelGGL((k_xback_chunked<T, N, 4>), g, b, 0, s, a);
+    } else {
+      switch (maxS) {
+        case 1: hipLaunchKernelGGL((k_xback<T, N, 1>), g, b, 0, s, a); break;
+        case 2: hipLaunchKernelGGL((k_xback<T, N, 2>), g, b, 0, s, a); break;
+        case 3: hipLaunchKernelGGL((k_xback<T, N, 3>), g, b, 0, s, a); break;
+        case 4: hipLaunchKernelGGL((k_xback<T, N, 4>), g, b, 0, s, a); break;
+        default: hipLaunchKernelGGL((k_xback_chunked<T, N, 4>), g, b, 0, s, a); break;
+      }
     }
   }
   static void zinv(const EvalArgs* a, int count, int sel, hipStream_t s) {

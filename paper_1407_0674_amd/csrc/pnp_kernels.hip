@@ -106,18 +106,20 @@ struct Buf {
       return __builtin_bit_cast(X, pr);
     }
   }
-  // Stores wider than 64 bits take the whole offset in the lane offset and a
-  // zero scalar offset: the store reads its data registers one instruction
-  // after issue, and the compiler inserts the wait that protects them from an
-  // immediate overwrite only for this form of the instruction (with a
-  // register scalar offset it emits none, and the low half of the stored
-  // data can be replaced by the next value written to those registers).
+  // Stores take the whole offset in the lane offset and a zero scalar
+  // offset: a store wider than 64 bits reads its data registers one
+  // instruction after issue, and the compiler inserts the wait that protects
+  // them from an immediate overwrite only for this form of the instruction
+  // (with a register scalar offset it emits none, and the low half of the
+  // stored data can be replaced by the next value written to those
+  // registers).  Narrow stores follow the same rule because the compiler may
+  // merge adjacent ones into a wide store.
   template <typename X>
   __device__ __forceinline__ void st(X v, uint32_t voff, uint32_t soff = 0) const {
     if constexpr (sizeof(X) == 4) {
-      __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, voff, soff, 0);
+      __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, voff + soff, 0, 0);
     } else if constexpr (sizeof(X) == 8) {
-      __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, voff, soff, 0);
+      __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, voff + soff, 0, 0);
     } else if constexpr (sizeof(X) == 16) {
       __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, v), r, voff + soff, 0, 0);
     } else {
@@ -425,32 +427,48 @@ template <typename T, int N, int EZ = default_ezd<T, N>()> struct GeoD {
   static constexpr int tiles = (N * N) / RDD;
 };
 
-template <typename T, int N, int EZ, bool BAR, int F, class L>
-__device__ __forceinline__ void zd_load(cx<T>* val, int t, const cx<T>* twN, const cx<T>* twH,
-                                        const L& lp, const Buf& B, uint32_t fbytes, uint32_t row) {
-  if constexpr (F < kFields) {
-    using D = GeoD<T, N, EZ>;
-    c2r_pre<T, N, D::TZD, EZ>(val + F * EZ, t, twN, B, F * fbytes, row);
-    fft_pencil<T, N / 2, EZ, false>(val + F * EZ, t, twH, lp);
-    if constexpr (BAR) __builtin_amdgcn_sched_barrier(0);  // keep the next field's loads after this FFT
-    zd_load<T, N, EZ, BAR, F + 1>(val, t, twN, twH, lp, B, fbytes, row);
+// raw loads for the c2r pre-step of one row: X[k] and X[H-k] (X[H] from the
+// Nyquist plane for k = 0) at the lane's elements k = t + TZ m
+template <typename T, int N, int TZ, int EZ>
+__device__ __forceinline__ void c2r_load(cx<T>* xk, cx<T>* xm, int t, const Buf& f, uint32_t soff,
+                                         uint32_t row_id) {
+  constexpr int H = N / 2;
+  constexpr uint32_t cs = sizeof(cx<T>);
+#pragma unroll
+  for (int m = 0; m < EZ; ++m) {
+    const int k = t + TZ * m;
+    xk[m] = f.ld<cx<T>>((row_id * H + k) * cs, soff);
+    xm[m] = f.ld<cx<T>>((k == 0 ? (uint32_t)(N * N * H) + row_id : row_id * H + (H - k)) * cs, soff);
   }
 }
 
-template <typename T, int N, int EZ, bool BAR, int F, class L>
-__device__ __forceinline__ void zd_store(cx<T>* val, int t, const cx<T>* twN, const cx<T>* twH,
-                                         const L& lp, cx<T>* lrow, const Buf& B, uint32_t fbytes,
-                                         uint32_t row) {
-  if constexpr (F < kFields) {
-    using D = GeoD<T, N, EZ>;
-    fft_pencil<T, N / 2, EZ, true>(val + F * EZ, t, twH, lp);
-    r2c_post<T, N, D::TZD, EZ>(val + F * EZ, t, twN, lrow, B, F * fbytes, row);
-    if constexpr (BAR) __builtin_amdgcn_sched_barrier(0);
-    zd_store<T, N, EZ, BAR, F + 1>(val, t, twN, twH, lp, lrow, B, fbytes, row);
+// the c2r pre-step on loaded values (same arithmetic as c2r_pre)
+template <typename T, int N, int TZ, int EZ>
+__device__ __forceinline__ void c2r_combine(cx<T>* v, const cx<T>* xk0, const cx<T>* xm0, int t,
+                                            const cx<T>* twN) {
+#pragma unroll
+  for (int m = 0; m < EZ; ++m) {
+    const int k = t + TZ * m;
+    cx<T> xk = xk0[m], xm = xm0[m];
+    if (k == 0) { xk.y = (T)0; xm.y = (T)0; }
+    const cx<T> cm = cconj<T>(xm);
+    const cx<T> s = cadd<T>(xk, cm);
+    const cx<T> d = csub<T>(xk, cm);
+    v[m] = cadd<T>(s, cmuli<T>(cmulc<T>(d, twN[k])));
   }
 }
 
-template <typename T, int N, int EZD = default_ezd<T, N>(), bool BAR = true>
+// 1 / x in FP64: hardware reciprocal estimate refined by two Newton steps
+// (error within an ulp of the quotient)
+__device__ __forceinline__ double recip_f64(double x) {
+  double y = __builtin_amdgcn_rcp(x);
+  double e = __builtin_fma(-x, y, 1.0);
+  y = __builtin_fma(y, e, y);
+  e = __builtin_fma(-x, y, 1.0);
+  return __builtin_fma(y, e, y);
+}
+
+template <typename T, int N, int EZD = default_ezd<T, N>()>
 __global__ void __launch_bounds__((GeoD<T, N, EZD>::RDD * GeoD<T, N, EZD>::TZD))
     k_zderiv(const EvalArgs* __restrict__ args) {
   using D = GeoD<T, N, EZD>;
@@ -469,9 +487,23 @@ __global__ void __launch_bounds__((GeoD<T, N, EZD>::RDD * GeoD<T, N, EZD>::TZD))
   cx<T>* lrow = xch + r * H;
   const LdsPencil<T, row_in_wave<TZ>()> lp{lrow, 1};
   const Buf B = make_buf(a.specB, spec_bytes<T>(a, kFields));
-  const uint32_t fbytes = (uint32_t)(a.fstride * sizeof(cx<T>));
+  const uint32_t fbytes = __builtin_amdgcn_readfirstlane((uint32_t)(a.fstride * sizeof(cx<T>)));
   cx<T> val[kFields * EZ];
-  zd_load<T, N, EZ, BAR, 0>(val, t, twN, twH, lp, B, fbytes, row);
+  {
+    // the raw values of field q + 1 are in flight while field q is transformed
+    cx<T> k0[EZ], m0[EZ], k1[EZ], m1[EZ];
+    c2r_load<T, N, TZ, EZ>(k0, m0, t, B, 0, row);
+#pragma unroll
+    for (int q = 0; q < kFields; ++q) {
+      cx<T>* kc = (q & 1) ? k1 : k0;
+      cx<T>* mc = (q & 1) ? m1 : m0;
+      cx<T>* kn = (q & 1) ? k0 : k1;
+      cx<T>* mn = (q & 1) ? m0 : m1;
+      if (q + 1 < kFields) c2r_load<T, N, TZ, EZ>(kn, mn, t, B, (uint32_t)(q + 1) * fbytes, row);
+      c2r_combine<T, N, TZ, EZ>(val + q * EZ, kc, mc, t, twN);
+      fft_pencil<T, N / 2, EZ, false>(val + q * EZ, t, twH, lp);
+    }
+  }
   uint32_t bad = 0u, badidx = 0xffffffffu;
   const double inv8pi = 1.0 / (8.0 * kPi), inv12pi = 1.0 / (12.0 * kPi), inv4pi = 1.0 / (4.0 * kPi);
 #pragma unroll
@@ -487,12 +519,15 @@ __global__ void __launch_bounds__((GeoD<T, N, EZD>::RDD * GeoD<T, N, EZD>::TZD))
         bad |= isfinite(n3) ? kStPacking : kStNonFinite;
         badidx = min(badidx, row * N + 2 * (t + TZ * m) + h);
       }
-      const double inv = 1.0 / (1.0 - n3), inv2 = inv * inv, inv3 = inv2 * inv;
+      const double u = 1.0 - n3;
+      const double inv = recip_f64(u), inv2 = inv * inv, inv3 = inv2 * inv;
       const double v12 = a1x * a2x + a1y * a2y + a1z * a2z;
       const double v22 = a2x * a2x + a2y * a2y + a2z * a2z;
       const double c2 = n2 * inv2 * inv4pi;
       double d[kFields];
-      d[0] = -log1p(-n3);
+      // -ln(1 - n3): log of the rounded u plus the first-order correction for
+      // the rounding of u, which equals log1p(-n3) to working precision
+      d[0] = -(log(u) - ((u - 1.0) + n3) * inv);
       d[1] = n2 * inv;
       d[2] = n1 * inv + (n2 * n2 - v22) * inv2 * inv8pi;
       d[3] = n0 * inv + (n1 * n2 - v12) * inv2 + (n2 * n2 * n2 - 3.0 * n2 * v22) * inv3 * inv12pi;
@@ -507,10 +542,15 @@ __global__ void __launch_bounds__((GeoD<T, N, EZD>::RDD * GeoD<T, N, EZD>::TZD))
         if (h) val[q * EZ + m].y = (T)d[q];
         else val[q * EZ + m].x = (T)d[q];
       }
-      if constexpr (BAR) __builtin_amdgcn_sched_barrier(0);  // one grid point at a time
+      __builtin_amdgcn_sched_barrier(0);  // one grid point at a time
     }
   }
-  zd_store<T, N, EZ, BAR, 0>(val, t, twN, twH, lp, lrow, B, fbytes, row);
+#pragma unroll
+  for (int q = 0; q < kFields; ++q) {
+    fft_pencil<T, N / 2, EZ, true>(val + q * EZ, t, twH, lp);
+    r2c_post<T, N, TZ, EZ>(val + q * EZ, t, twN, lrow, B, q * fbytes, row);
+    __builtin_amdgcn_sched_barrier(0);
+  }
   if (bad) raise_status(a.status, bad, badidx);
 }
 
