@@ -1,6 +1,6 @@
 """Throughput of the FFT evaluation of cDFT excess chemical potentials on one GPU.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload cfg3|cfg2]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload cfg3|cfg2|cfg4|cfg5]
 
 A step is one evaluation of beta mu_ex (all nine passes: weighted densities,
 FMT derivatives, back-convolution, electrostatic-correlation and square-well
@@ -15,6 +15,10 @@ evaluation's stream inside the timed region), p50/p99 latency of synchronous
 single evaluations for the mixed path and the plain FP64 path on the same
 GPU, the mixed path's error against the FP64 path per term, and the CPU
 oracle timed on a bounded sample of the same workload.
+
+--workload cfg4 times the 64-instance uneven batch (one batched call per
+step) and cfg5 replays a Poisson request trace against resident sessions;
+each prints its own JSON line.
 """
 import argparse
 import json
@@ -148,6 +152,184 @@ def traffic_from_profile(kernel, launches_per_step):
     return None if k is None else k["bytes_per_launch"]
 
 
+def bench_batch(ev, steps, warmup):
+    """The 64-instance uneven mix in one batched call per step (mixed
+    precision), against the same instances evaluated one call at a time and
+    against the FP64 batch."""
+    import torch
+    import pnp_inputs as P
+    inst = P.config4()
+    probs = [p for p, _ in inst]
+    rhos = [torch.from_numpy(r).to("cuda:0").contiguous() for _, r in inst]
+    outs = [torch.empty_like(r) for r in rhos]
+    slots = [torch.empty_like(r) for r in rhos]
+    wss = [torch.empty(ev.workspace_bytes(p), dtype=torch.uint8, device="cuda:0") for p in probs]
+    pts = sum(p.n ** 3 * p.S for p in probs)
+    bytes_model = sum((60 * p.S + 32 * F) * p.n ** 3 for p in probs)
+
+    probs64 = [p.with_(precision=0) for p in probs]
+    wss64 = [torch.empty(ev.workspace_bytes(p), dtype=torch.uint8, device="cuda:0") for p in probs64]
+
+    def run_batch(precision=None):
+        ps, ws = (probs, wss) if precision is None else (probs64, wss64)
+        _, _, st = ev.batch(ps, rhos, outs=outs, slots=slots, workspaces=ws)
+        assert all(x == 0 for x in st), st
+
+    for _ in range(warmup):
+        run_batch()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        run_batch()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    # one call per instance (each waits for its status, as a caller without the batch call would)
+    for p, r, o, s_, w in zip(probs, rhos, outs, slots, wss):
+        ev.mu_ex(p, r, out=o, slot=s_, workspace=w)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(max(1, steps // 2)):
+        for p, r, o, s_, w in zip(probs, rhos, outs, slots, wss):
+            ev.mu_ex(p, r, out=o, slot=s_, workspace=w)
+    torch.cuda.synchronize()
+    ms_alone = (time.perf_counter() - t0) * 1e3 / max(1, steps // 2)
+    run_batch(0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(max(1, steps // 2)):
+        run_batch(0)
+    torch.cuda.synchronize()
+    ms64 = (time.perf_counter() - t0) * 1e3 / max(1, steps // 2)
+    hist = {}
+    for p in probs:
+        hist[p.n] = hist.get(p.n, 0) + 1
+    return {
+        "metric": "mu_ex grid-pts*species/s, 64-instance uneven batch", "value": pts / (ms / 1e3),
+        "unit": "grid-pt*species/s", "n_gpus": 1, "steps": steps, "warmup": warmup, "ms_per_step": ms,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32 FFT/weights + f64 derivatives/accumulation", "data": "synthetic (seeded)",
+        "config": {"workload": "64 instances, n in {32,48,64,96,128}, S in {2,3,4}, T 250-350 K, HS+EC+SW, mixed",
+                   "sizes": hist, "grid_pt_species": pts},
+        "hbm": {"model_bytes_per_step": bytes_model, "GBps": bytes_model / 1e9 / (ms / 1e3),
+                "pct_peak": 100.0 * bytes_model / 1e9 / (ms / 1e3) / HBM_PEAK_GBS,
+                "note": "instances up to 128^3 partly stay in the 256 MB Infinity Cache between passes"},
+        "one_call_per_instance_ms": ms_alone, "speedup_vs_one_call_per_instance": ms_alone / ms,
+        "fp64_batch_ms": ms64, "speedup_vs_fp64": ms64 / ms,
+    }
+
+
+def serve_trace(ev, reqs, precision, budget, max_active, work_cap=None):
+    """Replay a request trace against a session pool: requests are admitted in
+    arrival order when their session fits the budget (at most max_active at a
+    time); every loop runs one step of the oldest active sessions whose
+    grid-pt*species sum stays within work_cap (at least one; all when None),
+    and a request completes after its iterations.  Returns per-request
+    latency (arrival to completion, ms), the makespan and the evaluated
+    grid-pt*species."""
+    import collections
+    import torch
+    from paper_1407_0674_amd import Pool
+    pool = Pool(ev, budget)
+    pending = collections.deque(reqs)
+    active = {}
+    lat = []
+    work = 0
+    t0 = time.perf_counter()
+    last_note = t0
+    while pending or active:
+        now = time.perf_counter() - t0
+        while pending and pending[0].arrival <= now and len(active) < max_active:
+            r = pending[0]
+            prob, prof = r.build_profile()
+            if precision is not None:
+                prob = prob.with_(precision=precision)
+            n = prob.n
+            rho0 = torch.from_numpy(prof).to("cuda:0")[:, :, None, :].expand(prob.S, n, n, n).contiguous()
+            sid = pool.open(prob, rho0)
+            if sid is None:
+                break  # the head of the queue waits for room
+            pending.popleft()
+            active[sid] = [r, r.iterations, prob]
+        if not active:
+            time.sleep(max(0.0, pending[0].arrival - (time.perf_counter() - t0)))
+            continue
+        ids = []
+        acc = 0
+        for sid, (r, left, prob) in active.items():  # admission order
+            w = prob.n ** 3 * prob.S
+            if ids and work_cap is not None and acc + w > work_cap:
+                break
+            ids.append(sid)
+            acc += w
+        st = pool.step(ids)
+        torch.cuda.synchronize()
+        done_t = time.perf_counter() - t0
+        for sid, s_ in zip(ids, st):
+            r, left, prob = active[sid]
+            if s_ != 0:
+                raise RuntimeError(f"request {r.rid}: status {s_}")
+            work += prob.n ** 3 * prob.S
+            left -= 1
+            if left == 0:
+                lat.append((done_t - r.arrival) * 1e3)
+                pool.close_session(sid)
+                del active[sid]
+            else:
+                active[sid][1] = left
+        if time.perf_counter() - last_note > 5.0:
+            last_note = time.perf_counter()
+            print(json.dumps({"progress": "serving", "done": len(lat), "active": len(active),
+                              "pending": len(pending)}), file=sys.stderr, flush=True)
+    makespan = time.perf_counter() - t0
+    torch.cuda.synchronize()
+    pool.close()
+    return lat, makespan, work
+
+
+def bench_serve(ev, duration, rate):
+    """Config-5 serving: Poisson arrivals, n up to 192, 5 steps per request on
+    resident state, mixed precision with all active sessions stepped together
+    under a 32 GiB budget; baseline: the same trace served one request at a
+    time by the plain FP64 path."""
+    import pnp_inputs as P
+    reqs = P.config5(duration=duration, rate=rate)
+    budget = 32 << 30
+    cap = 2 * 192 ** 3 * 4  # grid-pt*species per step: two of the largest requests
+    # untimed warm-up on a prefix of the trace (loads every kernel the trace uses)
+    sizes = {}
+    for r in reqs:
+        sizes.setdefault((r.problem().n, r.problem().S), r)
+    warm = list(sizes.values())
+    for prec in (None, 0):
+        serve_trace(ev, [P.Request(k, 0.0, r.seed, r.n_choices, r.precision, 1) for k, r in enumerate(warm)],
+                    prec, budget, 1 << 30)
+    lat, span, work = serve_trace(ev, reqs, None, budget, 1 << 30, work_cap=cap)
+    lat_all, span_all, _ = serve_trace(ev, reqs, None, budget, 1 << 30)
+    lat1, span1, _ = serve_trace(ev, reqs, None, budget, 1)
+    lat64, span64, work64 = serve_trace(ev, reqs, 0, budget, 1)
+    return {
+        "metric": "served requests: p50/p99 latency (arrival to done) and grid-pts*species/s",
+        "value": work / span, "unit": "grid-pt*species/s", "n_gpus": 1, "steps": len(reqs), "warmup": 0,
+        "ms_per_step": span * 1e3 / max(1, len(reqs)), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32 FFT/weights + f64 derivatives/accumulation",
+        "data": "synthetic (seeded Poisson trace)",
+        "config": {"workload": f"Poisson {rate:g} req/s for {duration:g} s, n in {{48,64,96,128,192}}, "
+                               "S in {2,3,4}, 5 steps per request, HS+EC+SW, mixed, budget 32 GiB",
+                   "requests": len(reqs)},
+        "latency_ms": {"p50": percentile(lat, 50), "p99": percentile(lat, 99), "max": max(lat)},
+        "throughput_req_s": len(lat) / span,
+        "policy": f"admission in arrival order under the budget; each step takes the oldest active sessions "
+                  f"up to {cap} grid-pt*species",
+        "mixed_all_active_each_step": {"latency_ms": {"p50": percentile(lat_all, 50), "p99": percentile(lat_all, 99)},
+                                       "throughput_req_s": len(lat_all) / span_all},
+        "mixed_one_at_a_time": {"latency_ms": {"p50": percentile(lat1, 50), "p99": percentile(lat1, 99)},
+                                "throughput_req_s": len(lat1) / span1},
+        "fp64_one_at_a_time": {"latency_ms": {"p50": percentile(lat64, 50), "p99": percentile(lat64, 99),
+                                              "max": max(lat64)},
+                               "throughput_req_s": len(lat64) / span64, "value": work64 / span64},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -157,6 +339,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--latency-reps", type=int, default=20)
+    ap.add_argument("--duration", type=float, default=10.0, help="cfg5: trace length [s]")
+    ap.add_argument("--rate", type=float, default=200.0, help="cfg5: arrivals per second")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run the copy kernel (reference for the memory counters)")
     args = ap.parse_args()
@@ -173,6 +357,14 @@ def main():
     ev = Evaluator(0)
     if args.calibrate_copy:
         print(json.dumps({"copy_kernel": copy_bandwidth(ev, 1.0, 5)}), flush=True)
+        ev.close()
+        return
+    if args.workload == "cfg4":
+        print(json.dumps(bench_batch(ev, args.steps, args.warmup)), flush=True)
+        ev.close()
+        return
+    if args.workload == "cfg5":
+        print(json.dumps(bench_serve(ev, args.duration, args.rate)), flush=True)
         ev.close()
         return
     prob, rho, desc = workload(args.workload)

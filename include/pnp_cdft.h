@@ -188,9 +188,12 @@ pnp_status pnp_read_status(pnp_ctx ctx, const void* workspace, void* stream);
 /*
  * Consumer stub of the PNP loop (not part of the evaluation): relaxes every
  * density toward the equilibrium of its current excess chemical potential,
- *   rho_i <- (1 - lambda) rho_i + lambda rho_i^bulk exp(beta mu_b,i - beta mu_ex,i),
+ *   rho_i <- (1 - lambda) rho_i + lambda rho_i^bulk exp(g_i),
+ *   g_i = beta mu_b,i - beta mu_ex,i, limited to [-clip, clip] when clip > 0,
  * where beta mu_b,i = mu_bulk[i].  Sec. 3.2 uses relaxation
- * rho <- lambda2 rho_new + (1 - lambda2) rho_old.
+ * rho <- lambda2 rho_new + (1 - lambda2) rho_old.  With clip > 0 every
+ * density stays within max(rho_i, e^clip rho_i^bulk), which keeps a strongly
+ * attractive state from running past close packing.
  *   rho      device, float64 [S][N], updated in place
  *   mu_ex    device, float64 [S][N]
  *   mu_bulk  host, S values [k_B T]
@@ -198,7 +201,77 @@ pnp_status pnp_read_status(pnp_ctx ctx, const void* workspace, void* stream);
 pnp_status pnp_relax_densities(pnp_ctx ctx, const pnp_grid* grid, int32_t S,
                                const pnp_species* species, double* rho,
                                const double* mu_ex, const double* mu_bulk, double lambda,
-                               void* stream);
+                               double clip, void* stream);
+
+/*
+ * beta mu_ex of the uniform bulk state (host arithmetic, no device work):
+ * every rho_i(r) = rho_bulk_i.  HS: the Rosenfeld free-energy derivatives
+ * at the bulk weighted densities, contracted with the k = 0 weights
+ * (Sec. 2.3.1); EC: mu_el_bulk (Sec. 2.3.4, no density deviation); SW:
+ * sw_prefactor * beta * sum_j rho_bulk_j u_ij(k = 0) (Sec. 2.3.2).  Equals
+ * what pnp_cdft_mu_ex returns for uniform bulk densities, to rounding.
+ *   ctx may be NULL (no device is used; errors are then not recorded)
+ *   mu  host, S values [k_B T]
+ * Errors: PNP_E_ARG, PNP_E_PACKING (bulk packing fraction >= 1).
+ */
+pnp_status pnp_bulk_mu_ex(pnp_ctx ctx, int32_t S, const pnp_species* species, double T,
+                          const pnp_params* params, double* mu);
+
+/*
+ * Serving: resident sessions in one caller-owned device pool.
+ *
+ * A session holds a PNP-style state on the device: densities rho_i(r)
+ * [S][N], their beta mu_ex [S][N], Slotboom factors [S][N] and the
+ * evaluation workspace, sub-allocated first-fit from the pool's range
+ * (256-byte aligned; freed blocks coalesce).  A step evaluates beta mu_ex
+ * of every listed session in shared launches (pnp_batch_mu_ex) and then
+ * relaxes each session's densities toward the equilibrium of the new
+ * mu_ex (pnp_relax_densities with the session's lambda and bulk mu).
+ * Pools are not thread-safe; closing a session does not wait for work in
+ * flight on it, so order any reuse of its memory after that work (same
+ * stream, or synchronise).
+ */
+typedef struct pnp_pool_s* pnp_pool;
+
+/* Device bytes one session of this shape takes from a pool (densities,
+ * mu_ex, Slotboom factors, workspace). */
+pnp_status pnp_session_bytes(pnp_ctx ctx, const pnp_grid* grid, int32_t S, const pnp_params* params,
+                             size_t* bytes);
+
+/* A pool over [arena, arena + arena_bytes): device memory owned by the
+ * caller, 256-byte aligned, valid until pnp_pool_destroy. */
+pnp_status pnp_pool_create(pnp_ctx ctx, void* arena, size_t arena_bytes, pnp_pool* out);
+void pnp_pool_destroy(pnp_pool pool);
+
+/* Bytes held by open sessions, the largest free block, and the number of
+ * open sessions. */
+pnp_status pnp_pool_usage(pnp_pool pool, size_t* used, size_t* largest_free, int32_t* sessions);
+
+/*
+ * Admit a session: copies rho0 (device, float64 [S][N]) into the pool on
+ * `stream`.  mu_bulk: host, S values of beta mu_ex in bulk for the update,
+ * or NULL for pnp_bulk_mu_ex.  lambda in [0, 1] and clip: the update's
+ * parameters (pnp_relax_densities).  params->per_term must be 0 and flags
+ * are ignored.  PNP_E_BUDGET when no free block is large enough (nothing
+ * is allocated).
+ */
+pnp_status pnp_session_open(pnp_pool pool, const pnp_grid* grid, int32_t S, const pnp_species* species,
+                            double T, const pnp_params* params, const double* rho0,
+                            const double* mu_bulk, double lambda, double clip, void* stream,
+                            int64_t* id);
+
+/* One step of `count` sessions; status[k] receives session k's pnp_status
+ * (its densities are not updated when it is not PNP_OK). */
+pnp_status pnp_session_step(pnp_pool pool, int32_t count, const int64_t* ids, int32_t* status,
+                            void* stream);
+
+/* Device pointers of a session's arrays (valid until it closes) and the
+ * number of completed steps; any output pointer may be NULL. */
+pnp_status pnp_session_view(pnp_pool pool, int64_t id, double** rho, double** mu_ex,
+                            double** slotboom, int64_t* steps);
+
+/* Release a session's block to the pool. */
+pnp_status pnp_session_close(pnp_pool pool, int64_t id);
 
 /*
  * Test hook: 3D real-to-complex DFT of `count` fields through the same

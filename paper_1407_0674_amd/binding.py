@@ -26,7 +26,8 @@ EXPORTED = [
     "pnp_create", "pnp_destroy", "pnp_last_error", "pnp_supported_size", "pnp_workspace_bytes",
     "pnp_cdft_mu_ex", "pnp_weighted_densities", "pnp_batch_mu_ex", "pnp_read_status",
     "pnp_relax_densities", "pnp_debug_rfft3", "pnp_debug_copy", "pnp_profile_enable",
-    "pnp_profile_read",
+    "pnp_profile_read", "pnp_bulk_mu_ex", "pnp_session_bytes", "pnp_pool_create", "pnp_pool_destroy",
+    "pnp_pool_usage", "pnp_session_open", "pnp_session_step", "pnp_session_view", "pnp_session_close",
 ]
 
 PASS_NAMES = ["tables", "z_fwd_rho", "y_fwd_rho", "x_fwd_weights", "y_inv_n", "z_deriv",
@@ -100,16 +101,34 @@ def load_library():
     lib.pnp_read_status.argtypes = [P, P, P]
     lib.pnp_relax_densities.argtypes = [P, ctypes.POINTER(Grid), ctypes.c_int32,
                                         ctypes.POINTER(SpeciesC), P, P,
-                                        ctypes.POINTER(ctypes.c_double), ctypes.c_double, P]
+                                        ctypes.POINTER(ctypes.c_double), ctypes.c_double, ctypes.c_double, P]
     lib.pnp_debug_rfft3.argtypes = [P, ctypes.POINTER(Grid), ctypes.c_int32, ctypes.c_int32,
                                     ctypes.c_int32, P, P, P, ctypes.c_size_t, P]
     lib.pnp_debug_copy.argtypes = [P, P, P, ctypes.c_size_t, P]
+    lib.pnp_bulk_mu_ex.argtypes = [P, ctypes.c_int32, ctypes.POINTER(SpeciesC), ctypes.c_double,
+                                   ctypes.POINTER(ParamsC), ctypes.POINTER(ctypes.c_double)]
+    lib.pnp_session_bytes.argtypes = [P, ctypes.POINTER(Grid), ctypes.c_int32, ctypes.POINTER(ParamsC),
+                                      ctypes.POINTER(ctypes.c_size_t)]
+    lib.pnp_pool_create.argtypes = [P, P, ctypes.c_size_t, ctypes.POINTER(P)]
+    lib.pnp_pool_destroy.argtypes = [P]
+    lib.pnp_pool_destroy.restype = None
+    lib.pnp_pool_usage.argtypes = [P, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t),
+                                   ctypes.POINTER(ctypes.c_int32)]
+    lib.pnp_session_open.argtypes = [P, ctypes.POINTER(Grid), ctypes.c_int32, ctypes.POINTER(SpeciesC),
+                                     ctypes.c_double, ctypes.POINTER(ParamsC), P,
+                                     ctypes.POINTER(ctypes.c_double), ctypes.c_double, ctypes.c_double, P,
+                                     ctypes.POINTER(ctypes.c_int64)]
+    lib.pnp_session_step.argtypes = [P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64),
+                                     ctypes.POINTER(ctypes.c_int32), P]
+    lib.pnp_session_view.argtypes = [P, ctypes.c_int64, ctypes.POINTER(P), ctypes.POINTER(P),
+                                     ctypes.POINTER(P), ctypes.POINTER(ctypes.c_int64)]
+    lib.pnp_session_close.argtypes = [P, ctypes.c_int64]
     lib.pnp_profile_enable.argtypes = [P, ctypes.c_int32]
     lib.pnp_profile_read.argtypes = [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32),
                                      ctypes.c_int32, ctypes.c_int32]
     for name in EXPORTED:
         f = getattr(lib, name)
-        if name not in ("pnp_destroy", "pnp_last_error"):
+        if name not in ("pnp_destroy", "pnp_last_error", "pnp_pool_destroy"):
             f.restype = ctypes.c_int
     _LIB = lib
     return lib
@@ -283,12 +302,12 @@ class Evaluator:
         ws = self._ws["default"] if workspace is None else workspace
         self._check(self.lib.pnp_read_status(self.ctx, ctypes.c_void_p(ws.data_ptr()), self._stream()))
 
-    def relax(self, problem, rho, mu, mu_bulk, lam=0.1):
+    def relax(self, problem, rho, mu, mu_bulk, lam=0.1, clip=0.0):
         m = _Marshal(problem)
         mb = (ctypes.c_double * m.S)(*[float(x) for x in mu_bulk])
         self._check(self.lib.pnp_relax_densities(self.ctx, ctypes.byref(m.grid), m.S, m.species,
                                                  self._dev(rho, "rho"), self._dev(mu, "mu"), mb,
-                                                 float(lam), self._stream()))
+                                                 float(lam), float(clip), self._stream()))
 
     def _fft_workspace(self, n, count, precision):
         g = Grid(n, n, n, 1.0)
@@ -338,3 +357,100 @@ class Evaluator:
         self._check(self.lib.pnp_debug_copy(self.ctx, ctypes.c_void_p(src.data_ptr()),
                                             ctypes.c_void_p(dst.data_ptr()), ctypes.c_size_t(nbytes),
                                             self._stream()))
+
+
+def bulk_mu_ex(problem):
+    """beta mu_ex of the uniform bulk state of `problem` (host arithmetic in
+    the library; no device needed).  Returns a list of S floats."""
+    lib = load_library()
+    m = _Marshal(problem)
+    out = (ctypes.c_double * m.S)()
+    st = lib.pnp_bulk_mu_ex(None, m.S, m.species, m.T, ctypes.byref(m.params), out)
+    if st != 0:
+        raise PnpError(st, "pnp_bulk_mu_ex failed")
+    return [float(x) for x in out]
+
+
+class Pool:
+    """Resident sessions in one device pool (see pnp_session_* in the header).
+
+    The pool's memory is one uint8 CUDA tensor of `nbytes` owned by this
+    object; sessions are sub-allocated from it by the library."""
+
+    def __init__(self, ev: "Evaluator", nbytes: int):
+        torch = _torch()
+        self.ev = ev
+        self.lib = ev.lib
+        self.arena = torch.empty(int(nbytes), dtype=torch.uint8, device=f"cuda:{ev.device}")
+        pool = ctypes.c_void_p()
+        ev._check(self.lib.pnp_pool_create(ev.ctx, ctypes.c_void_p(self.arena.data_ptr()),
+                                           ctypes.c_size_t(self.arena.numel()), ctypes.byref(pool)))
+        self.pool = pool
+        self._marshal = {}
+
+    def close(self):
+        if getattr(self, "pool", None):
+            _torch().cuda.synchronize()
+            self.lib.pnp_pool_destroy(self.pool)
+            self.pool = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def session_bytes(self, problem) -> int:
+        m = _Marshal(problem)
+        out = ctypes.c_size_t()
+        self.ev._check(self.lib.pnp_session_bytes(self.ev.ctx, ctypes.byref(m.grid), m.S,
+                                                  ctypes.byref(m.params), ctypes.byref(out)))
+        return int(out.value)
+
+    def usage(self):
+        used, big, n = ctypes.c_size_t(), ctypes.c_size_t(), ctypes.c_int32()
+        self.ev._check(self.lib.pnp_pool_usage(self.pool, ctypes.byref(used), ctypes.byref(big), ctypes.byref(n)))
+        return int(used.value), int(big.value), int(n.value)
+
+    def open(self, problem, rho0, mu_bulk=None, lam=0.1, clip=1.0):
+        """Admit a session; returns its id, or None when it does not fit now."""
+        m = _Marshal(problem)
+        mb = None if mu_bulk is None else (ctypes.c_double * m.S)(*[float(x) for x in mu_bulk])
+        sid = ctypes.c_int64()
+        st = self.lib.pnp_session_open(self.pool, ctypes.byref(m.grid), m.S, m.species, m.T,
+                                       ctypes.byref(m.params), self.ev._dev(rho0, "rho0"), mb, float(lam),
+                                       float(clip), self.ev._stream(), ctypes.byref(sid))
+        if st == -8:
+            return None
+        self.ev._check(st)
+        self._marshal[int(sid.value)] = (problem, m)
+        return int(sid.value)
+
+    def step(self, ids):
+        """One step of the listed sessions; returns their statuses."""
+        n = len(ids)
+        arr = (ctypes.c_int64 * n)(*ids)
+        st = (ctypes.c_int32 * n)()
+        self.ev._check(self.lib.pnp_session_step(self.pool, n, arr, st, self.ev._stream()))
+        return [int(x) for x in st]
+
+    def view(self, sid):
+        """(rho, mu_ex, slotboom, steps): CUDA tensors viewing the session's
+        resident arrays (valid until it closes)."""
+        torch = _torch()
+        problem, m = self._marshal[sid]
+        rp, mp, sp_, steps = ctypes.c_void_p(), ctypes.c_void_p(), ctypes.c_void_p(), ctypes.c_int64()
+        self.ev._check(self.lib.pnp_session_view(self.pool, sid, ctypes.byref(rp), ctypes.byref(mp),
+                                                 ctypes.byref(sp_), ctypes.byref(steps)))
+        shape = (m.S, problem.n, problem.n, problem.n)
+        base = self.arena.data_ptr()
+        out = []
+        for ptr in (rp, mp, sp_):
+            off = int(ptr.value) - base
+            nb = 8 * m.S * problem.n ** 3
+            out.append(self.arena[off:off + nb].view(torch.float64).view(shape))
+        return out[0], out[1], out[2], int(steps.value)
+
+    def close_session(self, sid):
+        self.ev._check(self.lib.pnp_session_close(self.pool, sid))
+        self._marshal.pop(sid, None)

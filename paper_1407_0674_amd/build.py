@@ -2,8 +2,9 @@
 
     python -m paper_1407_0674_amd.build
 
-The library is one translation unit (csrc/pnp_api.hip, which includes the
-kernels).  Packed-FP32 instructions are disabled for every device pass.
+The library is csrc/pnp_api.hip (C ABI, which includes the kernels) and
+csrc/pnp_serve.cpp (host-only serving layer over that ABI).  Packed-FP32
+instructions are disabled for every device pass.
 """
 import os
 import shutil
@@ -13,7 +14,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libpnpcdft.so")
-SRC = os.path.join(HERE, "csrc", "pnp_api.hip")
+SRC = [os.path.join(HERE, "csrc", "pnp_api.hip"), os.path.join(HERE, "csrc", "pnp_serve.cpp")]
 
 HIP_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
@@ -31,7 +32,7 @@ def hipcc() -> str:
 
 def build(verbose: bool = False) -> str:
     tmp = LIB + ".tmp"
-    cmd = [hipcc(), *HIP_FLAGS, "-I", os.path.join(ROOT, "include"), SRC, "-o", tmp]
+    cmd = [hipcc(), *HIP_FLAGS, "-I", os.path.join(ROOT, "include"), *SRC, "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)

@@ -180,7 +180,9 @@ pnp_status validate(pnp_ctx ctx, const pnp_grid* g, int S, const pnp_species* sp
       d.rout[q] = ro;
     }
   for (int i = 0; i < S; ++i) {
-    double c = sp[i].mu_el_bulk;
+    // the EC term's constant: its bulk value plus the k = 0 part of
+    // -sum_j C_ij rho_j^bulk; nothing when the EC term is off
+    double c = d.ec ? sp[i].mu_el_bulk : 0.0;
     if (d.ec)
       for (int j = 0; j < S; ++j) {
         const int pq = d.pi[i][j];
@@ -670,12 +672,14 @@ pnp_status pnp_read_status(pnp_ctx ctx, const void* ws, void* stream) {
 }
 
 pnp_status pnp_relax_densities(pnp_ctx ctx, const pnp_grid* g, int32_t S, const pnp_species* sp, double* rho,
-                               const double* mu, const double* mu_bulk, double lambda, void* stream) {
+                               const double* mu, const double* mu_bulk, double lambda, double clip,
+                               void* stream) {
   if (!ctx) return PNP_E_ARG;
   if (!g || !sp || !rho || !mu || !mu_bulk) return fail(ctx, PNP_E_ARG, "null argument");
   if (g->nx != g->ny || g->ny != g->nz || !size_ok(g->nx)) return fail(ctx, PNP_E_UNSUPPORTED_SIZE, "bad grid");
   if (S < 1 || S > kMaxSpecies) return fail(ctx, PNP_E_ARG, "species count");
   if (!(lambda >= 0.0 && lambda <= 1.0)) return fail(ctx, PNP_E_ARG, "lambda must be in [0, 1]");
+  if (std::isnan(clip)) return fail(ctx, PNP_E_ARG, "clip must be a number");
   if (hipSetDevice(ctx->device) != hipSuccess) return device_check(ctx, "set device");
   hipStream_t s = (hipStream_t)stream;
   double rb[2 * kMaxSpecies];
@@ -684,7 +688,7 @@ pnp_status pnp_relax_densities(pnp_ctx ctx, const pnp_grid* g, int32_t S, const 
   if (!drb) return device_check(ctx, "argument upload");
   const long n3 = (long)g->nx * g->ny * g->nz;
   const int blocks = (int)std::min<long>((S * n3 + 255) / 256, 4096);
-  hipLaunchKernelGGL(k_relax, dim3(blocks), dim3(256), 0, s, rho, mu, n3, (int)S, drb, lambda);
+  hipLaunchKernelGGL(k_relax, dim3(blocks), dim3(256), 0, s, rho, mu, n3, (int)S, drb, lambda, clip);
   return device_check(ctx, "relax launch");
 }
 
@@ -722,6 +726,47 @@ pnp_status pnp_debug_rfft3(pnp_ctx ctx, const pnp_grid* g, int32_t precision, in
   pnp_status st = device_check(ctx, "launch");
   if (st != PNP_OK) return st;
   if (hipStreamSynchronize(s) != hipSuccess) return device_check(ctx, "sync");
+  return PNP_OK;
+}
+
+pnp_status pnp_bulk_mu_ex(pnp_ctx ctx, int32_t S, const pnp_species* sp, double T, const pnp_params* p,
+                          double* mu) {
+  pnp_ctx_s local;  // host-only call: a context is optional (it only records the error)
+  if (!ctx) ctx = &local;
+  if (!mu) return fail(ctx, PNP_E_ARG, "null output");
+  const pnp_grid g{8, 8, 8, 1.0};  // the bulk value does not depend on the grid
+  Derived d;
+  pnp_status st = validate(ctx, &g, S, sp, T, p, d, true);
+  if (st != PNP_OK) return st;
+  // Rosenfeld FMT at uniform densities: n_a = sum_i rho_i w_i^a(k = 0), the
+  // vector densities vanish, and mu_i = sum_a dPhi/dn_a w_i^a(0) (Sec. 2.3.1)
+  double n0 = 0, n1 = 0, n2 = 0, n3 = 0;
+  for (int i = 0; i < S; ++i) {
+    const double R = 0.5 * sp[i].d, rb = sp[i].rho_bulk;
+    n0 += rb;
+    n1 += rb * R;
+    n2 += rb * 4.0 * M_PI * R * R;
+    n3 += rb * 4.0 / 3.0 * M_PI * R * R * R;
+  }
+  if (d.hs && !(n3 < 1.0)) return fail(ctx, PNP_E_PACKING, "bulk packing fraction >= 1");
+  const double u = 1.0 - n3;
+  const double d0 = -std::log1p(-n3), d1 = n2 / u, d2 = n1 / u + n2 * n2 / (8.0 * M_PI * u * u);
+  const double d3 = n0 / u + n1 * n2 / (u * u) + n2 * n2 * n2 / (12.0 * M_PI * u * u * u);
+  for (int i = 0; i < S; ++i) {
+    const double R = 0.5 * sp[i].d;
+    double m = 0.0;
+    if (d.hs) m += d0 + R * d1 + 4.0 * M_PI * R * R * d2 + 4.0 / 3.0 * M_PI * R * R * R * d3;
+    // EC (Sec. 2.3.4) at uniform bulk densities: only the bulk constant
+    if (d.ec) m += sp[i].mu_el_bulk;
+    // mean-field square well (Sec. 2.3.2): c_sw beta sum_j rho_j u_ij(k = 0)
+    if (d.sw)
+      for (int j = 0; j < S; ++j) {
+        const int q = d.pi[i][j];
+        const double s = d.sigma[q], ro = d.rout[q];
+        m += p->sw_prefactor * d.beta * sp[j].rho_bulk * (-d.eps[q]) * 4.0 / 3.0 * M_PI * (ro * ro * ro - s * s * s);
+      }
+    mu[i] = m;
+  }
   return PNP_OK;
 }
 

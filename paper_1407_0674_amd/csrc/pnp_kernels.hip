@@ -1200,14 +1200,17 @@ __global__ void __launch_bounds__(256) k_copy(const uint4* __restrict__ src, uin
   for (; e < words; e += stride) dst[e] = src[e];
 }
 
-// relaxation of the consumer stub: rho <- (1 - l) rho + l rho_b exp(mu_b - mu)
+// relaxation of the consumer stub: rho <- (1 - l) rho + l rho_b exp(g),
+// g = mu_b - mu limited to [-clip, clip] when clip > 0
 __global__ void k_relax(double* rho, const double* mu, long n3, int S, const double* rho_b_mu_b,
-                        double lambda) {
+                        double lambda, double clip) {
   const long total = (long)S * n3;
   for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (long)gridDim.x * blockDim.x) {
     const int s = (int)(e / n3);
     const double rb = rho_b_mu_b[2 * s], mb = rho_b_mu_b[2 * s + 1];
-    rho[e] = (1.0 - lambda) * rho[e] + lambda * rb * exp(mb - mu[e]);
+    double g = mb - mu[e];
+    if (clip > 0.0) g = fmin(fmax(g, -clip), clip);
+    rho[e] = (1.0 - lambda) * rho[e] + lambda * rb * exp(g);
   }
 }
 

@@ -110,6 +110,14 @@ def gaussian_channel(rng, n: int, h: float, rho_b: Sequence[float],
     minimum-image distance to a random axis (cx, cz), width w ~ U(L/10, L/6).
     Cations gather in the tube, anions are pushed out:
         rho_i = rho_b,i [1 + amp * sign(q_i) * (2 g - 1)]."""
+    prof = gaussian_channel_profile(rng, n, h, rho_b, q, amp)
+    return np.ascontiguousarray(np.broadcast_to(prof[:, :, None, :], (len(rho_b), n, n, n)))
+
+
+def gaussian_channel_profile(rng, n: int, h: float, rho_b: Sequence[float],
+                             q: Sequence[float], amp: float = 0.5) -> np.ndarray:
+    """The (x, z) profile [S][n][n] of gaussian_channel (the pattern is constant
+    along y); broadcasting it along y gives gaussian_channel's array exactly."""
     L = n * h
     cx, cz = rng.uniform(0.0, L, size=2)
     w = rng.uniform(L / 10.0, L / 6.0)
@@ -121,11 +129,10 @@ def gaussian_channel(rng, n: int, h: float, rho_b: Sequence[float],
     d2 = dx[:, None] ** 2 + dz[None, :] ** 2            # (x, z)
     g = np.exp(-d2 / (2.0 * w * w))
     S = len(rho_b)
-    out = np.empty((S, n, n, n))
+    out = np.empty((S, n, n))
     for i in range(S):
         s = np.sign(q[i]) if q[i] != 0 else 0.0
-        prof = rho_b[i] * (1.0 + amp * s * (2.0 * g - 1.0))  # (x, z)
-        out[i] = np.broadcast_to(prof[:, None, :], (n, n, n))
+        out[i] = rho_b[i] * (1.0 + amp * s * (2.0 * g - 1.0))  # (x, z)
     return out
 
 
@@ -189,11 +196,13 @@ def config3(seed: int = BASE_SEED + 3, n: int = 256, eta_max: float = 0.45,
 
 
 def random_instance(rng, n_choices, precision: int = MIXED, h: float = 0.05,
-                    with_rho: bool = True):
+                    with_rho: bool = True, profile: bool = False):
     """One uneven instance of the batched / served mixes: n from n_choices,
     T ~ U(250, 350) K, S ~ U{2,3,4}, d ~ U(0.15, 0.45) nm, bulk ~ U(0.1, 2.0) M,
     z ~ U{+-1, +-2}, channel pattern, HS + EC + SW (0.3 eV, 0.3 nm wells).
-    With with_rho=False only the description is drawn (rho is None)."""
+    With with_rho=False only the description is drawn (rho is None); with
+    profile=True the second value is the (x, z) profile [S][n][n] instead of
+    the full array (the same draws: broadcasting it along y gives rho)."""
     n = int(rng.choice(n_choices))
     T = float(rng.uniform(250.0, 350.0))
     S = int(rng.integers(2, 5))
@@ -204,8 +213,11 @@ def random_instance(rng, n_choices, precision: int = MIXED, h: float = 0.05,
     eps, rout = uniform_well(sp, 0.3, 0.3)
     prob = Problem(n=n, h=h, species=sp, T=T, terms=TERMS_ALL, sw_eps=eps,
                    sw_rout=rout, precision=precision, name=f"inst-{n}^3-S{S}")
-    rho = gaussian_channel(rng, n, h, [s.rho_bulk for s in sp], list(q), 0.5) if with_rho else None
-    return prob, rho
+    if not with_rho:
+        return prob, None
+    if profile:
+        return prob, gaussian_channel_profile(rng, n, h, [s.rho_bulk for s in sp], list(q), 0.5)
+    return prob, gaussian_channel(rng, n, h, [s.rho_bulk for s in sp], list(q), 0.5)
 
 
 def config4(seed: int = BASE_SEED + 4, count: int = 64, n_choices=(32, 48, 64, 96, 128),
@@ -234,6 +246,11 @@ class Request:
         return random_instance(np.random.default_rng(self.seed), self.n_choices,
                                self.precision)
 
+    def build_profile(self):
+        """(problem, (x, z) profile [S][n][n]); rho is the profile broadcast along y."""
+        return random_instance(np.random.default_rng(self.seed), self.n_choices,
+                               self.precision, profile=True)
+
 
 def config5(seed: int = BASE_SEED + 5, rate: float = 200.0, duration: float = 10.0,
             n_choices=(48, 64, 96, 128, 192), precision: int = MIXED,
@@ -257,6 +274,6 @@ def config5(seed: int = BASE_SEED + 5, rate: float = 200.0, duration: float = 10
 __all__ = [
     "MOLAR_TO_NM3", "TERM_HS", "TERM_EC", "TERM_SW", "TERMS_ALL", "FP64", "MIXED",
     "Species", "Problem", "Request", "uniform_well", "uniform_noise",
-    "gaussian_channel", "local_packing_max", "config1", "config2", "config3",
+    "gaussian_channel", "gaussian_channel_profile", "local_packing_max", "config1", "config2", "config3",
     "config4", "config5", "channel_problem", "random_instance", "BASE_SEED",
 ]

@@ -64,3 +64,54 @@ def test_struct_layouts_match_header():
     assert ctypes.sizeof(binding.SpeciesC) == 32
     assert ctypes.sizeof(binding.ParamsC) == 56
     assert binding.RequestC.status.offset == ctypes.sizeof(binding.RequestC) - 8
+
+
+def _uniform(problem, n=8):
+    import numpy as np
+    return np.stack([np.full((n, n, n), s.rho_bulk) for s in problem.species])
+
+
+@pytest.mark.parametrize("terms", [1, 2, 4, 3, 5, 6, 7])
+def test_bulk_mu_ex_against_oracle(terms):
+    """pnp_bulk_mu_ex (host arithmetic behind the ABI, no device) equals the
+    oracle's evaluation of uniform bulk densities, with non-zero EC bulk
+    constants."""
+    import numpy as np
+    import oracle
+    import pnp_inputs as P
+    for prob, _ in (P.config1(), P.channel_problem(16, 7), P.config3(n=16)):
+        sp = [P.Species(s.d, s.q, s.rho_bulk, 0.25 * (i + 1)) for i, s in enumerate(prob.species)]
+        pr = prob.with_(terms=terms, species=sp, n=8)
+        ref = oracle.mu_ex(pr, _uniform(pr), "fft")["total"][:, 0, 0, 0]
+        got = np.array(pkg.bulk_mu_ex(pr))
+        assert np.max(np.abs(got - ref)) < 1e-12 * max(1.0, float(np.max(np.abs(ref)))), (terms, got, ref)
+
+
+def test_bulk_mu_ex_percus_yevick():
+    """One hard-sphere species: the Rosenfeld bulk value is the Percus-Yevick
+    compressibility result, -ln(1-eta) + (14 eta - 13 eta^2 + 5 eta^3) / (2 (1-eta)^3)."""
+    import math
+    import pnp_inputs as P
+    eta, d = 0.45, 0.3
+    sp = [P.Species(d, 0.0, eta / (math.pi / 6.0 * d ** 3))]
+    pr = P.Problem(n=8, h=0.05, species=sp, T=300.0, terms=P.TERM_HS)
+    py = -math.log(1 - eta) + (14 * eta - 13 * eta ** 2 + 5 * eta ** 3) / (2 * (1 - eta) ** 3)
+    assert abs(pkg.bulk_mu_ex(pr)[0] - py) < 1e-12
+
+
+def test_bulk_mu_ex_packing_error():
+    import math
+    import pnp_inputs as P
+    sp = [P.Species(0.3, 0.0, 1.2 / (math.pi / 6.0 * 0.3 ** 3))]
+    pr = P.Problem(n=8, h=0.05, species=sp, T=300.0, terms=P.TERM_HS)
+    with pytest.raises(pkg.PnpError) as e:
+        pkg.bulk_mu_ex(pr)
+    assert e.value.status == -4
+
+
+def test_pool_calls_reject_null():
+    lib = binding.load_library()
+    assert lib.pnp_pool_create(None, None, 0, None) == -1
+    assert lib.pnp_session_step(None, 0, None, None, None) == -1
+    assert lib.pnp_session_close(None, 1) == -1
+    assert lib.pnp_pool_usage(None, None, None, None) == -1

@@ -99,14 +99,14 @@ def test_config4_batch(ev):
             assert relerr(mu[i], ref["total"][i]) < 1e-5, (p.name, i)
 
 
-@pytest.mark.parametrize("lam", [0.0, 0.1, 1.0])
-def test_relax_vs_oracle(ev, lam):
+@pytest.mark.parametrize("lam,clip", [(0.0, 0.0), (0.1, 0.0), (1.0, 0.0), (0.5, 1.0), (1.0, 0.3)])
+def test_relax_vs_oracle(ev, lam, clip):
     prob, rho = P.channel_problem(24, 5100)
     rng = np.random.default_rng(5101)
     mu = rng.normal(scale=2.0, size=rho.shape)
     mu_b = rng.normal(size=prob.S)
     rd, md = to_dev(rho), to_dev(mu)
-    ev.relax(prob, rd, md, mu_b, lam)
-    ref = oracle.relax_densities(rho, mu, [s.rho_bulk for s in prob.species], mu_b, lam)
+    ev.relax(prob, rd, md, mu_b, lam, clip)
+    ref = oracle.relax_densities(rho, mu, [s.rho_bulk for s in prob.species], mu_b, lam, clip)
     got = rd.cpu().numpy()
     assert np.max(np.abs(got - ref) / np.abs(ref)) < 1e-14

@@ -42,3 +42,16 @@ def test_bulk_state_is_fixed_point():
     for lam in (0.1, 0.5, 1.0):
         out = oracle.relax_densities(rho, mu, [rho_b], [mu_py], lam)
         assert np.max(np.abs(out - rho)) / rho_b < 1e-12
+
+
+def test_limit_bounds_the_exponent():
+    # with a limit c the target density lies in [rho_b e^-c, rho_b e^c]
+    rho = np.full((1, 2, 2, 2), 3.0)
+    mu = np.array([[[[-50.0, 0.2], [50.0, -0.1]], [[0.0, 7.0], [-7.0, 0.5]]]])
+    out = oracle.relax_densities(rho, mu, [2.0], [0.0], 1.0, clip=0.5)
+    g = np.clip(-mu, -0.5, 0.5)
+    assert np.allclose(out, 2.0 * np.exp(g), rtol=1e-15, atol=0)
+    assert out.max() <= 2.0 * math.exp(0.5) * (1 + 1e-15) and out.min() >= 2.0 * math.exp(-0.5) * (1 - 1e-15)
+    # clip <= 0: no limit
+    out0 = oracle.relax_densities(rho, mu, [2.0], [0.0], 1.0, clip=0.0)
+    assert np.allclose(out0, 2.0 * np.exp(-mu), rtol=1e-15, atol=0)
