@@ -285,7 +285,7 @@ pnp_status read_status(pnp_ctx c, const void* status_dev, hipStream_t s) {
 // launchers per (precision, n)
 // ---------------------------------------------------------------------------
 struct Ops {
-  void (*tables)(const TableArgs*, int, int, hipStream_t);
+  void (*tables)(const TableArgs*, int, int, int, hipStream_t);
   void (*zfwd)(const EvalArgs*, int, hipStream_t);
   void (*ystep)(const EvalArgs*, int, int, int, bool, hipStream_t);
   void (*xfwd)(const EvalArgs*, int, hipStream_t);
@@ -298,9 +298,10 @@ struct Ops {
 
 template <typename T, int N> struct Launch {
   using G = Geo<T, N>;
-  static void tables(const TableArgs* a, int count, int M, hipStream_t s) {
-    const int bp = (M + 255) / 256;
-    hipLaunchKernelGGL(k_tables<T>, dim3(count * bp), dim3(256), 0, s, a, bp);
+  // maxS: the largest species count among the launch's instances
+  static void tables(const TableArgs* a, int count, int M, int maxS, hipStream_t s) {
+    const int items = maxS * ((maxS + 3) / 4 * 4) + maxS;  // pair-table entries + hs species
+    hipLaunchKernelGGL(k_tables<T>, dim3((M + 255) / 256, items, count), dim3(256), 0, s, a);
   }
   static void zfwd(const EvalArgs* a, int count, hipStream_t s) {
     hipLaunchKernelGGL((k_zfwd<T, N>), dim3(count * G::tiles_z), dim3(G::RZ * G::TZ), 0, s, a);
@@ -378,7 +379,7 @@ const Ops* ops_for(int precision, int n) {
 void run_sequence(pnp_ctx c, const Ops* op, const EvalArgs* ea, const TableArgs* ta, int count, int M,
                   bool hs_any, int ch, hipStream_t s) {
   PassTimer pt{c, s};
-  pt.begin(0); op->tables(ta, count, M, s); pt.end();
+  pt.begin(0); op->tables(ta, count, M, ch, s); pt.end();
   pt.begin(1); op->zfwd(ea, count, s); pt.end();
   pt.begin(2); op->ystep(ea, count, 0, -1, true, s); pt.end();
   if (hs_any) {
@@ -526,8 +527,8 @@ pnp_status pnp_cdft_mu_ex(pnp_ctx ctx, const pnp_grid* g, int32_t S, const pnp_s
     if (!dta || !dea) return device_check(ctx, "argument upload");
     PassTimer pt{ctx, s};
     pt.begin(0);
-    op->tables(dta, 1, L.M, s);
-    if (d.sw) op->tables(dta + 1, 1, L.M, s);
+    op->tables(dta, 1, L.M, S, s);
+    if (d.sw) op->tables(dta + 1, 1, L.M, S, s);
     pt.end();
     pt.begin(1); op->zfwd(dea, 1, s); pt.end();
     pt.begin(2); op->ystep(dea, 1, 0, -1, true, s); pt.end();
@@ -580,7 +581,7 @@ pnp_status pnp_weighted_densities(pnp_ctx ctx, const pnp_grid* g, int32_t S, con
   const TableArgs* dta = (const TableArgs*)upload(ctx, &ta, sizeof(ta), s);
   const EvalArgs* dea = (const EvalArgs*)upload(ctx, &ea, sizeof(ea), s);
   if (!dta || !dea) return device_check(ctx, "argument upload");
-  op->tables(dta, 1, L.M, s);
+  op->tables(dta, 1, L.M, S, s);
   op->zfwd(dea, 1, s);
   op->ystep(dea, 1, 0, -1, true, s);
   op->xfwd(dea, 1, s);

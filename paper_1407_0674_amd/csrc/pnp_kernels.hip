@@ -212,17 +212,36 @@ __device__ double d_invrball(double k, double a) {
   return 4.0 * kPi * a * a * f;
 }
 
-// hs table [m][S][4] = (j0(kR), 4 pi R^3 j1(kR)/(kR), 4 pi R^2 j1(kR), 0);
-// pair table [m][j][i] (row length Sp) = G_ij, the combined pair kernel.
+// hs table [m][S][4] = (j0(kR), 4 pi R^3 j1(kR)/(kR), 4 pi R^2 j1(kR), 0)
+// (FP64 path only); pair table [m][j][i] (row length Sp) = G_ij, the combined
+// pair kernel, zero for i >= S.  One thread per (m, table entry): blockIdx.y
+// picks the entry (pair-table entries first, then the hs species), blockIdx.z
+// the instance.
 template <typename T>
-__global__ void __launch_bounds__(256) k_tables(const TableArgs* __restrict__ targs, int blocks_per) {
-  const int inst = blockIdx.x / blocks_per;
-  const TableArgs& a = targs[inst];
-  const int m = (blockIdx.x % blocks_per) * blockDim.x + threadIdx.x;
+__global__ void __launch_bounds__(256) k_tables(const TableArgs* __restrict__ targs) {
+  const TableArgs& a = targs[blockIdx.z];
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
   if (m >= a.M) return;
+  const int item = blockIdx.y;
+  const int npair = a.S * a.Sp;
   const double k = a.kscale * sqrt((double)m);
-  const Buf hs = make_buf(a.hs_tab, sizeof(T) == 8 ? (uint64_t)a.M * a.S * 4 * sizeof(T) : 0);
-  for (int i = 0; i < (sizeof(T) == 8 ? a.S : 0); ++i) {  // the FP32 path evaluates these in registers
+  if (item < npair) {
+    if (!a.pair_tab) return;
+    const int j = item / a.Sp, i = item % a.Sp;
+    double v = 0.0;
+    if (i < a.S) {
+      const int p = a.pidx[i][j];
+      const double s = a.sigma[p];
+      if (a.ec_pref[p] != 0.0) {
+        const double b = a.Bsig[p];
+        v += a.ec_pref[p] * (2.0 * b * d_ball(k, s) - b * b * d_rball(k, s) - d_invrball(k, s));
+      }
+      if (a.sw_pref[p] != 0.0) v += a.sw_pref[p] * (d_ball(k, a.rout[p]) - d_ball(k, s));
+    }
+    const Buf pr = make_buf(a.pair_tab, (uint64_t)a.M * a.S * a.Sp * sizeof(T));
+    pr.st<T>((T)v, (uint32_t)(((m * a.S + j) * a.Sp + i) * sizeof(T)));
+  } else if (sizeof(T) == 8 && item < npair + a.S) {  // the FP32 path evaluates these in registers
+    const int i = item - npair;
     const double R = a.R[i];
     const double x = k * R;
     const double j1x = d_j1x(x);
@@ -232,24 +251,8 @@ __global__ void __launch_bounds__(256) k_tables(const TableArgs* __restrict__ ta
     w.y = (T)(4.0 * kPi * R * R * R * j1x);
     w.z = (T)(4.0 * kPi * R * R * x * j1x);
     w.w = (T)0;
+    const Buf hs = make_buf(a.hs_tab, (uint64_t)a.M * a.S * 4 * sizeof(T));
     hs.st<v4<T>>(w, (uint32_t)((m * a.S + i) * sizeof(v4<T>)));
-  }
-  if (a.pair_tab) {
-    const Buf pr = make_buf(a.pair_tab, (uint64_t)a.M * a.S * a.Sp * sizeof(T));
-    double g[kMaxPairs];
-    for (int p = 0; p < (a.S * (a.S + 1)) / 2; ++p) {
-      double v = 0.0;
-      const double s = a.sigma[p];
-      if (a.ec_pref[p] != 0.0) {
-        const double b = a.Bsig[p];
-        v += a.ec_pref[p] * (2.0 * b * d_ball(k, s) - b * b * d_rball(k, s) - d_invrball(k, s));
-      }
-      if (a.sw_pref[p] != 0.0) v += a.sw_pref[p] * (d_ball(k, a.rout[p]) - d_ball(k, s));
-      g[p] = v;
-    }
-    for (int j = 0; j < a.S; ++j)
-      for (int i = 0; i < a.Sp; ++i)
-        pr.st<T>((T)(i < a.S ? g[a.pidx[i][j]] : 0.0), (uint32_t)(((m * a.S + j) * a.Sp + i) * sizeof(T)));
   }
 }
 
