@@ -34,21 +34,28 @@ HBM_PEAK_GBS = 8000.0
 F = 10  # weighted-density fields
 
 
+FV = 8  # fields between the x passes and the y passes: each vector density
+        # travels as two fields there ([x] and Q_b or the khat . F partial sum)
+
+
 def pass_bytes_per_point(S: int, precision: int, slot: bool = True):
     """Algorithmic HBM bytes per grid point of each pass: every pass reads its
     inputs once and writes its outputs once; a half spectrum of one field
-    holds n^3/2 complex values (ts bytes per grid point and field, ts = 4 in
-    the mixed path, 8 in FP64); densities in and mu / exp(-mu) out are FP64."""
+    holds n^3/2 complex values (c bytes per grid point and field, c = 4 in
+    the mixed path, 8 in FP64); densities in and mu / exp(-mu) out are FP64.
+    The ten FMT fields are 8 stored fields on either side of the y/z passes
+    (60 S + 28.8 F bytes per point in the mixed path; 60 S + 32 F with all
+    ten fields in every pass)."""
     c = 4 if precision == 1 else 8
     out = 16 if slot else 8
     return {
         "z_fwd_rho": (8 + c) * S,
         "y_fwd_rho": 2 * c * S,
-        "x_fwd_weights": c * S + c * F,
-        "y_inv_n": 2 * c * F,
+        "x_fwd_weights": c * S + c * FV,
+        "y_inv_n": c * FV + c * F,
         "z_deriv": 2 * c * F,
-        "y_fwd_dphi": 2 * c * F,
-        "x_back_pairs": c * F + 2 * c * S,
+        "y_fwd_dphi": c * F + c * FV,
+        "x_back_pairs": c * FV + 2 * c * S,
         "y_inv_mu": 2 * c * S,
         "z_inv_final": c * S + out * S,
     }

@@ -384,9 +384,9 @@ void run_sequence(pnp_ctx c, const Ops* op, const EvalArgs* ea, const TableArgs*
   pt.begin(2); op->ystep(ea, count, 0, -1, true, s); pt.end();
   if (hs_any) {
     pt.begin(3); op->xfwd(ea, count, s); pt.end();
-    pt.begin(4); op->ystep(ea, count, 1, kFields, false, s); pt.end();
+    pt.begin(4); op->ystep(ea, count, 1, kVecMode, false, s); pt.end();
     pt.begin(5); op->zderiv(ea, count, s); pt.end();
-    pt.begin(6); op->ystep(ea, count, 1, kFields, true, s); pt.end();
+    pt.begin(6); op->ystep(ea, count, 1, kVecMode, true, s); pt.end();
   }
   pt.begin(7); op->xback(ea, count, ch, s); pt.end();
   pt.begin(8); op->ystep(ea, count, 2, -1, false, s); pt.end();
@@ -534,9 +534,9 @@ pnp_status pnp_cdft_mu_ex(pnp_ctx ctx, const pnp_grid* g, int32_t S, const pnp_s
     pt.begin(2); op->ystep(dea, 1, 0, -1, true, s); pt.end();
     if (d.hs) {
       pt.begin(3); op->xfwd(dea, 1, s); pt.end();
-      pt.begin(4); op->ystep(dea, 1, 1, kFields, false, s); pt.end();
+      pt.begin(4); op->ystep(dea, 1, 1, kVecMode, false, s); pt.end();
       pt.begin(5); op->zderiv(dea, 1, s); pt.end();
-      pt.begin(6); op->ystep(dea, 1, 1, kFields, true, s); pt.end();
+      pt.begin(6); op->ystep(dea, 1, 1, kVecMode, true, s); pt.end();
     }
     for (int k = 1; k < 4; ++k) {
       pt.begin(7); op->xback(dea + k, 1, ch, s); pt.end();
@@ -578,6 +578,8 @@ pnp_status pnp_weighted_densities(pnp_ctx ctx, const pnp_grid* g, int32_t S, con
   ea.final_mode = 0;
   ea.nreal = kFields;
   ea.out = n_out;
+  // the z components of the vector densities are i s_z Q_b until the z pass
+  ea.zmul_mask = (1u << kSlotZ) | (1u << (kSlotZ + kVecStride));
   const TableArgs* dta = (const TableArgs*)upload(ctx, &ta, sizeof(ta), s);
   const EvalArgs* dea = (const EvalArgs*)upload(ctx, &ea, sizeof(ea), s);
   if (!dta || !dea) return device_check(ctx, "argument upload");
@@ -585,7 +587,7 @@ pnp_status pnp_weighted_densities(pnp_ctx ctx, const pnp_grid* g, int32_t S, con
   op->zfwd(dea, 1, s);
   op->ystep(dea, 1, 0, -1, true, s);
   op->xfwd(dea, 1, s);
-  op->ystep(dea, 1, 1, kFields, false, s);
+  op->ystep(dea, 1, 1, kVecMode, false, s);
   op->zinv(dea, 1, 1, s);
   st = device_check(ctx, "launch");
   if (st != PNP_OK) return st;

@@ -13,11 +13,13 @@
 // inverse transform is applied once, in the spectral multiplies):
 //   P1 z r2c of S densities            k_zfwd
 //   P2 y forward                       k_ystep<FWD>
-//   P3 x forward, weights, x inverse   k_xfwd      (S -> 10 weighted densities)
-//   P4 y inverse                       k_ystep<INV>
+//   P3 x forward, weights, x inverse   k_xfwd      (S -> 8 stored fields)
+//   P4 y inverse                       k_ystep<INV> (8 -> 10: vector y components)
 //   P5 z c2r, FMT derivatives, z r2c   k_zderiv    (10 -> 10, FP64 pointwise)
-//   P6 y forward                       k_ystep<FWD>
-//   P7 x forward, back-convolution, pair kernels, x inverse   k_xback (10 + S -> S)
+//   P6 y forward                       k_ystep<FWD> (10 -> 8: khat . F partial sums)
+//   P7 x forward, back-convolution, pair kernels, x inverse   k_xback (8 + S -> S)
+// (the vector densities carry one component per axis pass; see the
+// field-slot layout in pnp_kernels.hpp)
 //   P8 y inverse                       k_ystep<INV>
 //   P9 z c2r, + constants, exp(-mu)    k_zinv
 //
@@ -61,6 +63,9 @@ template <typename T, int N> struct Geo {
   static constexpr int tiles_y = (N * H) / PY + N / PY;
   static constexpr int tiles_x = (N * H) / PX + N / PX;
 };
+
+// signed wavenumber index of position j on an axis of n points
+__device__ __forceinline__ int sgn_idx(int j, int n) { return j < n / 2 ? j : j - n; }
 
 // twiddle table exp(-2 pi i j / L), computed in double
 template <typename T, int L>
@@ -268,10 +273,11 @@ __global__ void __launch_bounds__(256) k_tables(const TableArgs* __restrict__ ta
 // wave-local.
 template <int TZ> constexpr bool row_in_wave() { return TZ <= 64 && 64 % TZ == 0; }
 
-// v holds C[k] at k = t + TZ m; writes X[k] (k < H) and X[H] of one row
+// v holds C[k] at k = t + TZ m; writes X[k] (k < H) and X[H] of one row.
+// zmul: store i s_z X instead (s_z = k below the Nyquist index, 0 at it).
 template <typename T, int N, int TZ, int EZ>
 __device__ __forceinline__ void r2c_post(cx<T>* v, int t, const cx<T>* twN, cx<T>* row, const Buf& f,
-                                         uint32_t soff, uint32_t row_id) {
+                                         uint32_t soff, uint32_t row_id, bool zmul = false) {
   constexpr int H = N / 2;
   constexpr uint32_t cs = sizeof(cx<T>);
 #pragma unroll
@@ -284,8 +290,11 @@ __device__ __forceinline__ void r2c_post(cx<T>* v, int t, const cx<T>* twN, cx<T
     const cx<T> cm = cconj<T>(row[k == 0 ? 0 : H - k]);
     const cx<T> e = mk<T>((T)0.5 * (c.x + cm.x), (T)0.5 * (c.y + cm.y));
     const cx<T> d = mk<T>((T)0.5 * (c.x - cm.x), (T)0.5 * (c.y - cm.y));  // O = d / i
-    f.st<cx<T>>(cadd<T>(e, cmul<T>(twN[k], cmulmi<T>(d))), (row_id * H + k) * cs, soff);
-    if (k == 0) f.st<cx<T>>(mk<T>(c.x - c.y, (T)0), ((uint32_t)(N * N * H) + row_id) * cs, soff);
+    cx<T> x = cadd<T>(e, cmul<T>(twN[k], cmulmi<T>(d)));
+    if (zmul) x = cscale<T>(cmuli<T>(x), (T)k);
+    f.st<cx<T>>(x, (row_id * H + k) * cs, soff);
+    if (k == 0) f.st<cx<T>>(zmul ? mk<T>((T)0, (T)0) : mk<T>(c.x - c.y, (T)0),
+                            ((uint32_t)(N * N * H) + row_id) * cs, soff);
   }
   lds_sync<row_in_wave<TZ>()>();
 }
@@ -293,9 +302,10 @@ __device__ __forceinline__ void r2c_post(cx<T>* v, int t, const cx<T>* twN, cx<T
 // inverse: from X[k] (k < H) and X[H] build C[k] = (X[k] + conj X[H-k]) +
 // i (X[k] - conj X[H-k]) W^-k; the unnormalised length-H inverse of C is
 // then n (a[2j] + i a[2j+1])
+// zmul: transform i s_z X instead of X (s_z = k below the Nyquist index, 0 at it)
 template <typename T, int N, int TZ, int EZ>
 __device__ __forceinline__ void c2r_pre(cx<T>* v, int t, const cx<T>* twN, const Buf& f, uint32_t soff,
-                                        uint32_t row_id) {
+                                        uint32_t row_id, bool zmul = false) {
   constexpr int H = N / 2;
   constexpr uint32_t cs = sizeof(cx<T>);
 #pragma unroll
@@ -304,6 +314,10 @@ __device__ __forceinline__ void c2r_pre(cx<T>* v, int t, const cx<T>* twN, const
     cx<T> xk = f.ld<cx<T>>((row_id * H + k) * cs, soff);
     cx<T> xm = f.ld<cx<T>>((k == 0 ? (uint32_t)(N * N * H) + row_id : row_id * H + (H - k)) * cs, soff);
     if (k == 0) { xk.y = (T)0; xm.y = (T)0; }
+    if (zmul) {
+      xk = cscale<T>(cmuli<T>(xk), (T)k);
+      xm = k == 0 ? mk<T>((T)0, (T)0) : cscale<T>(cmuli<T>(xm), (T)(H - k));
+    }
     const cx<T> cm = cconj<T>(xm);
     const cx<T> s = cadd<T>(xk, cm);
     const cx<T> d = csub<T>(xk, cm);
@@ -381,7 +395,8 @@ __global__ void __launch_bounds__((Geo<T, N>::RZ * Geo<T, N>::TZ))
   uint32_t bad = 0u, badidx = 0xffffffffu;
   for (int s = 0; s < a.nreal; ++s) {
     cx<T> v[EZ];
-    c2r_pre<T, N, TZ, EZ>(v, t, twN, src, (uint32_t)(s * a.fstride * sizeof(cx<T>)), row);
+    c2r_pre<T, N, TZ, EZ>(v, t, twN, src, (uint32_t)(s * a.fstride * sizeof(cx<T>)), row,
+                          (a.zmul_mask >> s) & 1u);
     fft_pencil<T, H, EZ, false>(v, t, twH, lp);
     const uint32_t so = (uint32_t)s * n3b;
     if (a.final_mode) {
@@ -448,12 +463,17 @@ __device__ __forceinline__ void c2r_load(cx<T>* xk, cx<T>* xm, int t, const Buf&
 // the c2r pre-step on loaded values (same arithmetic as c2r_pre)
 template <typename T, int N, int TZ, int EZ>
 __device__ __forceinline__ void c2r_combine(cx<T>* v, const cx<T>* xk0, const cx<T>* xm0, int t,
-                                            const cx<T>* twN) {
+                                            const cx<T>* twN, bool zmul = false) {
+  constexpr int H = N / 2;
 #pragma unroll
   for (int m = 0; m < EZ; ++m) {
     const int k = t + TZ * m;
     cx<T> xk = xk0[m], xm = xm0[m];
     if (k == 0) { xk.y = (T)0; xm.y = (T)0; }
+    if (zmul) {
+      xk = cscale<T>(cmuli<T>(xk), (T)k);
+      xm = k == 0 ? mk<T>((T)0, (T)0) : cscale<T>(cmuli<T>(xm), (T)(H - k));
+    }
     const cx<T> cm = cconj<T>(xm);
     const cx<T> s = cadd<T>(xk, cm);
     const cx<T> d = csub<T>(xk, cm);
@@ -503,7 +523,8 @@ __global__ void __launch_bounds__((GeoD<T, N, EZD>::RDD * GeoD<T, N, EZD>::TZD))
       cx<T>* kn = (q & 1) ? k0 : k1;
       cx<T>* mn = (q & 1) ? m0 : m1;
       if (q + 1 < kFields) c2r_load<T, N, TZ, EZ>(kn, mn, t, B, (uint32_t)(q + 1) * fbytes, row);
-      c2r_combine<T, N, TZ, EZ>(val + q * EZ, kc, mc, t, twN);
+      // the z component of each vector density is i s_z Q_b, formed here
+      c2r_combine<T, N, TZ, EZ>(val + q * EZ, kc, mc, t, twN, q == kSlotZ || q == kSlotZ + kVecStride);
       fft_pencil<T, N / 2, EZ, false>(val + q * EZ, t, twH, lp);
     }
   }
@@ -551,7 +572,8 @@ __global__ void __launch_bounds__((GeoD<T, N, EZD>::RDD * GeoD<T, N, EZD>::TZD))
 #pragma unroll
   for (int q = 0; q < kFields; ++q) {
     fft_pencil<T, N / 2, EZ, true>(val + q * EZ, t, twH, lp);
-    r2c_post<T, N, TZ, EZ>(val + q * EZ, t, twN, lrow, B, q * fbytes, row);
+    // the z components of the vector derivatives leave as i s_z F_z
+    r2c_post<T, N, TZ, EZ>(val + q * EZ, t, twN, lrow, B, q * fbytes, row, q == kSlotZ || q == kSlotZ + kVecStride);
     __builtin_amdgcn_sched_barrier(0);
   }
   if (bad) raise_status(a.status, bad, badidx);
@@ -559,8 +581,24 @@ __global__ void __launch_bounds__((GeoD<T, N, EZD>::RDD * GeoD<T, N, EZD>::TZD))
 
 // ---------------------------------------------------------------------------
 // y direction: c2c along y for every (x, kz) pencil of the main array and
-// every x row of the Nyquist plane; in place on `nf` fields of `sel`.
+// every x row of the Nyquist plane; in place on `nf` fields of `sel`
+// (nf_code -1: S fields).  nf_code kVecMode: the ten FMT fields of specB
+// with the vector-component bookkeeping of the field-slot layout: the
+// inverse pass also writes [y] = i s_y Q_b next to Q_b; the forward pass
+// writes [z] = i s_y F_y + [z] and leaves [y] unused.
 // ---------------------------------------------------------------------------
+constexpr int kVecMode = -2;
+
+template <typename T, int N, int EY, int TY>
+__device__ __forceinline__ void mul_isy(cx<T>* v, int t) {
+#pragma unroll
+  for (int m = 0; m < EY; ++m) {
+    const int ky = t + TY * m;
+    const T sy = ky == N / 2 ? (T)0 : (T)sgn_idx(ky, N);
+    v[m] = cscale<T>(cmuli<T>(v[m]), sy);
+  }
+}
+
 template <typename T, int N, bool FWD>
 __global__ void __launch_bounds__((Geo<T, N>::PY * Geo<T, N>::TY))
     k_ystep(const EvalArgs* __restrict__ args, int sel, int nf_code) {
@@ -573,7 +611,8 @@ __global__ void __launch_bounds__((Geo<T, N>::PY * Geo<T, N>::TY))
   if (sel == 1 && !a.hs_on) return;  // uniform per block
   init_twiddles<T, N>(tw);
   __syncthreads();
-  const int nf = nf_code == -1 ? a.S : nf_code;
+  const bool vec = nf_code == kVecMode;
+  const int nf = nf_code == -1 ? a.S : vec ? kFields : nf_code;
   const Buf base = make_buf(sel == 0 ? a.specA : sel == 1 ? a.specB : a.specC, spec_bytes<T>(a, nf));
   constexpr int tiles_main = (N * H) / PY;
   uint32_t off, es;
@@ -599,6 +638,7 @@ __global__ void __launch_bounds__((Geo<T, N>::PY * Geo<T, N>::TY))
   for (int m = 0; m < EY; ++m) eo[m] = (off + (uint32_t)(t + TY * m) * es) * (uint32_t)sizeof(cx<T>);
   const uint32_t fbytes = (uint32_t)(a.fstride * sizeof(cx<T>));
   for (int f = 0; f < nf; ++f) {
+    if (vec && (f - kSlotX) % kVecStride != 0 && f > kSlotX) continue;  // [y], [z] below
     const uint32_t so = (uint32_t)f * fbytes;
     cx<T> v[EY];
 #pragma unroll
@@ -606,6 +646,39 @@ __global__ void __launch_bounds__((Geo<T, N>::PY * Geo<T, N>::TY))
     fft_pencil<T, N, EY, FWD>(v, t, tw, lp);
 #pragma unroll
     for (int m = 0; m < EY; ++m) base.st<cx<T>>(v[m], eo[m], so);
+  }
+  if (!vec) return;
+#pragma unroll 1
+  for (int b = 0; b < 2; ++b) {
+    const uint32_t sy_off = (uint32_t)(kSlotY + kVecStride * b) * fbytes;
+    const uint32_t sz_off = (uint32_t)(kSlotZ + kVecStride * b) * fbytes;
+    if constexpr (!FWD) {
+      // Q_b -> [y] = y-inverse of i s_y Q_b and [z] = y-inverse of Q_b
+      cx<T> q[EY], w[EY];
+#pragma unroll
+      for (int m = 0; m < EY; ++m) q[m] = base.ld<cx<T>>(eo[m], sz_off);
+#pragma unroll
+      for (int m = 0; m < EY; ++m) w[m] = q[m];
+      mul_isy<T, N, EY, TY>(w, t);
+      fft_pencil<T, N, EY, false>(w, t, tw, lp);
+#pragma unroll
+      for (int m = 0; m < EY; ++m) base.st<cx<T>>(w[m], eo[m], sy_off);
+      fft_pencil<T, N, EY, false>(q, t, tw, lp);
+#pragma unroll
+      for (int m = 0; m < EY; ++m) base.st<cx<T>>(q[m], eo[m], sz_off);
+    } else {
+      // [z] <- i s_y (y-forward of F_y) + y-forward of [z]
+      cx<T> fy[EY], g[EY];
+#pragma unroll
+      for (int m = 0; m < EY; ++m) fy[m] = base.ld<cx<T>>(eo[m], sy_off);
+#pragma unroll
+      for (int m = 0; m < EY; ++m) g[m] = base.ld<cx<T>>(eo[m], sz_off);
+      fft_pencil<T, N, EY, true>(fy, t, tw, lp);
+      mul_isy<T, N, EY, TY>(fy, t);
+      fft_pencil<T, N, EY, true>(g, t, tw, lp);
+#pragma unroll
+      for (int m = 0; m < EY; ++m) base.st<cx<T>>(cadd<T>(g[m], fy[m]), eo[m], sz_off);
+    }
   }
 }
 
@@ -632,7 +705,6 @@ struct XPencil {
 
 template <int N, int PX> constexpr int x_tiles() { return (N * (N / 2)) / PX + N / PX; }
 
-__device__ __forceinline__ int sgn_idx(int j, int n) { return j < n / 2 ? j : j - n; }
 
 template <typename T>
 __device__ __forceinline__ T inv_sqrt_m(int m) {
@@ -727,6 +799,12 @@ __device__ __forceinline__ void hs_weights(const EvalArgs& a, const Buf& hs, int
   }
 }
 
+// signed index of a wavenumber along one axis, 0 on the Nyquist plane
+template <typename T, int N>
+__device__ __forceinline__ T s_axis(int k) {
+  return k == N / 2 ? (T)0 : (T)sgn_idx(k, N);
+}
+
 // unit-vector component c of k at element kx of a pencil (0 on that axis's
 // Nyquist plane)
 template <typename T, int N>
@@ -735,6 +813,11 @@ __device__ __forceinline__ T khat(int c, int kx, int ky, int kz, int m) {
   if (c == 0) return kx == N / 2 ? (T)0 : (T)sgn_idx(kx, N) * r;
   if (c == 1) return ky == N / 2 ? (T)0 : (T)sgn_idx(ky, N) * r;
   return kz == N / 2 ? (T)0 : (T)kz * r;
+}
+
+// field slot of the q-th field the back pass reads (0..3, [x]1, [z]1, [x]2, [z]2)
+__device__ __forceinline__ constexpr int back_field(int q) {
+  return q < 4 ? q : kSlotX + (q - 4) / 2 * kVecStride + ((q - 4) % 2) * (kSlotZ - kSlotX);
 }
 
 // Per-lane addressing of an x tile: element m of the lane's pencil sits at
@@ -833,18 +916,23 @@ __global__ void __launch_bounds__((PX * (N / EX)))
 #pragma unroll
     for (int m = 0; m < EX; ++m) B.st<cx<T>>(v[m], xa.vo, (uint32_t)o * fbytes + m * xa.mstride);
   }
-  // vector weighted densities: n1v_c = +i khat_c V1, n2v_c = +i khat_c V2
+  // vector weighted densities n_bv,c = +i khat_c A_b (A_1 = sum rho V1, A_2 =
+  // sum rho V2): stored as [x] = i s_x Q_b and [z] = Q_b with Q_b = A_b / |j|
+  // (the y and z components are formed by the y and z passes)
 #pragma unroll
   for (int b = 0; b < 2; ++b) {
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
+    for (int c = 0; c < 2; ++c) {
       cx<T> v[EX];
 #pragma unroll
-      for (int m = 0; m < EX; ++m)
-        v[m] = cscale<T>(cmuli<T>(acc[4 + b][m]), khat<T, N>(c, t + TX * m, pc.ky, pc.kz, mm[m]) * sc);
+      for (int m = 0; m < EX; ++m) {
+        const cx<T> q = cscale<T>(acc[4 + b][m], inv_sqrt_m<T>(mm[m]) * sc);
+        v[m] = c == 0 ? cmuli<T>(cscale<T>(q, s_axis<T, N>(t + TX * m))) : q;
+      }
       fft_pencil<T, N, EX, false>(v, t, tw, lp);
+      const int slot = (c == 0 ? kSlotX : kSlotZ) + kVecStride * b;
 #pragma unroll
-      for (int m = 0; m < EX; ++m) B.st<cx<T>>(v[m], xa.vo, (uint32_t)(4 + 3 * b + c) * fbytes + m * xa.mstride);
+      for (int m = 0; m < EX; ++m) B.st<cx<T>>(v[m], xa.vo, (uint32_t)slot * fbytes + m * xa.mstride);
     }
   }
 }
@@ -893,28 +981,33 @@ __global__ void __launch_bounds__((PX * (N / EX)))
   cx<T> out[CH][EX];
   cx<T> b0[EX], b1[EX];
   if (hs_on) {
+    // F[0..3]: scalar derivative spectra; F[4 + b] = i (khat . F_bv) =
+    // (i s_x F_bx + [z]) / |j| (see the field-slot layout)
     cx<T> F[6][EX];
 #pragma unroll
     for (int m = 0; m < EX; ++m) b0[m] = B.ld<cx<T>>(xa.vo, m * xa.mstride);
 #pragma unroll
-    for (int q = 0; q < kFields; ++q) {
+    for (int q = 0; q < kBackFields; ++q) {
       cx<T>* cur = (q & 1) ? b1 : b0;
       cx<T>* nxt = (q & 1) ? b0 : b1;
-      if (q + 1 < kFields) {
+      if (q + 1 < kBackFields) {
+        const int f1 = back_field(q + 1);
 #pragma unroll
-        for (int m = 0; m < EX; ++m) nxt[m] = B.ld<cx<T>>(xa.vo, (uint32_t)(q + 1) * fbytes + m * xa.mstride);
+        for (int m = 0; m < EX; ++m) nxt[m] = B.ld<cx<T>>(xa.vo, (uint32_t)f1 * fbytes + m * xa.mstride);
       }
       fft_pencil<T, N, EX, true>(cur, t, tw, lp);
-      if (q < 4) {
+      const int f = back_field(q);
+      if (f < 4) {
 #pragma unroll
-        for (int m = 0; m < EX; ++m) F[q][m] = cur[m];
+        for (int m = 0; m < EX; ++m) F[f][m] = cur[m];
       } else {
-        const int b = (q - 4) / 3, c = (q - 4) % 3;
+        const int b = (f - kSlotX) / kVecStride;
+        const bool xs = (f - kSlotX) % kVecStride == 0;
 #pragma unroll
         for (int m = 0; m < EX; ++m) {
-          const T u = khat<T, N>(c, t + TX * m, pc.ky, pc.kz, mm[m]);
-          if (c == 0) F[4 + b][m] = cscale<T>(cur[m], u);
-          else cfma<T>(F[4 + b][m], cur[m], u);
+          const T r = inv_sqrt_m<T>(mm[m]);
+          if (xs) F[4 + b][m] = cscale<T>(cmuli<T>(cur[m]), s_axis<T, N>(t + TX * m) * r);
+          else cfma<T>(F[4 + b][m], cur[m], r);
         }
       }
     }
@@ -931,9 +1024,10 @@ __global__ void __launch_bounds__((PX * (N / EX)))
         cfma<T>(s0, F[2][m], ar);
         cx<T> u = cscale<T>(s0, j0);
         cfma<T>(u, F[3][m], w3);
+        // -i V2 (D1 / (4 pi R) + D2) with F[4 + b] = i D_b
         cx<T> dv = F[5][m];
         cfma<T>(dv, F[4][m], i4);
-        cfma<T>(u, cmulmi<T>(dv), v2);
+        cfma<T>(u, dv, -v2);
         out[c][m] = u;
       }
     }
@@ -1064,17 +1158,22 @@ __global__ void __launch_bounds__((PX * (N / EX)))
         }
       }
     }
+    // F[4 + b] = i (khat . F_bv) = (i s_x F_bx + [z]) / |j| (field-slot layout)
 #pragma unroll
     for (int b = 0; b < 2; ++b) {
-#pragma unroll 1
-      for (int c = 0; c < 3; ++c) {
-        cx<T> v[EX];
 #pragma unroll
-        for (int m = 0; m < EX; ++m) v[m] = B.ld<cx<T>>(eo[m], (uint32_t)(4 + 3 * b + c) * fbytes);
+      for (int c = 0; c < 2; ++c) {
+        cx<T> v[EX];
+        const int slot = (c == 0 ? kSlotX : kSlotZ) + kVecStride * b;
+#pragma unroll
+        for (int m = 0; m < EX; ++m) v[m] = B.ld<cx<T>>(eo[m], (uint32_t)slot * fbytes);
         fft_pencil<T, N, EX, true>(v, t, tw, lp);
 #pragma unroll
-        for (int m = 0; m < EX; ++m)
-          cfma<T>(F[4 + b][m], v[m], c == 0 ? ks.ux[m] : c == 1 ? ks.uy[m] : ks.uz[m]);
+        for (int m = 0; m < EX; ++m) {
+          const T r = inv_sqrt_m<T>(ks.mm[m]);
+          if (c == 0) cfma<T>(F[4 + b][m], cmuli<T>(v[m]), s_axis<T, N>(t + TX * m) * r);
+          else cfma<T>(F[4 + b][m], v[m], r);
+        }
       }
     }
   }
@@ -1121,9 +1220,10 @@ __global__ void __launch_bounds__((PX * (N / EX)))
             cfma<T>(sc0, F[2][m], ar);
             cfma<T>(u, sc0, j0);
             cfma<T>(u, F[3][m], w3);
+            // -i V2 (D1 / (4 pi R) + D2) with F[4 + b] = i D_b
             cx<T> dv = F[5][m];
             cfma<T>(dv, F[4][m], i4);
-            cfma<T>(u, cmulmi<T>(dv), v2);
+            cfma<T>(u, dv, -v2);
           }
           v[m] = cscale<T>(u, sc);
         }

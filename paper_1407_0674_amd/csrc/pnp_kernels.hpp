@@ -9,6 +9,20 @@ constexpr int kMaxSpecies = 8;
 constexpr int kMaxPairs = kMaxSpecies * (kMaxSpecies + 1) / 2;
 constexpr int kFields = 10;  // n0, n1, n2, n3, n1v(x,y,z), n2v(x,y,z)
 
+// Storage of the two vector weighted densities n_bv (b = 1, 2) and of their
+// derivative fields.  n_bv,c(k) = i s_c Q_b(k) with Q_b = A_b / |j| the
+// spectrum of a real field and s_c the signed index along axis c (0 on that
+// axis's Nyquist plane), so each component is formed in the pass that
+// transforms its own axis.  Field slots 4..6 hold vector 1, 7..9 vector 2:
+//   after the x-forward pass:  [x] = i s_x Q_b, [z] = Q_b        ([y] unused)
+//   after the y-inverse pass:  [x], [y] = i s_y Q_b, [z] = Q_b    (z multiply
+//                              by i s_z is applied inside the z pass)
+//   after the z derivative pass: [x] = F_x, [y] = F_y, [z] = i s_z F_z
+//   after the y-forward pass:  [x] = F_x, [z] = i s_y F_y + i s_z F_z
+// and the back pass forms i |j| (khat . F) = i s_x F_x + [z].
+constexpr int kSlotX = 4, kSlotY = 5, kSlotZ = 6, kVecStride = 3;
+constexpr int kBackFields = 8;  // fields the back pass reads: 0..3, 4, 6, 7, 9
+
 // status word bits (word 0); word 1 holds the smallest offending flat index
 enum : uint32_t { kStPacking = 1u, kStNonFinite = 2u, kStOverflow = 4u };
 
@@ -21,7 +35,7 @@ struct EvalArgs {
   int32_t np;         // S (S + 1) / 2
   int32_t nreal;      // fields written by the real-space output pass
   int32_t final_mode; // 1: add constant, write mu and exp(-mu); 0: plain real output
-  int32_t pad0;
+  uint32_t zmul_mask; // real-output pass: fields whose z spectrum is multiplied by i s_z first
   int64_t fstride;    // complex elements per spectral field (n*n*(n/2) + n*n)
   double inv_n3;      // 1 / n^3
   double kscale;      // 2 pi / L: |k| = kscale * sqrt(jx^2 + jy^2 + jz^2)
