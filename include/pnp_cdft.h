@@ -148,6 +148,53 @@ pnp_status pnp_cdft_mu_ex(pnp_ctx ctx, const pnp_grid* grid, int32_t S,
                           void* workspace, size_t workspace_bytes, void* stream);
 
 /*
+ * Excess free energies [k_B T] of the densities rho (Sec. 2.3), from one
+ * per-term evaluation (the same operator as pnp_cdft_mu_ex):
+ *   F_hs = h^3 sum_r Phi_hs(n(r))                          (Sec. 2.3.1)
+ *   F_el = h^3 sum_i sum_r drho_i (beta mu_el_i[bulk] - 1/2 (C (*) drho)_i)
+ *        = h^3/2 sum_i sum_r drho_i (beta mu_el_i + beta mu_el_i[bulk])  (Sec. 2.3.4)
+ *   F_sh = 1/2 beta h^3 sum_ij sum_r rho_i (u_ij (*) rho_j)
+ *        = h^3 / (2 sw_prefactor) sum_i sum_r rho_i beta mu_sh_i       (Sec. 2.3.2)
+ * with drho = rho - rho_bulk (the constant F_el[bulk] is dropped); terms
+ * that are switched off contribute 0.  Sums run in a fixed order, so the
+ * result is reproducible bit for bit.
+ *   energies  host, 4 values: F_hs, F_el, F_sh, total
+ *   mu3       device, float64 [3][S][N]: receives the per-term beta mu_ex
+ *   workspace >= pnp_workspace_bytes() with params->per_term = 1
+ * Errors: as pnp_cdft_mu_ex.  The call waits for its result.
+ */
+pnp_status pnp_free_energy(pnp_ctx ctx, const pnp_grid* grid, int32_t S,
+                           const pnp_species* species, const double* rho, double T,
+                           const pnp_params* params, double* energies, double* mu3,
+                           void* workspace, size_t workspace_bytes, void* stream);
+
+/*
+ * Equilibrium densities of the grand ensemble at the bulk chemical
+ * potentials (the cDFT state Sec. 3.2 solves for before the PNP iteration):
+ *   rho_i(r) = rho_bulk_i exp(beta mu_b,i - beta mu_ex,i[rho](r) - beta V_i(r)),
+ * with beta mu_b = pnp_bulk_mu_ex, by Picard iteration with mixing lambda
+ * (the relaxation of Sec. 3.2),
+ *   rho <- (1 - lambda) rho + lambda rho_bulk exp(beta mu_b - beta mu_ex[rho] - beta V),
+ * until max_i max_r |rho_new - rho| / rho_bulk_i <= tol or max_iter steps.
+ *   beta_v   device, float64 [S][N] external potential [k_B T], or NULL
+ *   rho      device, float64 [S][N]: in the initial guess, out the last iterate
+ *   mu_ex    device, float64 [S][N]: out beta mu_ex of the densities before
+ *            the last update
+ *   iters, residual  host out: steps taken and the last residual
+ *   lambda in (0, 1], tol >= 0, max_iter >= 1; rho_bulk > 0 for every species
+ *   workspace >= pnp_workspace_bytes() (params->per_term = 0)
+ * Plain Picard iteration converges for moderate coupling; dense or strongly
+ * correlated fluids need a small lambda.  Errors: as pnp_cdft_mu_ex (a
+ * packing error stops the iteration and reports the step in iters).
+ * The call waits for every step.
+ */
+pnp_status pnp_equilibrium(pnp_ctx ctx, const pnp_grid* grid, int32_t S,
+                           const pnp_species* species, double T, const pnp_params* params,
+                           const double* beta_v, double* rho, double* mu_ex, double lambda,
+                           double tol, int32_t max_iter, int32_t* iters, double* residual,
+                           void* workspace, size_t workspace_bytes, void* stream);
+
+/*
  * The weighted densities of Sec. 2.3.1 alone, in real space.
  *   n_out  device, float64 [10][N] in the order n0, n1, n2, n3, n1v(x,y,z), n2v(x,y,z)
  * Same errors as pnp_cdft_mu_ex (no packing check).
@@ -306,6 +353,9 @@ pnp_status pnp_debug_copy(pnp_ctx ctx, const void* src, void* dst, size_t bytes,
  */
 enum { PNP_NUM_PASSES = 10 };
 pnp_status pnp_profile_enable(pnp_ctx ctx, int32_t enable);
+/* Record events only around the passes whose bit (1 << pass id) is set in
+ * mask (default: all); fewer events disturb the timed stream less. */
+pnp_status pnp_profile_select(pnp_ctx ctx, uint32_t mask);
 pnp_status pnp_profile_read(pnp_ctx ctx, double* ms, int32_t* launches, int32_t n, int32_t reset);
 
 #ifdef __cplusplus

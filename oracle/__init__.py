@@ -32,6 +32,7 @@ from .fmt import phi_hs, dphi_hs
 from .direct import correlate_direct, convolve_direct
 from .mu_ex import mu_ex, weighted_densities, free_energy
 from .relax import relax_densities
+from .equilibrium import picard, bulk_mu_ex
 
 STATUS = {
     "units": "pinned: tests/test_oracle_units.py (Table 1 beta and l_B)",
@@ -41,6 +42,7 @@ STATUS = {
     "direct": "pinned: tests/test_oracle_direct.py (brute-force loops, FFT route)",
     "mu_ex": "pinned: tests/test_oracle_mu_ex.py (bulk closed forms, FD consistency, symmetry)",
     "relax": "pinned: tests/test_oracle_relax.py (lambda 0 and 1, bulk fixed point)",
+    "equilibrium": "pinned: tests/test_oracle_equilibrium.py (bulk fixed point, dilute Boltzmann limit, self-consistency)",
 }
 
 __all__ = [
@@ -48,5 +50,5 @@ __all__ = [
     "ball_ft", "shell_ft", "shell_vec_ft", "r_ball_ft", "inv_r_ball_ft", "j0", "j1",
     "j1_over_x", "Operator", "build_operator", "real_space_kernel", "wavevectors",
     "phi_hs", "dphi_hs", "correlate_direct", "convolve_direct", "mu_ex",
-    "weighted_densities", "free_energy", "relax_densities", "STATUS",
+    "weighted_densities", "free_energy", "relax_densities", "picard", "bulk_mu_ex", "STATUS",
 ]

@@ -26,7 +26,7 @@ EXPORTED = [
     "pnp_create", "pnp_destroy", "pnp_last_error", "pnp_supported_size", "pnp_workspace_bytes",
     "pnp_cdft_mu_ex", "pnp_weighted_densities", "pnp_batch_mu_ex", "pnp_read_status",
     "pnp_relax_densities", "pnp_debug_rfft3", "pnp_debug_copy", "pnp_profile_enable",
-    "pnp_profile_read", "pnp_bulk_mu_ex", "pnp_session_bytes", "pnp_pool_create", "pnp_pool_destroy",
+    "pnp_profile_select", "pnp_profile_read", "pnp_free_energy", "pnp_equilibrium", "pnp_bulk_mu_ex", "pnp_session_bytes", "pnp_pool_create", "pnp_pool_destroy",
     "pnp_pool_usage", "pnp_session_open", "pnp_session_step", "pnp_session_view", "pnp_session_close",
 ]
 
@@ -98,6 +98,13 @@ def load_library():
                                            ctypes.POINTER(SpeciesC), P, ctypes.POINTER(ParamsC), P,
                                            P, ctypes.c_size_t, P]
     lib.pnp_batch_mu_ex.argtypes = [P, ctypes.c_int32, ctypes.POINTER(RequestC), P]
+    lib.pnp_equilibrium.argtypes = [P, ctypes.POINTER(Grid), ctypes.c_int32, ctypes.POINTER(SpeciesC),
+                                    ctypes.c_double, ctypes.POINTER(ParamsC), P, P, P, ctypes.c_double,
+                                    ctypes.c_double, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
+                                    ctypes.POINTER(ctypes.c_double), P, ctypes.c_size_t, P]
+    lib.pnp_free_energy.argtypes = [P, ctypes.POINTER(Grid), ctypes.c_int32, ctypes.POINTER(SpeciesC), P,
+                                    ctypes.c_double, ctypes.POINTER(ParamsC), ctypes.POINTER(ctypes.c_double),
+                                    P, P, ctypes.c_size_t, P]
     lib.pnp_read_status.argtypes = [P, P, P]
     lib.pnp_relax_densities.argtypes = [P, ctypes.POINTER(Grid), ctypes.c_int32,
                                         ctypes.POINTER(SpeciesC), P, P,
@@ -124,6 +131,7 @@ def load_library():
                                      ctypes.POINTER(P), ctypes.POINTER(ctypes.c_int64)]
     lib.pnp_session_close.argtypes = [P, ctypes.c_int64]
     lib.pnp_profile_enable.argtypes = [P, ctypes.c_int32]
+    lib.pnp_profile_select.argtypes = [P, ctypes.c_uint32]
     lib.pnp_profile_read.argtypes = [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32),
                                      ctypes.c_int32, ctypes.c_int32]
     for name in EXPORTED:
@@ -240,6 +248,39 @@ class Evaluator:
         self._check(st)
         return out, (slot if slotboom else None)
 
+    def free_energy(self, problem, rho, precision=None):
+        """{"hs", "el", "sh", "total"} excess free energies [k_B T] and the
+        per-term beta mu_ex [3][S][n][n][n] they came from."""
+        torch = _torch()
+        m = _Marshal(problem, True, 0, precision)
+        mu3 = torch.empty((3, m.S, problem.n, problem.n, problem.n), dtype=torch.float64, device=rho.device)
+        nb = self.workspace_bytes(problem, True, precision)
+        ws = self.workspace(nb)
+        out = (ctypes.c_double * 4)()
+        self._check(self.lib.pnp_free_energy(self.ctx, ctypes.byref(m.grid), m.S, m.species,
+                                             self._dev(rho, "rho"), m.T, ctypes.byref(m.params), out,
+                                             self._dev(mu3, "mu3"), ctypes.c_void_p(ws.data_ptr()),
+                                             ctypes.c_size_t(ws.numel()), self._stream()))
+        return {"hs": out[0], "el": out[1], "sh": out[2], "total": out[3]}, mu3
+
+    def equilibrium(self, problem, rho, beta_v=None, lam=0.1, tol=1e-10, max_iter=200, precision=None):
+        """Picard solve of the grand-ensemble equilibrium in place on `rho`;
+        returns (mu_ex of the last evaluated densities, iterations, residual)."""
+        torch = _torch()
+        m = _Marshal(problem, False, 0, precision)
+        mu = torch.empty_like(rho)
+        nb = self.workspace_bytes(problem, False, precision)
+        ws = self.workspace(nb)
+        it = ctypes.c_int32()
+        res = ctypes.c_double()
+        self._check(self.lib.pnp_equilibrium(
+            self.ctx, ctypes.byref(m.grid), m.S, m.species, m.T, ctypes.byref(m.params),
+            self._dev(beta_v, "beta_v") if beta_v is not None else ctypes.c_void_p(0),
+            self._dev(rho, "rho"), self._dev(mu, "mu_ex"), float(lam), float(tol), int(max_iter),
+            ctypes.byref(it), ctypes.byref(res), ctypes.c_void_p(ws.data_ptr()), ctypes.c_size_t(ws.numel()),
+            self._stream()))
+        return mu, int(it.value), float(res.value)
+
     def weighted_densities(self, problem, rho, precision=None):
         torch = _torch()
         m = _Marshal(problem, False, 0, precision)
@@ -288,7 +329,11 @@ class Evaluator:
         self._check(st)
         return mus, sls, [int(reqs[r].status) for r in range(count)]
 
-    def profile(self, enable: bool = True):
+    def profile(self, enable: bool = True, passes=None):
+        """Pass timing on/off; `passes`: names of the passes that record
+        events (default all)."""
+        mask = 0xFFFFFFFF if passes is None else sum(1 << PASS_NAMES.index(p) for p in passes)
+        self._check(self.lib.pnp_profile_select(self.ctx, mask))
         self._check(self.lib.pnp_profile_enable(self.ctx, int(bool(enable))))
 
     def profile_read(self, reset: bool = True):

@@ -28,6 +28,7 @@ struct pnp_ctx_s {
   size_t arena_pos = 0;
   // pass timing
   bool prof = false;
+  uint32_t prof_mask = ~0u;                        // passes that record events
   std::vector<hipEvent_t> ev_pool;                 // free events
   std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_open;  // recorded, unread
   double prof_ms[PNP_NUM_PASSES] = {0};
@@ -44,6 +45,7 @@ constexpr double kBoltzmannEv = kBoltzmann / kElementaryCharge;  // eV/K
 const double kCoulombEvNm = kElementaryCharge / (4.0 * M_PI * kVacuumPermittivity) * 1e9;
 
 constexpr size_t kAlign = 256;
+constexpr int kEnergyBlocks = 1024;  // workgroups of the pair-energy reduction
 inline size_t up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 pnp_status fail(pnp_ctx c, pnp_status s, const std::string& m) {
@@ -69,7 +71,7 @@ struct PassTimer {
   int id = -1;
   hipEvent_t e0 = nullptr;
   void begin(int pass) {
-    if (!c || !c->prof) return;
+    if (!c || !c->prof || !((c->prof_mask >> pass) & 1u)) return;
     id = pass;
     e0 = take_event(c);
     if (e0) hipEventRecord(e0, s);
@@ -108,7 +110,7 @@ struct Derived {
 };
 
 struct Layout {
-  size_t status, hs, pair, pair2, A, B, C, total;
+  size_t status, energy, hs, pair, pair2, A, B, C, total;
   long fstride;
   int M;
 };
@@ -124,6 +126,9 @@ Layout layout_of(int n, int S, int precision, bool hs, bool pairs, bool per_term
   const size_t prow = (size_t)S * padded_species(S);
   size_t o = 0;
   L.status = o; o = up(o + 64);
+  // free-energy partial sums: one per derivative-pass workgroup (at most n^2),
+  // kEnergyBlocks pairs from the pair-energy pass, and the four results
+  L.energy = o; o = up(o + sizeof(double) * ((size_t)n * n + 2 * kEnergyBlocks + 4));
   L.hs = o; if (precision == PNP_FP64) o = up(o + (size_t)L.M * 4 * S * ts);  // FP32 weights live in registers
   L.pair = o; if (pairs) o = up(o + (size_t)L.M * prow * ts);
   L.pair2 = o; if (pairs && per_term) o = up(o + (size_t)L.M * prow * ts);
@@ -289,8 +294,9 @@ struct Ops {
   void (*zfwd)(const EvalArgs*, int, hipStream_t);
   void (*ystep)(const EvalArgs*, int, int, int, bool, hipStream_t);
   void (*xfwd)(const EvalArgs*, int, hipStream_t);
-  void (*zderiv)(const EvalArgs*, int, hipStream_t);
+  void (*zderiv)(const EvalArgs*, int, bool, hipStream_t);
   void (*xback)(const EvalArgs*, int, int, hipStream_t);
+  int zderiv_tiles;  // workgroups of the derivative pass per instance
   void (*zinv)(const EvalArgs*, int, int, hipStream_t);
   void (*xplain)(const EvalArgs*, int, int, bool, hipStream_t);
   void (*xport)(const EvalArgs*, int, double*, int, hipStream_t);
@@ -315,8 +321,11 @@ template <typename T, int N> struct Launch {
   static void xfwd(const EvalArgs* a, int count, hipStream_t s) {
     hipLaunchKernelGGL((k_xfwd<T, N>), dim3(count * G::tiles_x), dim3(G::PX * G::TX), 0, s, a);
   }
-  static void zderiv(const EvalArgs* a, int count, hipStream_t s) {
-    hipLaunchKernelGGL((k_zderiv<T, N>), dim3(count * GeoD<T, N>::tiles), dim3(GeoD<T, N>::RDD * GeoD<T, N>::TZD), 0, s, a);
+  // phi: also sum Phi_hs per workgroup (free-energy calls)
+  static void zderiv(const EvalArgs* a, int count, bool phi, hipStream_t s) {
+    const dim3 g(count * GeoD<T, N>::tiles), b(GeoD<T, N>::RDD * GeoD<T, N>::TZD);
+    if (phi) hipLaunchKernelGGL((k_zderiv<T, N, true>), g, b, 0, s, a);
+    else hipLaunchKernelGGL((k_zderiv<T, N, false>), g, b, 0, s, a);
   }
   // maxS: the largest species count among the launch's instances
   static void xback(const EvalArgs* a, int count, int maxS, hipStream_t s) {
@@ -349,7 +358,7 @@ template <typename T, int N> struct Launch {
     const int blocks = (int)std::min<long>((total + 255) / 256, 4096);
     hipLaunchKernelGGL((k_export<T, N>), dim3(blocks), dim3(256), 0, s, a, nf, buf, to_numpy);
   }
-  static constexpr Ops ops{tables, zfwd, ystep, xfwd, zderiv, xback, zinv, xplain, xport};
+  static constexpr Ops ops{tables, zfwd, ystep, xfwd, zderiv, xback, GeoD<T, N>::tiles, zinv, xplain, xport};
 };
 
 template <typename T>
@@ -385,7 +394,7 @@ void run_sequence(pnp_ctx c, const Ops* op, const EvalArgs* ea, const TableArgs*
   if (hs_any) {
     pt.begin(3); op->xfwd(ea, count, s); pt.end();
     pt.begin(4); op->ystep(ea, count, 1, kVecMode, false, s); pt.end();
-    pt.begin(5); op->zderiv(ea, count, s); pt.end();
+    pt.begin(5); op->zderiv(ea, count, false, s); pt.end();
     pt.begin(6); op->ystep(ea, count, 1, kVecMode, true, s); pt.end();
   }
   pt.begin(7); op->xback(ea, count, ch, s); pt.end();
@@ -398,6 +407,66 @@ void run_sequence(pnp_ctx c, const Ops* op, const EvalArgs* ea, const TableArgs*
 // ===========================================================================
 // C ABI
 // ===========================================================================
+// The per-term evaluation: mu3 = [hs, el, sh] ([3][S][N]) and slot =
+// exp(-(hs + el + sh)); phi_part (or null) receives the derivative pass's
+// per-workgroup sums of Phi_hs.
+static pnp_status enqueue_per_term(pnp_ctx ctx, const Derived& d, const pnp_grid* g, const pnp_species* sp,
+                          const double* rho, const pnp_params* p, const Layout& L, char* w, double* mu,
+                          double* slot, double* phi_part, hipStream_t s) {
+  const int S = d.S;
+  const bool pairs = d.ec || d.sw;
+  const Ops* op = ops_for(d.precision, d.n);
+  const double sw_c = p->sw_prefactor;
+  const int ch = S;
+  const long n3 = (long)d.n * d.n * d.n;
+  // tables: HS (+ EC pairs into pair), SW pairs into pair2
+  TableArgs ta[2];
+  fill_table_args(ta[0], d, sp, g->h, sw_c, d.ec, false, w + L.hs, pairs ? w + L.pair : nullptr, L.M);
+  fill_table_args(ta[1], d, sp, g->h, sw_c, false, d.sw, w + L.hs, pairs ? w + L.pair2 : nullptr,
+                  L.M);
+  // four argument records: forward half, hs-only, el-only, sh-only
+  EvalArgs ea[4];
+  for (int k = 0; k < 4; ++k) {
+    fill_eval_args(ea[k], d, sp, L, w, rho);
+    ea[k].slot = nullptr;
+    ea[k].phi_part = phi_part;
+  }
+  ea[0].out = mu;
+  ea[1].out = mu; ea[1].pair_on = 0;
+  for (int i = 0; i < S; ++i) ea[1].cfin[i] = 0.0;
+  ea[2].out = mu + (long)S * n3; ea[2].hs_on = 0; ea[2].pair_on = d.ec;
+  ea[3].out = mu + 2L * S * n3; ea[3].hs_on = 0; ea[3].pair_on = d.sw; ea[3].pair_tab = w + L.pair2;
+  for (int i = 0; i < S; ++i) ea[3].cfin[i] = 0.0;
+  if (!d.ec) for (int i = 0; i < S; ++i) ea[2].cfin[i] = 0.0;
+  if (!d.hs) ea[1].hs_on = 0;
+  const TableArgs* dta = (const TableArgs*)upload(ctx, ta, sizeof(ta), s);
+  const EvalArgs* dea = (const EvalArgs*)upload(ctx, ea, sizeof(ea), s);
+  if (!dta || !dea) return device_check(ctx, "argument upload");
+  PassTimer pt{ctx, s};
+  pt.begin(0);
+  op->tables(dta, 1, L.M, S, s);
+  if (d.sw) op->tables(dta + 1, 1, L.M, S, s);
+  pt.end();
+  pt.begin(1); op->zfwd(dea, 1, s); pt.end();
+  pt.begin(2); op->ystep(dea, 1, 0, -1, true, s); pt.end();
+  if (d.hs) {
+    pt.begin(3); op->xfwd(dea, 1, s); pt.end();
+    pt.begin(4); op->ystep(dea, 1, 1, kVecMode, false, s); pt.end();
+    pt.begin(5); op->zderiv(dea, 1, phi_part != nullptr, s); pt.end();
+    pt.begin(6); op->ystep(dea, 1, 1, kVecMode, true, s); pt.end();
+  }
+  for (int k = 1; k < 4; ++k) {
+    pt.begin(7); op->xback(dea + k, 1, ch, s); pt.end();
+    pt.begin(8); op->ystep(dea + k, 1, 2, -1, false, s); pt.end();
+    pt.begin(9); op->zinv(dea + k, 1, 2, s); pt.end();
+  }
+  const long sn3 = (long)S * n3;
+  const int blocks = (int)std::min<long>((sn3 + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_sum_exp, dim3(blocks), dim3(256), 0, s, (const double*)mu, slot, sn3,
+                     (uint32_t*)(w + L.status));
+  return device_check(ctx, "launch");
+}
+
 extern "C" {
 
 pnp_status pnp_create(int device, pnp_ctx* out) {
@@ -431,6 +500,12 @@ void pnp_destroy(pnp_ctx c) {
 pnp_status pnp_profile_enable(pnp_ctx c, int32_t enable) {
   if (!c) return PNP_E_ARG;
   c->prof = enable != 0;
+  return PNP_OK;
+}
+
+pnp_status pnp_profile_select(pnp_ctx c, uint32_t mask) {
+  if (!c) return PNP_E_ARG;
+  c->prof_mask = mask;
   return PNP_OK;
 }
 
@@ -503,55 +578,120 @@ pnp_status pnp_cdft_mu_ex(pnp_ctx ctx, const pnp_grid* g, int32_t S, const pnp_s
     if (!dta || !dea) return device_check(ctx, "argument upload");
     run_sequence(ctx, op, dea, dta, 1, L.M, d.hs, ch, s);
   } else {
-    // tables: HS (+ EC pairs into pair), SW pairs into pair2
-    TableArgs ta[2];
-    fill_table_args(ta[0], d, sp, g->h, sw_c, d.ec, false, w + L.hs, pairs ? w + L.pair : nullptr, L.M);
-    fill_table_args(ta[1], d, sp, g->h, sw_c, false, d.sw, w + L.hs, pairs ? w + L.pair2 : nullptr,
-                    L.M);
-    // four argument records: forward half, hs-only, el-only, sh-only
-    EvalArgs ea[4];
-    for (int k = 0; k < 4; ++k) {
-      fill_eval_args(ea[k], d, sp, L, w, rho);
-      ea[k].slot = nullptr;
-    }
-    ea[0].out = mu;
-    ea[1].out = mu; ea[1].pair_on = 0;
-    for (int i = 0; i < S; ++i) ea[1].cfin[i] = 0.0;
-    ea[2].out = mu + (long)S * n3; ea[2].hs_on = 0; ea[2].pair_on = d.ec;
-    ea[3].out = mu + 2L * S * n3; ea[3].hs_on = 0; ea[3].pair_on = d.sw; ea[3].pair_tab = w + L.pair2;
-    for (int i = 0; i < S; ++i) ea[3].cfin[i] = 0.0;
-    if (!d.ec) for (int i = 0; i < S; ++i) ea[2].cfin[i] = 0.0;
-    if (!d.hs) ea[1].hs_on = 0;
-    const TableArgs* dta = (const TableArgs*)upload(ctx, ta, sizeof(ta), s);
-    const EvalArgs* dea = (const EvalArgs*)upload(ctx, ea, sizeof(ea), s);
-    if (!dta || !dea) return device_check(ctx, "argument upload");
-    PassTimer pt{ctx, s};
-    pt.begin(0);
-    op->tables(dta, 1, L.M, S, s);
-    if (d.sw) op->tables(dta + 1, 1, L.M, S, s);
-    pt.end();
-    pt.begin(1); op->zfwd(dea, 1, s); pt.end();
-    pt.begin(2); op->ystep(dea, 1, 0, -1, true, s); pt.end();
-    if (d.hs) {
-      pt.begin(3); op->xfwd(dea, 1, s); pt.end();
-      pt.begin(4); op->ystep(dea, 1, 1, kVecMode, false, s); pt.end();
-      pt.begin(5); op->zderiv(dea, 1, s); pt.end();
-      pt.begin(6); op->ystep(dea, 1, 1, kVecMode, true, s); pt.end();
-    }
-    for (int k = 1; k < 4; ++k) {
-      pt.begin(7); op->xback(dea + k, 1, ch, s); pt.end();
-      pt.begin(8); op->ystep(dea + k, 1, 2, -1, false, s); pt.end();
-      pt.begin(9); op->zinv(dea + k, 1, 2, s); pt.end();
-    }
-    const long sn3 = (long)S * n3;
-    const int blocks = (int)std::min<long>((sn3 + 255) / 256, 4096);
-    hipLaunchKernelGGL(k_sum_exp, dim3(blocks), dim3(256), 0, s, (const double*)mu, slot, sn3,
-                       (uint32_t*)(w + L.status));
+    st = enqueue_per_term(ctx, d, g, sp, rho, p, L, w, mu, slot, nullptr, s);
+    if (st != PNP_OK) return st;
   }
   st = device_check(ctx, "launch");
   if (st != PNP_OK) return st;
   if (p->flags & PNP_FLAG_ASYNC) return PNP_OK;
   return read_status(ctx, w + L.status, s);
+}
+
+pnp_status pnp_free_energy(pnp_ctx ctx, const pnp_grid* g, int32_t S, const pnp_species* sp, const double* rho,
+                           double T, const pnp_params* p, double* energies, double* mu3, void* ws,
+                           size_t ws_bytes, void* stream) {
+  Derived d;
+  pnp_status st = validate(ctx, g, S, sp, T, p, d, true);
+  if (st != PNP_OK) return st;
+  if (!rho || !mu3 || !ws || !energies) return fail(ctx, PNP_E_ARG, "null pointer");
+  if ((uintptr_t)ws % kAlign) return fail(ctx, PNP_E_ARG, "workspace must be 256-byte aligned");
+  const bool pairs = d.ec || d.sw;
+  const Layout L = layout_of(d.n, S, d.precision, d.hs, pairs, true);
+  if (ws_bytes < L.total) return fail(ctx, PNP_E_NOMEM, "workspace too small: need " + std::to_string(L.total));
+  if (hipSetDevice(ctx->device) != hipSuccess) return device_check(ctx, "set device");
+  hipStream_t s = (hipStream_t)stream;
+  char* w = (char*)ws;
+  double* phi_part = (double*)(w + L.energy);
+  double* part = phi_part + (size_t)d.n * d.n;
+  double* res = part + 2 * kEnergyBlocks;
+  st = enqueue_per_term(ctx, d, g, sp, rho, p, L, w, mu3, nullptr, d.hs ? phi_part : nullptr, s);
+  if (st != PNP_OK) return st;
+  const long n3 = (long)d.n * d.n * d.n;
+  double rb[2 * kMaxSpecies];
+  for (int i = 0; i < S; ++i) {
+    rb[2 * i] = sp[i].rho_bulk;
+    rb[2 * i + 1] = d.ec ? sp[i].mu_el_bulk : 0.0;
+  }
+  const double* drb = (const double*)upload(ctx, rb, sizeof(double) * 2 * S, s);
+  if (!drb) return device_check(ctx, "argument upload");
+  hipLaunchKernelGGL(k_energy_part, dim3(kEnergyBlocks), dim3(256), 0, s, rho, (const double*)mu3, n3, (int)S, drb,
+                     part);
+  const double h3 = g->h * g->h * g->h;
+  // F_el = h^3/2 sum drho (mu_el + mu_el[bulk]); F_sh = h^3 / (2 c_sw) sum rho mu_sh (Sec. 2.3.2, 2.3.4)
+  const double el_scale = d.ec ? 0.5 * h3 : 0.0;
+  const double sh_scale = (d.sw && p->sw_prefactor != 0.0) ? h3 / (2.0 * p->sw_prefactor) : 0.0;
+  const Ops* op = ops_for(d.precision, d.n);
+  hipLaunchKernelGGL(k_energy_final, dim3(1), dim3(256), 0, s, (const double*)phi_part,
+                     d.hs ? op->zderiv_tiles : 0, (const double*)part, kEnergyBlocks, h3, el_scale, sh_scale, res);
+  st = device_check(ctx, "energy launch");
+  if (st != PNP_OK) return st;
+  if (hipMemcpyAsync(energies, res, 4 * sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess)
+    return device_check(ctx, "energy read");
+  return read_status(ctx, w + L.status, s);
+}
+
+pnp_status pnp_equilibrium(pnp_ctx ctx, const pnp_grid* g, int32_t S, const pnp_species* sp, double T,
+                           const pnp_params* p, const double* beta_v, double* rho, double* mu, double lambda,
+                           double tol, int32_t max_iter, int32_t* iters, double* residual, void* ws,
+                           size_t ws_bytes, void* stream) {
+  Derived d;
+  pnp_status st = validate(ctx, g, S, sp, T, p, d, true);
+  if (st != PNP_OK) return st;
+  if (!rho || !mu || !ws || !iters || !residual) return fail(ctx, PNP_E_ARG, "null pointer");
+  if (!(lambda > 0.0 && lambda <= 1.0)) return fail(ctx, PNP_E_ARG, "lambda must be in (0, 1]");
+  if (!(tol >= 0.0) || max_iter < 1) return fail(ctx, PNP_E_ARG, "tol must be >= 0 and max_iter >= 1");
+  if (p->per_term) return fail(ctx, PNP_E_ARG, "per_term is not available here");
+  if ((uintptr_t)ws % kAlign) return fail(ctx, PNP_E_ARG, "workspace must be 256-byte aligned");
+  for (int i = 0; i < S; ++i)
+    if (!(sp[i].rho_bulk > 0.0)) return fail(ctx, PNP_E_ARG, "bulk densities must be > 0");
+  const bool pairs = d.ec || d.sw;
+  const Layout L = layout_of(d.n, S, d.precision, d.hs, pairs, false);
+  if (ws_bytes < L.total) return fail(ctx, PNP_E_NOMEM, "workspace too small: need " + std::to_string(L.total));
+  double mb[kMaxSpecies];
+  st = pnp_bulk_mu_ex(ctx, S, sp, T, p, mb);
+  if (st != PNP_OK) return st;
+  if (hipSetDevice(ctx->device) != hipSuccess) return device_check(ctx, "set device");
+  hipStream_t s = (hipStream_t)stream;
+  char* w = (char*)ws;
+  const Ops* op = ops_for(d.precision, d.n);
+  unsigned long long* res = (unsigned long long*)(w + L.energy);
+  const long n3 = (long)d.n * d.n * d.n;
+  double rbmb[2 * kMaxSpecies];
+  for (int i = 0; i < S; ++i) { rbmb[2 * i] = sp[i].rho_bulk; rbmb[2 * i + 1] = mb[i]; }
+  TableArgs ta;
+  fill_table_args(ta, d, sp, g->h, p->sw_prefactor, d.ec, d.sw, w + L.hs, pairs ? w + L.pair : nullptr, L.M);
+  EvalArgs ea;
+  fill_eval_args(ea, d, sp, L, w, rho);
+  ea.out = mu;
+  ea.slot = nullptr;
+  const TableArgs* dta = (const TableArgs*)upload(ctx, &ta, sizeof(ta), s);
+  const EvalArgs* dea = (const EvalArgs*)upload(ctx, &ea, sizeof(ea), s);
+  const double* drb = (const double*)upload(ctx, rbmb, sizeof(double) * 2 * S, s);
+  if (!dta || !dea || !drb) return device_check(ctx, "argument upload");
+  const int blocks = (int)std::min<long>(((long)S * n3 + 255) / 256, 4096);
+  *iters = 0;
+  *residual = INFINITY;
+  for (int it = 1; it <= max_iter; ++it) {
+    run_sequence(ctx, op, dea, dta, 1, L.M, d.hs, S, s);
+    if (hipMemsetAsync(res, 0, sizeof(unsigned long long), s) != hipSuccess) return device_check(ctx, "reset");
+    hipLaunchKernelGGL(k_picard, dim3(blocks), dim3(256), 0, s, rho, (const double*)mu, beta_v, n3, (int)S, drb,
+                       lambda, res);
+    st = device_check(ctx, "picard launch");
+    if (st != PNP_OK) return st;
+    unsigned long long rbits = 0;
+    uint32_t stw[2] = {0, 0};
+    if (hipMemcpyAsync(&rbits, res, sizeof(rbits), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipMemcpyAsync(stw, w + L.status, sizeof(stw), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      return device_check(ctx, "residual read");
+    st = status_of(ctx, stw);
+    *iters = it;
+    std::memcpy(residual, &rbits, sizeof(double));
+    if (st != PNP_OK) return st;
+    if (!std::isfinite(*residual)) return fail(ctx, PNP_E_NONFINITE, "non-finite density update");
+    if (*residual <= tol) break;
+  }
+  return PNP_OK;
 }
 
 pnp_status pnp_weighted_densities(pnp_ctx ctx, const pnp_grid* g, int32_t S, const pnp_species* sp,

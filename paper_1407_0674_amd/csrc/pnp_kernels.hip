@@ -148,6 +148,22 @@ __device__ __forceinline__ int inst_of(int tiles, int& tile) {
   return b / tiles;
 }
 
+// Sum of one double per thread over the workgroup, in a fixed order (the
+// result is the same on every run); valid in thread 0.  red: LDS scratch of
+// one double per wavefront.
+__device__ __forceinline__ double block_sum(double v, double* red) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  const int w = threadIdx.x / 64, nw = (blockDim.x + 63) / 64;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[w] = v;
+  __syncthreads();
+  double t = 0.0;
+  if (threadIdx.x == 0)
+    for (int k = 0; k < nw; ++k) t += red[k];
+  return t;
+}
+
 __device__ __forceinline__ void raise_status(uint32_t* st, uint32_t bits, uint32_t idx) {
   atomicOr(st, bits);
   atomicMin(st + 1, idx);
@@ -491,7 +507,8 @@ __device__ __forceinline__ double recip_f64(double x) {
   return __builtin_fma(y, e, y);
 }
 
-template <typename T, int N, int EZD = default_ezd<T, N>()>
+// PHI: also sum Phi_hs per workgroup into a.phi_part (free-energy calls)
+template <typename T, int N, bool PHI = false, int EZD = default_ezd<T, N>()>
 __global__ void __launch_bounds__((GeoD<T, N, EZD>::RDD * GeoD<T, N, EZD>::TZD))
     k_zderiv(const EvalArgs* __restrict__ args) {
   using D = GeoD<T, N, EZD>;
@@ -530,6 +547,8 @@ __global__ void __launch_bounds__((GeoD<T, N, EZD>::RDD * GeoD<T, N, EZD>::TZD))
   }
   uint32_t bad = 0u, badidx = 0xffffffffu;
   const double inv8pi = 1.0 / (8.0 * kPi), inv12pi = 1.0 / (12.0 * kPi), inv4pi = 1.0 / (4.0 * kPi);
+  const double inv24pi = 1.0 / (24.0 * kPi);
+  double phi = 0.0;  // Phi_hs summed over this thread's grid points
 #pragma unroll
   for (int m = 0; m < EZ; ++m) {
 #pragma unroll
@@ -552,6 +571,9 @@ __global__ void __launch_bounds__((GeoD<T, N, EZD>::RDD * GeoD<T, N, EZD>::TZD))
       // -ln(1 - n3): log of the rounded u plus the first-order correction for
       // the rounding of u, which equals log1p(-n3) to working precision
       d[0] = -(log(u) - ((u - 1.0) + n3) * inv);
+      // Phi_hs (Sec. 2.3.1): -n0 ln(1 - n3) + (n1 n2 - n1v.n2v) / (1 - n3)
+      //                      + (n2^3 - 3 n2 n2v.n2v) / (24 pi (1 - n3)^2)
+      if constexpr (PHI) phi += n0 * d[0] + (n1 * n2 - v12) * inv + (n2 * n2 * n2 - 3.0 * n2 * v22) * inv2 * inv24pi;
       d[1] = n2 * inv;
       d[2] = n1 * inv + (n2 * n2 - v22) * inv2 * inv8pi;
       d[3] = n0 * inv + (n1 * n2 - v12) * inv2 + (n2 * n2 * n2 - 3.0 * n2 * v22) * inv3 * inv12pi;
@@ -577,6 +599,11 @@ __global__ void __launch_bounds__((GeoD<T, N, EZD>::RDD * GeoD<T, N, EZD>::TZD))
     __builtin_amdgcn_sched_barrier(0);
   }
   if (bad) raise_status(a.status, bad, badidx);
+  if constexpr (PHI) {
+    __shared__ double red[16];
+    const double tot = block_sum(phi, red);
+    if (threadIdx.x == 0) a.phi_part[tile] = tot;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1315,6 +1342,76 @@ __global__ void k_relax(double* rho, const double* mu, long n3, int S, const dou
     if (clip > 0.0) g = fmin(fmax(g, -clip), clip);
     rho[e] = (1.0 - lambda) * rho[e] + lambda * rb * exp(g);
   }
+}
+
+// Pair free energies from one per-term evaluation, per-workgroup partial sums
+// (fixed order): part[2b] = sum_i sum_r (rho_i - rho_b,i)(beta mu_el,i +
+// beta mu_el,i[bulk]); part[2b + 1] = sum_i sum_r rho_i beta mu_sh,i.
+// rb_mb: [S][2] = (rho_b, beta mu_el[bulk]); mu3: [3][S][n3] per-term output.
+__global__ void __launch_bounds__(256) k_energy_part(const double* rho, const double* mu3, long n3, int S,
+                                                     const double* rb_mb, double* part) {
+  __shared__ double red[4];
+  const long sn3 = (long)S * n3;
+  double e = 0.0, f = 0.0;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < sn3; i += (long)gridDim.x * blockDim.x) {
+    const int s = (int)(i / n3);
+    const double r = rho[i];
+    e += (r - rb_mb[2 * s]) * (mu3[sn3 + i] + rb_mb[2 * s + 1]);
+    f += r * mu3[2 * sn3 + i];
+  }
+  const double te = block_sum(e, red);
+  const double tf = block_sum(f, red);
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = te;
+    part[2 * blockIdx.x + 1] = tf;
+  }
+}
+
+// out[0..3] = F_hs, F_el, F_sh, total [k_B T] from the partial sums, in a
+// fixed order.  phi_scale converts the Phi sums to h^3 sum Phi.
+__global__ void __launch_bounds__(256) k_energy_final(const double* phi_part, int nphi, const double* part,
+                                                      int npart, double phi_scale, double el_scale,
+                                                      double sh_scale, double* out) {
+  __shared__ double red[4];
+  double a = 0.0, e = 0.0, f = 0.0;
+  for (int i = threadIdx.x; i < nphi; i += blockDim.x) a += phi_part[i];
+  for (int i = threadIdx.x; i < npart; i += blockDim.x) {
+    e += part[2 * i];
+    f += part[2 * i + 1];
+  }
+  const double ta = block_sum(a, red);
+  const double te = block_sum(e, red);
+  const double tf = block_sum(f, red);
+  if (threadIdx.x == 0) {
+    const double hs = phi_scale * ta, el = el_scale * te, sh = sh_scale * tf;
+    out[0] = hs;
+    out[1] = el;
+    out[2] = sh;
+    out[3] = hs + el + sh;
+  }
+}
+
+// Picard step of the equilibrium solve: rho <- (1 - l) rho + l rho_b
+// exp(mu_b - mu - beta V) (beta_v may be null) and the residual
+// max |rho_new - rho| / rho_b as the bit pattern of a non-negative double
+// (integer max of such patterns is the max of the values: exact and
+// independent of the order of the updates).
+__global__ void __launch_bounds__(256) k_picard(double* rho, const double* mu, const double* beta_v, long n3, int S,
+                                                const double* rb_mb, double lambda, unsigned long long* res) {
+  double r = 0.0;
+  const long total = (long)S * n3;
+  for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (long)gridDim.x * blockDim.x) {
+    const int s = (int)(e / n3);
+    const double rb = rb_mb[2 * s], mb = rb_mb[2 * s + 1];
+    const double g = mb - mu[e] - (beta_v ? beta_v[e] : 0.0);
+    const double old = rho[e];
+    const double nw = (1.0 - lambda) * old + lambda * rb * exp(g);
+    rho[e] = nw;
+    r = fmax(r, fabs(nw - old) / rb);
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) r = fmax(r, __shfl_xor(r, o, 64));
+  if ((threadIdx.x & 63) == 0) atomicMax(res, (unsigned long long)__double_as_longlong(r));
 }
 
 // per-term mode: slot = exp(-(hs + el + sh))

@@ -55,6 +55,7 @@ struct EvalArgs {
   double* out;        // real output [nreal][n^3] (mu_ex or weighted densities)
   double* slot;       // [S][n^3] exp(-mu) or null
   uint32_t* status;   // two words
+  double* phi_part;   // per-workgroup sums of Phi_hs from the derivative pass, or null
 };
 
 // Per-instance arguments of the radial table builder.
