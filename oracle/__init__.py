@@ -28,7 +28,7 @@ from .units import beta, bjerrum_length, kappa_squared, KB_EV_PER_K, COULOMB_EV_
 from .transforms import (ball_ft, shell_ft, shell_vec_ft, r_ball_ft, inv_r_ball_ft,
                          j0, j1, j1_over_x)
 from .discrete import (Operator, build_operator, real_space_kernel, wavevectors)
-from .fmt import phi_hs, dphi_hs
+from .fmt import phi_hs, dphi_hs, phi_hs_wb, dphi_hs_wb
 from .direct import correlate_direct, convolve_direct
 from .mu_ex import mu_ex, weighted_densities, free_energy
 from .relax import relax_densities
@@ -49,6 +49,6 @@ __all__ = [
     "beta", "bjerrum_length", "kappa_squared", "KB_EV_PER_K", "COULOMB_EV_NM",
     "ball_ft", "shell_ft", "shell_vec_ft", "r_ball_ft", "inv_r_ball_ft", "j0", "j1",
     "j1_over_x", "Operator", "build_operator", "real_space_kernel", "wavevectors",
-    "phi_hs", "dphi_hs", "correlate_direct", "convolve_direct", "mu_ex",
+    "phi_hs", "dphi_hs", "phi_hs_wb", "dphi_hs_wb", "correlate_direct", "convolve_direct", "mu_ex",
     "weighted_densities", "free_energy", "relax_densities", "picard", "bulk_mu_ex", "STATUS",
 ]

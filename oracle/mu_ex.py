@@ -20,7 +20,18 @@ import numpy as np
 
 from .discrete import build_operator, real_space_kernel
 from .direct import correlate_direct, convolve_direct
-from .fmt import dphi_hs, phi_hs
+from .fmt import dphi_hs, dphi_hs_wb, phi_hs, phi_hs_wb
+
+HS_ROSENFELD, HS_WHITE_BEAR = 1, 8  # term bits of the hard-sphere functional (Sec. 2.3.1)
+
+
+def _hs_functional(terms):
+    """(phi, dphi) of the selected hard-sphere free-energy density, or None."""
+    if terms & HS_WHITE_BEAR:
+        return phi_hs_wb, dphi_hs_wb
+    if terms & HS_ROSENFELD:
+        return phi_hs, dphi_hs
+    return None
 
 SCALARS = ("w0", "w1", "w2", "w3")
 VECTORS = ("v1", "v2")
@@ -85,12 +96,13 @@ def mu_ex(problem, rho, route="direct"):
     res = {"hs": zero.copy(), "el": zero.copy(), "sh": zero.copy(), "n": None, "dphi": None}
     drho = rho - op.rho_bulk[:, None, None, None]
 
+    hs_fn = _hs_functional(terms)
     if route == "direct":
-        kernels = _species_kernels(op) if terms & 1 else None
+        kernels = _species_kernels(op) if hs_fn else None
         fields, kers, slots = [], [], []
-        if terms & 1:
+        if hs_fn:
             nal = weighted_densities(problem, rho, "direct", op, kernels)
-            d = dphi_hs(nal["n0"], nal["n1"], nal["n2"], nal["n3"], nal["n1v"], nal["n2v"])
+            d = hs_fn[1](nal["n0"], nal["n1"], nal["n2"], nal["n3"], nal["n1v"], nal["n2v"])
             res["n"], res["dphi"] = nal, d
             dl = _dphi_list(d)
             for i in range(S):
@@ -115,9 +127,9 @@ def mu_ex(problem, rho, route="direct"):
     else:
         def conv(f_hat, spec):
             return np.fft.irfftn(f_hat * spec, s=(n, n, n), axes=(0, 1, 2))
-        if terms & 1:
+        if hs_fn:
             nal = weighted_densities(problem, rho, "fft", op)
-            d = dphi_hs(nal["n0"], nal["n1"], nal["n2"], nal["n3"], nal["n1v"], nal["n2v"])
+            d = hs_fn[1](nal["n0"], nal["n1"], nal["n2"], nal["n3"], nal["n1v"], nal["n2v"])
             res["n"], res["dphi"] = nal, d
             dh = [np.fft.rfftn(x) for x in _dphi_list(d)]
             for i in range(S):
@@ -156,9 +168,10 @@ def free_energy(problem, rho, route="fft"):
     op = build_operator(problem, half=True)
     h3 = op.h ** 3
     out = {"hs": 0.0, "el": 0.0, "sh": 0.0}
-    if problem.terms & 1:
+    hs_fn = _hs_functional(problem.terms)
+    if hs_fn:
         nal = weighted_densities(problem, rho, "fft", op)
-        out["hs"] = h3 * float(np.sum(phi_hs(nal["n0"], nal["n1"], nal["n2"], nal["n3"],
+        out["hs"] = h3 * float(np.sum(hs_fn[0](nal["n0"], nal["n1"], nal["n2"], nal["n3"],
                                              nal["n1v"], nal["n2v"])))
     drho = rho - op.rho_bulk[:, None, None, None]
     if problem.terms & 2:

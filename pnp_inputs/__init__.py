@@ -24,6 +24,7 @@ MOLAR_TO_NM3 = 0.602214076
 TERM_HS = 1
 TERM_EC = 2
 TERM_SW = 4
+TERM_HS_WB = 8  # hard spheres with the modified (White Bear) functional instead of Rosenfeld's
 TERMS_ALL = TERM_HS | TERM_EC | TERM_SW
 
 FP64 = 0
@@ -272,7 +273,7 @@ def config5(seed: int = BASE_SEED + 5, rate: float = 200.0, duration: float = 10
 
 
 __all__ = [
-    "MOLAR_TO_NM3", "TERM_HS", "TERM_EC", "TERM_SW", "TERMS_ALL", "FP64", "MIXED",
+    "MOLAR_TO_NM3", "TERM_HS", "TERM_EC", "TERM_SW", "TERM_HS_WB", "TERMS_ALL", "FP64", "MIXED",
     "Species", "Problem", "Request", "uniform_well", "uniform_noise",
     "gaussian_channel", "gaussian_channel_profile", "local_packing_max", "config1", "config2", "config3",
     "config4", "config5", "channel_problem", "random_instance", "BASE_SEED",

@@ -89,3 +89,69 @@ def test_packing_violation_raises():
     z = np.zeros((3, 1))
     with pytest.raises(ValueError):
         dphi_hs(np.ones(1), np.ones(1), np.ones(1), np.array([1.0]), z, z)
+
+
+# --------------------------------------------------------------------------
+# the modified (White Bear) functional
+# --------------------------------------------------------------------------
+from oracle import dphi_hs_wb, phi_hs_wb  # noqa: E402
+from oracle.fmt import WB_SERIES_BELOW, _wb_g  # noqa: E402
+
+
+@pytest.mark.parametrize("n3", [1e-4, 0.01, 0.049, 0.051, 0.2, 0.45, 0.7])
+def test_wb_derivatives_match_finite_differences(n3):
+    rng = np.random.default_rng(int(n3 * 1e4))
+    p = _point(rng)
+    p["n3"] = n3
+    args = lambda q: (np.array(q["n0"]), np.array(q["n1"]), np.array(q["n2"]), np.array(q["n3"]),
+                      np.asarray(q["n1v"])[:, None], np.asarray(q["n2v"])[:, None])
+    d = dphi_hs_wb(*args(p))
+    for key, dk in (("n0", "d0"), ("n1", "d1"), ("n2", "d2"), ("n3", "d3")):
+        eps = 1e-6 * max(1e-3, abs(p[key]))
+        qp, qm = dict(p), dict(p)
+        qp[key] = p[key] + eps
+        qm[key] = p[key] - eps
+        fd = (phi_hs_wb(*args(qp)) - phi_hs_wb(*args(qm))) / (2 * eps)
+        assert float(d[dk]) == pytest.approx(float(fd), rel=1e-6, abs=1e-7), key
+    for key, dk in (("n1v", "d1v"), ("n2v", "d2v")):
+        for c in range(3):
+            eps = 1e-6
+            qp, qm = dict(p), dict(p)
+            qp[key] = np.array(p[key]); qp[key][c] += eps
+            qm[key] = np.array(p[key]); qm[key][c] -= eps
+            fd = (phi_hs_wb(*args(qp)) - phi_hs_wb(*args(qm))) / (2 * eps)
+            assert float(d[dk][c]) == pytest.approx(float(fd), rel=1e-7, abs=1e-8), (key, c)
+
+
+def test_wb_bracket_limits_and_switch():
+    # the n2^3 coefficient tends to Rosenfeld's 1/(24 pi) at vanishing packing
+    g, _ = _wb_g(np.array([0.0, 1e-8]))
+    assert g[0] / 36.0 == pytest.approx(1.0 / 24.0, rel=1e-15)
+    assert g[1] / 36.0 == pytest.approx(1.0 / 24.0, rel=1e-7)
+    # the series and the closed form agree where they meet
+    x = WB_SERIES_BELOW
+    one = 1 - x
+    closed = (x + one ** 2 * math.log1p(-x)) / (x ** 2 * one ** 2)
+    series = sum((k + 1) * (k + 3) / (k + 2) * x ** k for k in range(40))
+    assert closed == pytest.approx(series, rel=1e-12)
+    gs, _ = _wb_g(np.array([x * (1 - 1e-12), x * (1 + 1e-12)]))
+    assert gs[0] == pytest.approx(gs[1], rel=1e-11)
+
+
+@pytest.mark.parametrize("eta", [0.1, 0.3, 0.45])
+def test_wb_bulk_is_carnahan_starling(eta):
+    """For a uniform one-component fluid the White Bear functional gives the
+    Carnahan-Starling excess chemical potential (8 eta - 9 eta^2 + 3 eta^3) / (1 - eta)^3
+    through the full evaluation (weights, derivatives, back-convolution)."""
+    import oracle
+    import pnp_inputs as P
+    d = 0.3
+    sp = [P.Species(d, 0.0, eta / (math.pi / 6.0 * d ** 3))]
+    prob = P.Problem(n=8, h=0.05, species=sp, T=300.0, terms=P.TERM_HS_WB)
+    rho = np.full((1, 8, 8, 8), sp[0].rho_bulk)
+    mu = oracle.mu_ex(prob, rho, "fft")["total"]
+    cs = (8 * eta - 9 * eta ** 2 + 3 * eta ** 3) / (1 - eta) ** 3
+    assert np.max(np.abs(mu - cs)) < 1e-12 * cs
+    # the Rosenfeld functional differs (it gives the Percus-Yevick value)
+    ros = oracle.mu_ex(prob.with_(terms=P.TERM_HS), rho, "fft")["total"]
+    assert np.max(np.abs(ros - cs)) > 1e-3 * cs
