@@ -71,8 +71,13 @@ typedef enum {
   PNP_E_BUDGET = -8            /* request does not fit the memory budget */
 } pnp_status;
 
-/* terms of beta mu_ex */
-enum { PNP_TERM_HS = 1, PNP_TERM_EC = 2, PNP_TERM_SW = 4, PNP_TERM_ALL = 7 };
+/* terms of beta mu_ex.  The hard-sphere term uses Rosenfeld's free-energy
+ * density (PNP_TERM_HS) or the modified White Bear form of Sec. 2.3.1
+ * (PNP_TERM_HS_WB), whose n2^3 coefficient
+ *   phi3(n3) = [n3 + (1 - n3)^2 ln(1 - n3)] / (36 pi n3^2 (1 - n3)^2)
+ * replaces 1 / (24 pi (1 - n3)^2) and gives the Carnahan-Starling bulk
+ * fluid.  The two hard-sphere bits are exclusive (PNP_E_ARG if both). */
+enum { PNP_TERM_HS = 1, PNP_TERM_EC = 2, PNP_TERM_SW = 4, PNP_TERM_ALL = 7, PNP_TERM_HS_WB = 8 };
 
 /* arithmetic of the spectral path */
 enum {
@@ -252,9 +257,9 @@ pnp_status pnp_relax_densities(pnp_ctx ctx, const pnp_grid* grid, int32_t S,
 
 /*
  * beta mu_ex of the uniform bulk state (host arithmetic, no device work):
- * every rho_i(r) = rho_bulk_i.  HS: the Rosenfeld free-energy derivatives
- * at the bulk weighted densities, contracted with the k = 0 weights
- * (Sec. 2.3.1); EC: mu_el_bulk (Sec. 2.3.4, no density deviation); SW:
+ * every rho_i(r) = rho_bulk_i.  HS: the free-energy derivatives (Rosenfeld
+ * or White Bear, as selected) at the bulk weighted densities, contracted
+ * with the k = 0 weights (Sec. 2.3.1); EC: mu_el_bulk (Sec. 2.3.4, no density deviation); SW:
  * sw_prefactor * beta * sum_j rho_bulk_j u_ij(k = 0) (Sec. 2.3.2).  Equals
  * what pnp_cdft_mu_ex returns for uniform bulk densities, to rounding.
  *   ctx may be NULL (no device is used; errors are then not recorded)

@@ -12,7 +12,7 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 
-TERM_HS, TERM_EC, TERM_SW, TERM_ALL = 1, 2, 4, 7
+TERM_HS, TERM_EC, TERM_SW, TERM_ALL, TERM_HS_WB = 1, 2, 4, 7, 8
 FP64, MIXED = 0, 1
 FLAG_ASYNC = 1
 

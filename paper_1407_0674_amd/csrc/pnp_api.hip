@@ -102,12 +102,16 @@ bool size_ok(int n) {
 struct Derived {
   int n = 0, S = 0, np = 0, precision = 0;
   double h = 0;
-  bool hs = false, ec = false, sw = false;
+  bool hs = false, wb = false, ec = false, sw = false;  // wb: hard spheres by the White Bear form
   double beta = 0, lB = 0, kappa = 0;
   double sigma[kMaxPairs], B[kMaxPairs], rout[kMaxPairs], eps[kMaxPairs];
   int pi[kMaxSpecies][kMaxSpecies];
   double cfin_ec[kMaxSpecies];
 };
+
+// the hard-sphere functional of one instance as a variant bit: 1 Rosenfeld,
+// 2 White Bear, 0 no hard-sphere term
+inline int hs_mask(const Derived& d) { return d.hs ? (d.wb ? 2 : 1) : 0; }
 
 struct Layout {
   size_t status, energy, hs, pair, pair2, A, B, C, total;
@@ -148,7 +152,9 @@ pnp_status validate(pnp_ctx ctx, const pnp_grid* g, int S, const pnp_species* sp
     return fail(ctx, PNP_E_UNSUPPORTED_SIZE, "grid size " + std::to_string(g->nx) + " not supported");
   if (!(g->h > 0.0) || !std::isfinite(g->h)) return fail(ctx, PNP_E_ARG, "spacing h must be > 0");
   if (S < 1 || S > kMaxSpecies) return fail(ctx, PNP_E_ARG, "species count must be in [1, 8]");
-  if (p->terms == 0 || (p->terms & ~7u)) return fail(ctx, PNP_E_ARG, "terms must be a non-empty PNP_TERM_* mask");
+  if (p->terms == 0 || (p->terms & ~15u)) return fail(ctx, PNP_E_ARG, "terms must be a non-empty PNP_TERM_* mask");
+  if ((p->terms & PNP_TERM_HS) && (p->terms & PNP_TERM_HS_WB))
+    return fail(ctx, PNP_E_ARG, "PNP_TERM_HS and PNP_TERM_HS_WB are exclusive");
   if (p->precision != PNP_FP64 && p->precision != PNP_MIXED) return fail(ctx, PNP_E_ARG, "bad precision");
   if (need_T && !(T > 0.0 && std::isfinite(T))) return fail(ctx, PNP_E_ARG, "temperature must be > 0");
   for (int i = 0; i < S; ++i)
@@ -156,7 +162,7 @@ pnp_status validate(pnp_ctx ctx, const pnp_grid* g, int S, const pnp_species* sp
         !std::isfinite(sp[i].mu_el_bulk))
       return fail(ctx, PNP_E_ARG, "species " + std::to_string(i) + ": bad diameter, valence or bulk density");
   d.n = g->nx; d.h = g->h; d.S = S; d.np = S * (S + 1) / 2; d.precision = p->precision;
-  d.hs = p->terms & PNP_TERM_HS; d.ec = p->terms & PNP_TERM_EC; d.sw = p->terms & PNP_TERM_SW;
+  d.hs = p->terms & (PNP_TERM_HS | PNP_TERM_HS_WB); d.wb = p->terms & PNP_TERM_HS_WB; d.ec = p->terms & PNP_TERM_EC; d.sw = p->terms & PNP_TERM_SW;
   if (need_T) {
     if (d.ec && !(p->eps_r > 0.0)) return fail(ctx, PNP_E_ARG, "eps_r must be > 0");
     d.beta = 1.0 / (kBoltzmannEv * T);
@@ -226,7 +232,7 @@ void fill_eval_args(EvalArgs& e, const Derived& d, const pnp_species* sp, const 
                     const double* rho) {
   std::memset(&e, 0, sizeof(e));
   e.n = d.n; e.S = d.S; e.np = d.np;
-  e.hs_on = d.hs; e.pair_on = d.ec || d.sw;
+  e.hs_on = d.hs; e.hs_wb = d.wb; e.pair_on = d.ec || d.sw;
   e.fstride = L.fstride;
   e.inv_n3 = 1.0 / ((double)d.n * d.n * d.n);
   e.kscale = 2.0 * M_PI / (d.n * d.h);
@@ -294,7 +300,7 @@ struct Ops {
   void (*zfwd)(const EvalArgs*, int, hipStream_t);
   void (*ystep)(const EvalArgs*, int, int, int, bool, hipStream_t);
   void (*xfwd)(const EvalArgs*, int, hipStream_t);
-  void (*zderiv)(const EvalArgs*, int, bool, hipStream_t);
+  void (*zderiv)(const EvalArgs*, int, bool, int, hipStream_t);
   void (*xback)(const EvalArgs*, int, int, hipStream_t);
   int zderiv_tiles;  // workgroups of the derivative pass per instance
   void (*zinv)(const EvalArgs*, int, int, hipStream_t);
@@ -321,11 +327,19 @@ template <typename T, int N> struct Launch {
   static void xfwd(const EvalArgs* a, int count, hipStream_t s) {
     hipLaunchKernelGGL((k_xfwd<T, N>), dim3(count * G::tiles_x), dim3(G::PX * G::TX), 0, s, a);
   }
-  // phi: also sum Phi_hs per workgroup (free-energy calls)
-  static void zderiv(const EvalArgs* a, int count, bool phi, hipStream_t s) {
+  // phi: also sum Phi_hs per workgroup (free-energy calls); fmask: the
+  // hard-sphere functionals among the instances (1 Rosenfeld, 2 White Bear),
+  // one launch of the matching variant each
+  static void zderiv(const EvalArgs* a, int count, bool phi, int fmask, hipStream_t s) {
     const dim3 g(count * GeoD<T, N>::tiles), b(GeoD<T, N>::RDD * GeoD<T, N>::TZD);
-    if (phi) hipLaunchKernelGGL((k_zderiv<T, N, true>), g, b, 0, s, a);
-    else hipLaunchKernelGGL((k_zderiv<T, N, false>), g, b, 0, s, a);
+    if (fmask & 1) {
+      if (phi) hipLaunchKernelGGL((k_zderiv<T, N, true, false>), g, b, 0, s, a);
+      else hipLaunchKernelGGL((k_zderiv<T, N, false, false>), g, b, 0, s, a);
+    }
+    if (fmask & 2) {
+      if (phi) hipLaunchKernelGGL((k_zderiv<T, N, true, true>), g, b, 0, s, a);
+      else hipLaunchKernelGGL((k_zderiv<T, N, false, true>), g, b, 0, s, a);
+    }
   }
   // maxS: the largest species count among the launch's instances
   static void xback(const EvalArgs* a, int count, int maxS, hipStream_t s) {
@@ -383,18 +397,19 @@ const Ops* ops_for(int precision, int n) {
 }
 
 // The full launch sequence for `count` instances of one size and precision.
-// ea: device arg tables; hs_any: some instance has the HS term on;
-// pair_any likewise; ch: output chunk of the back pass.
+// ea: device arg tables; fmask: the hard-sphere functionals among the
+// instances (1 Rosenfeld, 2 White Bear, 0 no HS term); ch: output chunk of
+// the back pass.
 void run_sequence(pnp_ctx c, const Ops* op, const EvalArgs* ea, const TableArgs* ta, int count, int M,
-                  bool hs_any, int ch, hipStream_t s) {
+                  int fmask, int ch, hipStream_t s) {
   PassTimer pt{c, s};
   pt.begin(0); op->tables(ta, count, M, ch, s); pt.end();
   pt.begin(1); op->zfwd(ea, count, s); pt.end();
   pt.begin(2); op->ystep(ea, count, 0, -1, true, s); pt.end();
-  if (hs_any) {
+  if (fmask) {
     pt.begin(3); op->xfwd(ea, count, s); pt.end();
     pt.begin(4); op->ystep(ea, count, 1, kVecMode, false, s); pt.end();
-    pt.begin(5); op->zderiv(ea, count, false, s); pt.end();
+    pt.begin(5); op->zderiv(ea, count, false, fmask, s); pt.end();
     pt.begin(6); op->ystep(ea, count, 1, kVecMode, true, s); pt.end();
   }
   pt.begin(7); op->xback(ea, count, ch, s); pt.end();
@@ -452,7 +467,7 @@ static pnp_status enqueue_per_term(pnp_ctx ctx, const Derived& d, const pnp_grid
   if (d.hs) {
     pt.begin(3); op->xfwd(dea, 1, s); pt.end();
     pt.begin(4); op->ystep(dea, 1, 1, kVecMode, false, s); pt.end();
-    pt.begin(5); op->zderiv(dea, 1, phi_part != nullptr, s); pt.end();
+    pt.begin(5); op->zderiv(dea, 1, phi_part != nullptr, hs_mask(d), s); pt.end();
     pt.begin(6); op->ystep(dea, 1, 1, kVecMode, true, s); pt.end();
   }
   for (int k = 1; k < 4; ++k) {
@@ -542,7 +557,7 @@ pnp_status pnp_workspace_bytes(pnp_ctx ctx, const pnp_grid* g, int32_t S, const 
     return fail(ctx, PNP_E_UNSUPPORTED_SIZE, "unsupported grid");
   if (S < 1 || S > kMaxSpecies) return fail(ctx, PNP_E_ARG, "species count must be in [1, 8]");
   if (p->precision != PNP_FP64 && p->precision != PNP_MIXED) return fail(ctx, PNP_E_ARG, "bad precision");
-  const bool hs = p->terms & PNP_TERM_HS, pairs = p->terms & (PNP_TERM_EC | PNP_TERM_SW);
+  const bool hs = p->terms & (PNP_TERM_HS | PNP_TERM_HS_WB), pairs = p->terms & (PNP_TERM_EC | PNP_TERM_SW);
   *bytes = layout_of(g->nx, S, p->precision, hs, pairs, p->per_term).total;
   return PNP_OK;
 }
@@ -576,7 +591,7 @@ pnp_status pnp_cdft_mu_ex(pnp_ctx ctx, const pnp_grid* g, int32_t S, const pnp_s
     const TableArgs* dta = (const TableArgs*)upload(ctx, &ta, sizeof(ta), s);
     const EvalArgs* dea = (const EvalArgs*)upload(ctx, &ea, sizeof(ea), s);
     if (!dta || !dea) return device_check(ctx, "argument upload");
-    run_sequence(ctx, op, dea, dta, 1, L.M, d.hs, ch, s);
+    run_sequence(ctx, op, dea, dta, 1, L.M, hs_mask(d), ch, s);
   } else {
     st = enqueue_per_term(ctx, d, g, sp, rho, p, L, w, mu, slot, nullptr, s);
     if (st != PNP_OK) return st;
@@ -672,7 +687,7 @@ pnp_status pnp_equilibrium(pnp_ctx ctx, const pnp_grid* g, int32_t S, const pnp_
   *iters = 0;
   *residual = INFINITY;
   for (int it = 1; it <= max_iter; ++it) {
-    run_sequence(ctx, op, dea, dta, 1, L.M, d.hs, S, s);
+    run_sequence(ctx, op, dea, dta, 1, L.M, hs_mask(d), S, s);
     if (hipMemsetAsync(res, 0, sizeof(unsigned long long), s) != hipSuccess) return device_check(ctx, "reset");
     hipLaunchKernelGGL(k_picard, dim3(blocks), dim3(256), 0, s, rho, (const double*)mu, beta_v, n3, (int)S, drb,
                        lambda, res);
@@ -764,7 +779,7 @@ pnp_status pnp_batch_mu_ex(pnp_ctx ctx, int32_t count, pnp_request* reqs, void* 
     const int cnt = (int)ids.size();
     std::vector<TableArgs> ta(cnt);
     std::vector<EvalArgs> ea(cnt);
-    bool hs_any = false;
+    int fmask = 0;
     int maxS = 1;
     for (int k = 0; k < cnt; ++k) {
       pnp_request& q = reqs[ids[k]];
@@ -777,8 +792,7 @@ pnp_status pnp_batch_mu_ex(pnp_ctx ctx, int32_t count, pnp_request* reqs, void* 
       fill_eval_args(ea[k], d, q.species, L, w, q.rho);
       ea[k].out = q.mu_ex;
       ea[k].slot = q.slotboom;
-      hs_any |= d.hs;
-
+      fmask |= hs_mask(d);
       maxS = std::max(maxS, q.S);
     }
     const TableArgs* dta = (const TableArgs*)upload(ctx, ta.data(), sizeof(TableArgs) * cnt, s);
@@ -787,7 +801,7 @@ pnp_status pnp_batch_mu_ex(pnp_ctx ctx, int32_t count, pnp_request* reqs, void* 
     const Ops* op = ops_for(kv.first.first, kv.first.second);
     int M = 0;
     for (int k = 0; k < cnt; ++k) M = std::max(M, lay[ids[k]].M);
-    run_sequence(ctx, op, dea, dta, cnt, M, hs_any, maxS, s);
+    run_sequence(ctx, op, dea, dta, cnt, M, fmask, maxS, s);
   }
   pnp_status st = device_check(ctx, "batch launch");
   if (st != PNP_OK) return st;
@@ -881,8 +895,8 @@ pnp_status pnp_bulk_mu_ex(pnp_ctx ctx, int32_t S, const pnp_species* sp, double 
   Derived d;
   pnp_status st = validate(ctx, &g, S, sp, T, p, d, true);
   if (st != PNP_OK) return st;
-  // Rosenfeld FMT at uniform densities: n_a = sum_i rho_i w_i^a(k = 0), the
-  // vector densities vanish, and mu_i = sum_a dPhi/dn_a w_i^a(0) (Sec. 2.3.1)
+  // FMT at uniform densities: n_a = sum_i rho_i w_i^a(k = 0), the vector
+  // densities vanish, and mu_i = sum_a dPhi/dn_a w_i^a(0) (Sec. 2.3.1)
   double n0 = 0, n1 = 0, n2 = 0, n3 = 0;
   for (int i = 0; i < S; ++i) {
     const double R = 0.5 * sp[i].d, rb = sp[i].rho_bulk;
@@ -893,8 +907,28 @@ pnp_status pnp_bulk_mu_ex(pnp_ctx ctx, int32_t S, const pnp_species* sp, double 
   }
   if (d.hs && !(n3 < 1.0)) return fail(ctx, PNP_E_PACKING, "bulk packing fraction >= 1");
   const double u = 1.0 - n3;
-  const double d0 = -std::log1p(-n3), d1 = n2 / u, d2 = n1 / u + n2 * n2 / (8.0 * M_PI * u * u);
-  const double d3 = n0 / u + n1 * n2 / (u * u) + n2 * n2 * n2 / (12.0 * M_PI * u * u * u);
+  // phi3 and its derivative: the coefficient of n2^3 in Phi
+  double p3 = 1.0 / (24.0 * M_PI * u * u), dp3 = 1.0 / (12.0 * M_PI * u * u * u);
+  if (d.wb) {
+    // 36 pi phi3 = [n3 + u^2 ln u] / (n3^2 u^2); its power series
+    // sum_k (k+1)(k+3)/(k+2) n3^k below n3 = 0.05, where the closed form cancels
+    double g = 0.0, dg = 0.0;
+    if (n3 < 0.05) {
+      for (int k = 19; k >= 0; --k) {
+        const double c = (double)((k + 1) * (k + 3)) / (double)(k + 2);
+        g = g * n3 + c;
+        if (k >= 1) dg = dg * n3 + k * c;
+      }
+    } else {
+      const double lu = std::log1p(-n3), ix = 1.0 / n3;
+      g = ix / (u * u) + lu * ix * ix;
+      dg = 2.0 * ix / (u * u * u) - ix * ix / (u * u) - ix * ix / u - 2.0 * lu * ix * ix * ix;
+    }
+    p3 = g / (36.0 * M_PI);
+    dp3 = dg / (36.0 * M_PI);
+  }
+  const double d0 = -std::log1p(-n3), d1 = n2 / u, d2 = n1 / u + 3.0 * n2 * n2 * p3;
+  const double d3 = n0 / u + n1 * n2 / (u * u) + n2 * n2 * n2 * dp3;
   for (int i = 0; i < S; ++i) {
     const double R = 0.5 * sp[i].d;
     double m = 0.0;

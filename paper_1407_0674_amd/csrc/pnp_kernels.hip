@@ -507,8 +507,40 @@ __device__ __forceinline__ double recip_f64(double x) {
   return __builtin_fma(y, e, y);
 }
 
+// Coefficient of the n2^3 term of the modified (White Bear) functional,
+// phi3(x) = [x + (1 - x)^2 ln(1 - x)] / (36 pi x^2 (1 - x)^2), as
+// g = 36 pi phi3 and its derivative g'.  With u = 1 - x:
+//   g  = 1 / (x u^2) + ln(u) / x^2,
+//   g' = 2 / (x u^3) - 1 / (x^2 u^2) - 1 / (x^2 u) - 2 ln(u) / x^3.
+// Both forms cancel as x -> 0; below |x| = 0.05 the power series
+// g = sum_k (k+1)(k+3)/(k+2) x^k (from the series of ln(1 - x)) is used
+// instead, 16 terms (truncation of g and g' below 1e-17 relative).
+// inv = 1 / u and lnu = ln(u) come from the caller.
+__device__ __forceinline__ void wb_coeff(double x, double inv, double lnu, double& g, double& dg) {
+  constexpr int K = 16;
+  double gs = (double)(K * (K + 2)) / (double)(K + 1), dgs = (double)(K - 1) * gs;
+  // Horner from the top coefficient down: c_k = (k+1)(k+3)/(k+2)
+#pragma unroll
+  for (int k = K - 2; k >= 0; --k) {
+    gs = __builtin_fma(gs, x, (double)((k + 1) * (k + 3)) / (double)(k + 2));
+    if (k >= 1) dgs = __builtin_fma(dgs, x, (double)k * ((double)((k + 1) * (k + 3)) / (double)(k + 2)));
+  }
+  const bool small = fabs(x) < 0.05;
+  const double xl = small ? 0.5 : x;
+  const double ix = recip_f64(xl), ix2 = ix * ix;
+  const double il = small ? 2.0 : inv, ll = small ? -0.6931471805599453 : lnu;
+  const double gl = ix * il * il + ll * ix2;
+  const double dgl = ix * (2.0 * il * il * il - ix * il * il - ix * il - 2.0 * ll * ix2);
+  g = small ? gs : gl;
+  dg = small ? dgs : dgl;
+}
+
 // PHI: also sum Phi_hs per workgroup into a.phi_part (free-energy calls)
-template <typename T, int N, bool PHI = false, int EZD = default_ezd<T, N>()>
+// WB: the functional this variant evaluates (White Bear or Rosenfeld); blocks
+// of instances that select the other one exit, so a launch list holding both
+// runs each variant over it and every instance gets the same arithmetic as
+// when evaluated alone
+template <typename T, int N, bool PHI = false, bool WB = false, int EZD = default_ezd<T, N>()>
 __global__ void __launch_bounds__((GeoD<T, N, EZD>::RDD * GeoD<T, N, EZD>::TZD))
     k_zderiv(const EvalArgs* __restrict__ args) {
   using D = GeoD<T, N, EZD>;
@@ -518,7 +550,7 @@ __global__ void __launch_bounds__((GeoD<T, N, EZD>::RDD * GeoD<T, N, EZD>::TZD))
   __shared__ cx<T> xch[RD * H];
   int tile;
   const EvalArgs& a = args[inst_of(D::tiles, tile)];
-  if (!a.hs_on) return;  // uniform per block
+  if (!a.hs_on || (a.hs_wb != 0) != WB) return;  // uniform per block
   init_twiddles<T, H>(twH);
   init_twiddles<T, N>(twN);
   __syncthreads();
@@ -547,7 +579,7 @@ __global__ void __launch_bounds__((GeoD<T, N, EZD>::RDD * GeoD<T, N, EZD>::TZD))
   }
   uint32_t bad = 0u, badidx = 0xffffffffu;
   const double inv8pi = 1.0 / (8.0 * kPi), inv12pi = 1.0 / (12.0 * kPi), inv4pi = 1.0 / (4.0 * kPi);
-  const double inv24pi = 1.0 / (24.0 * kPi);
+  const double inv24pi = 1.0 / (24.0 * kPi), inv36pi = 1.0 / (36.0 * kPi);
   double phi = 0.0;  // Phi_hs summed over this thread's grid points
 #pragma unroll
   for (int m = 0; m < EZ; ++m) {
@@ -566,17 +598,30 @@ __global__ void __launch_bounds__((GeoD<T, N, EZD>::RDD * GeoD<T, N, EZD>::TZD))
       const double inv = recip_f64(u), inv2 = inv * inv, inv3 = inv2 * inv;
       const double v12 = a1x * a2x + a1y * a2y + a1z * a2z;
       const double v22 = a2x * a2x + a2y * a2y + a2z * a2z;
-      const double c2 = n2 * inv2 * inv4pi;
       double d[kFields];
       // -ln(1 - n3): log of the rounded u plus the first-order correction for
       // the rounding of u, which equals log1p(-n3) to working precision
       d[0] = -(log(u) - ((u - 1.0) + n3) * inv);
       // Phi_hs (Sec. 2.3.1): -n0 ln(1 - n3) + (n1 n2 - n1v.n2v) / (1 - n3)
-      //                      + (n2^3 - 3 n2 n2v.n2v) / (24 pi (1 - n3)^2)
-      if constexpr (PHI) phi += n0 * d[0] + (n1 * n2 - v12) * inv + (n2 * n2 * n2 - 3.0 * n2 * v22) * inv2 * inv24pi;
+      //                      + (n2^3 - 3 n2 n2v.n2v) phi3(n3)
+      // with phi3 = 1 / (24 pi (1 - n3)^2) (Rosenfeld) or the modified form
+      double c2;  // 6 n2 phi3: the n2v coefficient of d[7..9]
       d[1] = n2 * inv;
-      d[2] = n1 * inv + (n2 * n2 - v22) * inv2 * inv8pi;
-      d[3] = n0 * inv + (n1 * n2 - v12) * inv2 + (n2 * n2 * n2 - 3.0 * n2 * v22) * inv3 * inv12pi;
+      if constexpr (WB) {
+        double g, dg;
+        wb_coeff(n3, inv, -d[0], g, dg);
+        const double p3 = g * inv36pi, dp3 = dg * inv36pi;  // phi3 and its derivative
+        c2 = 6.0 * n2 * p3;
+        if constexpr (PHI) phi += n0 * d[0] + (n1 * n2 - v12) * inv + (n2 * n2 * n2 - 3.0 * n2 * v22) * p3;
+        d[2] = n1 * inv + 3.0 * (n2 * n2 - v22) * p3;
+        d[3] = n0 * inv + (n1 * n2 - v12) * inv2 + (n2 * n2 * n2 - 3.0 * n2 * v22) * dp3;
+      } else {
+        // Rosenfeld: 3 phi3 = 1 / (8 pi u^2), phi3' = 1 / (12 pi u^3), 6 n2 phi3 = n2 / (4 pi u^2)
+        c2 = n2 * inv2 * inv4pi;
+        if constexpr (PHI) phi += n0 * d[0] + (n1 * n2 - v12) * inv + (n2 * n2 * n2 - 3.0 * n2 * v22) * inv2 * inv24pi;
+        d[2] = n1 * inv + (n2 * n2 - v22) * inv2 * inv8pi;
+        d[3] = n0 * inv + (n1 * n2 - v12) * inv2 + (n2 * n2 * n2 - 3.0 * n2 * v22) * inv3 * inv12pi;
+      }
       d[4] = -a2x * inv;
       d[5] = -a2y * inv;
       d[6] = -a2z * inv;

@@ -44,7 +44,7 @@ struct EvalArgs {
   double inv4piR[kMaxSpecies];  // 1 / (4 pi R)
   double cfin[kMaxSpecies];     // constant added to beta mu in the final pass
   int32_t Sp;         // S rounded up to a multiple of 4 (row length of the pair table)
-  int32_t pad1;
+  int32_t hs_wb;      // 1: modified (White Bear) hard-sphere functional, 0: Rosenfeld
   const double* rho;  // [S][n^3] input densities
   void* specA;        // S spectral fields (densities)
   void* specB;        // 10 spectral fields (weighted densities, then derivatives)

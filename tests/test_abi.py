@@ -71,7 +71,7 @@ def _uniform(problem, n=8):
     return np.stack([np.full((n, n, n), s.rho_bulk) for s in problem.species])
 
 
-@pytest.mark.parametrize("terms", [1, 2, 4, 3, 5, 6, 7])
+@pytest.mark.parametrize("terms", [1, 2, 4, 3, 5, 6, 7, 8, 14])
 def test_bulk_mu_ex_against_oracle(terms):
     """pnp_bulk_mu_ex (host arithmetic behind the ABI, no device) equals the
     oracle's evaluation of uniform bulk densities, with non-zero EC bulk
@@ -115,3 +115,26 @@ def test_pool_calls_reject_null():
     assert lib.pnp_session_step(None, 0, None, None, None) == -1
     assert lib.pnp_session_close(None, 1) == -1
     assert lib.pnp_pool_usage(None, None, None, None) == -1
+
+
+@pytest.mark.parametrize("eta", [0.0, 0.02, 0.049, 0.051, 0.3, 0.45])
+def test_bulk_mu_ex_carnahan_starling(eta):
+    """One hard-sphere species with the White Bear functional: the bulk value
+    is the Carnahan-Starling result (8 eta - 9 eta^2 + 3 eta^3) / (1 - eta)^3,
+    on both sides of the switch between the series and the closed form."""
+    import math
+    import pnp_inputs as P
+    d = 0.3
+    sp = [P.Species(d, 0.0, eta / (math.pi / 6.0 * d ** 3))]
+    pr = P.Problem(n=8, h=0.05, species=sp, T=300.0, terms=P.TERM_HS_WB)
+    cs = (8 * eta - 9 * eta ** 2 + 3 * eta ** 3) / (1 - eta) ** 3
+    assert abs(pkg.bulk_mu_ex(pr)[0] - cs) < 1e-13 * max(1.0, cs)
+
+
+def test_hs_bits_are_exclusive():
+    import pnp_inputs as P
+    prob, _ = P.config1()
+    for terms in (P.TERM_HS | P.TERM_HS_WB, 16, 0):
+        with pytest.raises(pkg.PnpError) as e:
+            pkg.bulk_mu_ex(prob.with_(terms=terms))
+        assert e.value.status == -1
