@@ -138,3 +138,17 @@ def test_hs_bits_are_exclusive():
         with pytest.raises(pkg.PnpError) as e:
             pkg.bulk_mu_ex(prob.with_(terms=terms))
         assert e.value.status == -1
+
+
+def test_bulk_mu_ex_bmcsl_mixture():
+    """White Bear bulk values of a three-species mixture (host arithmetic
+    behind the ABI) against the BMCSL closed form."""
+    import numpy as np
+    import pnp_inputs as P
+    from test_oracle_fmt import bmcsl_mu
+    ds, rb = (0.15, 0.3, 0.4), (3.0, 2.0, 4.0)
+    pr = P.Problem(n=8, h=0.05, species=[P.Species(ds[i], 0.0, rb[i]) for i in range(3)], T=300.0,
+                   terms=P.TERM_HS_WB)
+    got = np.array(pkg.bulk_mu_ex(pr))
+    ref = bmcsl_mu(ds, rb)
+    assert np.max(np.abs(got - ref)) < 1e-12 * np.max(np.abs(ref))

@@ -96,3 +96,15 @@ def test_wb_batch_mixes_functionals(ev):
         m1, s1 = ev.mu_ex(prob, rd)
         assert torch.equal(mu, m1), prob.terms
         assert torch.equal(sl, s1), prob.terms
+
+
+def test_wb_uniform_mixture_is_bmcsl(ev):
+    from test_oracle_fmt import bmcsl_mu
+    ds, rb = (0.15, 0.3, 0.4), (3.0, 2.0, 4.0)
+    prob = P.Problem(n=16, h=0.05, species=[P.Species(ds[i], 0.0, rb[i]) for i in range(3)], T=300.0,
+                     terms=P.TERM_HS_WB)
+    rho = np.stack([np.full((16, 16, 16), r) for r in rb])
+    mu = ev.mu_ex(prob, to_dev(rho))[0].cpu().numpy()
+    ref = bmcsl_mu(ds, rb)
+    for i in range(3):
+        assert np.max(np.abs(mu[i] - ref[i])) < 1e-12 * np.max(np.abs(ref))

@@ -155,3 +155,42 @@ def test_wb_bulk_is_carnahan_starling(eta):
     # the Rosenfeld functional differs (it gives the Percus-Yevick value)
     ros = oracle.mu_ex(prob.with_(terms=P.TERM_HS), rho, "fft")["total"]
     assert np.max(np.abs(ros - cs)) > 1e-3 * cs
+
+
+def bmcsl_mu(d, rho):
+    """Excess chemical potentials of a hard-sphere mixture from the
+    Boublik-Mansoori-Carnahan-Starling-Leland equation of state, written with
+    xi_k = (pi/6) sum_j rho_j d_j^k (a closed form from the liquid-state
+    literature, independent of any functional)."""
+    d = np.asarray(d, dtype=np.float64)
+    rho = np.asarray(rho, dtype=np.float64)
+    x0, x1, x2, x3 = (math.pi / 6.0 * float(np.sum(rho * d ** k)) for k in range(4))
+    u = 1.0 - x3
+    ln = math.log(u)
+    beta_p = 6.0 / math.pi * (x0 / u + 3.0 * x1 * x2 / u ** 2 + (3.0 - x3) * x2 ** 3 / u ** 3)
+    out = []
+    for di in d:
+        a = di * x2 / x3
+        out.append(-ln + (3.0 * x2 * di + 3.0 * x1 * di ** 2) / u + 4.5 * (x2 * di / u) ** 2
+                   + 3.0 * a ** 2 * (ln + x3 / u - 0.5 * (x3 / u) ** 2)
+                   - a ** 3 * (2.0 * ln + x3 * (2.0 - x3) / u)
+                   + beta_p * math.pi * di ** 3 / 6.0)
+    return np.array(out)
+
+
+@pytest.mark.parametrize("rb", [(3.0, 2.0, 4.0), (0.5, 0.1, 9.0), (20.0, 1.0, 1.0)])
+def test_wb_bulk_mixture_is_bmcsl(rb):
+    """White Bear at uniform mixture densities, through the full evaluation,
+    equals the BMCSL chemical potentials of every species."""
+    import oracle
+    import pnp_inputs as P
+    ds = (0.15, 0.3, 0.4)
+    sp = [P.Species(ds[i], 0.0, rb[i]) for i in range(3)]
+    prob = P.Problem(n=8, h=0.05, species=sp, T=300.0, terms=P.TERM_HS_WB)
+    got = oracle.bulk_mu_ex(prob)
+    ref = bmcsl_mu(ds, rb)
+    assert np.max(np.abs(got - ref)) < 1e-12 * np.max(np.abs(ref))
+    # one component: Carnahan-Starling
+    eta = 0.35
+    one = bmcsl_mu([0.3], [eta / (math.pi / 6.0 * 0.3 ** 3)])[0]
+    assert one == pytest.approx((8 * eta - 9 * eta ** 2 + 3 * eta ** 3) / (1 - eta) ** 3, rel=1e-14)
