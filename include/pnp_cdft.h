@@ -233,6 +233,48 @@ typedef struct {
  */
 pnp_status pnp_batch_mu_ex(pnp_ctx ctx, int32_t count, pnp_request* reqs, void* stream);
 
+/*
+ * Captured evaluations.  A plan binds `count` requests (as pnp_batch_mu_ex:
+ * same validation, same grouping by grid size and precision, the same
+ * kernels and arithmetic, so a replay equals the batch call bit for bit) and
+ * records every launch of their evaluation in one HIP graph; a replay costs
+ * one graph launch instead of about ten kernel launches and one argument
+ * upload per grid size.  This is for callers that evaluate the same buffers
+ * over and over (the Gummel iterations of a PNP solve, resident sessions):
+ * they rewrite rho in place and replay.
+ *
+ * relax: NULL, or one pnp_relax_spec per request.  With it each replay also
+ * applies the density update of pnp_relax_densities to that request's rho
+ * (in place: rho must then be writable) after its evaluation, skipped on the
+ * device for a request whose evaluation raised a status.
+ *
+ * pnp_plan_create validates every request (reqs[r].status receives the
+ * result; failed requests are left out of the graph), copies their argument
+ * records into a device block owned by the plan (a few KiB per request),
+ * and captures the graph on a private stream.  The request array and the
+ * host arrays it points to may be released afterwards; the device buffers
+ * must stay allocated while the plan exists.  Errors: PNP_E_ARG (no valid
+ * plan arguments, or a bad relax spec), PNP_E_DEVICE (capture failed).
+ * pnp_plan_launch replays asynchronously on `stream` (no allocation, no
+ * host work beyond the launch).  pnp_plan_status waits for `stream` and
+ * writes the pnp_status of each request of the last replay into
+ * status[count] (creation-time failures keep their code).  A plan is tied to
+ * its context; replays of one plan on different streams must not overlap.
+ */
+typedef struct pnp_plan_s* pnp_plan;
+
+typedef struct {
+  const double* mu_bulk;  /* host, S values [k_B T]: beta mu_b of the update; copied */
+  double lambda;          /* mixing in [0, 1] */
+  double clip;            /* exponent limit (<= 0: none), as pnp_relax_densities */
+} pnp_relax_spec;
+
+pnp_status pnp_plan_create(pnp_ctx ctx, int32_t count, pnp_request* reqs,
+                           const pnp_relax_spec* relax, pnp_plan* out);
+pnp_status pnp_plan_launch(pnp_plan plan, void* stream);
+pnp_status pnp_plan_status(pnp_plan plan, void* stream, int32_t* status);
+void pnp_plan_destroy(pnp_plan plan);
+
 /* Read the status word left by an asynchronous call (after the stream has
  * finished the work).  workspace: the one passed to that call. */
 pnp_status pnp_read_status(pnp_ctx ctx, const void* workspace, void* stream);
@@ -324,6 +366,15 @@ pnp_status pnp_session_view(pnp_pool pool, int64_t id, double** rho, double** mu
 
 /* Release a session's block to the pool. */
 pnp_status pnp_session_close(pnp_pool pool, int64_t id);
+
+/* Captured session steps: keep up to max_plans step graphs (pnp_plan_*),
+ * keyed by the exact id list of a step, least recently used evicted; a step
+ * whose list has a graph replays it (evaluation and density update in one
+ * graph launch; the update is skipped on the device for a session whose
+ * evaluation raised a status).  Closing a session drops the graphs that
+ * hold it.  0 (the default) steps through pnp_batch_mu_ex and
+ * pnp_relax_densities instead.  Results are identical either way. */
+pnp_status pnp_pool_graphs(pnp_pool pool, int32_t max_plans);
 
 /*
  * Test hook: 3D real-to-complex DFT of `count` fields through the same

@@ -28,6 +28,7 @@ EXPORTED = [
     "pnp_relax_densities", "pnp_debug_rfft3", "pnp_debug_copy", "pnp_profile_enable",
     "pnp_profile_select", "pnp_profile_read", "pnp_free_energy", "pnp_equilibrium", "pnp_bulk_mu_ex", "pnp_session_bytes", "pnp_pool_create", "pnp_pool_destroy",
     "pnp_pool_usage", "pnp_session_open", "pnp_session_step", "pnp_session_view", "pnp_session_close",
+    "pnp_plan_create", "pnp_plan_launch", "pnp_plan_status", "pnp_plan_destroy", "pnp_pool_graphs",
 ]
 
 PASS_NAMES = ["tables", "z_fwd_rho", "y_fwd_rho", "x_fwd_weights", "y_inv_n", "z_deriv",
@@ -64,6 +65,11 @@ class RequestC(ctypes.Structure):
                 ("params", ctypes.POINTER(ParamsC)), ("mu_ex", ctypes.c_void_p),
                 ("slotboom", ctypes.c_void_p), ("workspace", ctypes.c_void_p),
                 ("workspace_bytes", ctypes.c_size_t), ("status", ctypes.c_int32)]
+
+
+class RelaxSpecC(ctypes.Structure):
+    _fields_ = [("mu_bulk", ctypes.POINTER(ctypes.c_double)), ("lambda_", ctypes.c_double),
+                ("clip", ctypes.c_double)]
 
 
 _LIB = None
@@ -130,13 +136,20 @@ def load_library():
     lib.pnp_session_view.argtypes = [P, ctypes.c_int64, ctypes.POINTER(P), ctypes.POINTER(P),
                                      ctypes.POINTER(P), ctypes.POINTER(ctypes.c_int64)]
     lib.pnp_session_close.argtypes = [P, ctypes.c_int64]
+    lib.pnp_plan_create.argtypes = [P, ctypes.c_int32, ctypes.POINTER(RequestC), ctypes.POINTER(RelaxSpecC),
+                                    ctypes.POINTER(P)]
+    lib.pnp_plan_launch.argtypes = [P, P]
+    lib.pnp_plan_status.argtypes = [P, P, ctypes.POINTER(ctypes.c_int32)]
+    lib.pnp_plan_destroy.argtypes = [P]
+    lib.pnp_plan_destroy.restype = None
+    lib.pnp_pool_graphs.argtypes = [P, ctypes.c_int32]
     lib.pnp_profile_enable.argtypes = [P, ctypes.c_int32]
     lib.pnp_profile_select.argtypes = [P, ctypes.c_uint32]
     lib.pnp_profile_read.argtypes = [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32),
                                      ctypes.c_int32, ctypes.c_int32]
     for name in EXPORTED:
         f = getattr(lib, name)
-        if name not in ("pnp_destroy", "pnp_last_error", "pnp_pool_destroy"):
+        if name not in ("pnp_destroy", "pnp_last_error", "pnp_pool_destroy", "pnp_plan_destroy"):
             f.restype = ctypes.c_int
     _LIB = lib
     return lib
@@ -295,15 +308,14 @@ class Evaluator:
         self._check(st)
         return out
 
-    def batch(self, problems: Sequence, rhos: Sequence, slotboom=True, workspaces=None,
-              outs=None, slots=None):
-        """Evaluate independent problems in shared launches.  Returns
-        (mu list, slot list, status list)."""
+    def _requests(self, problems, rhos, slotboom, workspaces, outs, slots):
+        """C request records for `problems` with their output and workspace
+        tensors; returns (reqs, keep-alive list, mu list, slot list)."""
         torch = _torch()
         count = len(problems)
         ms = [_Marshal(p) for p in problems]
         reqs = (RequestC * count)()
-        keep = []
+        keep = [ms]
         mus, sls = [], []
         for r, (p, m, rho) in enumerate(zip(problems, ms, rhos)):
             mu = outs[r] if outs is not None else torch.empty(tuple(rho.shape), dtype=torch.float64, device=rho.device)
@@ -325,9 +337,22 @@ class Evaluator:
             reqs[r].workspace_bytes = ws.numel()
             mus.append(mu)
             sls.append(sl)
+        return reqs, keep, mus, sls
+
+    def batch(self, problems: Sequence, rhos: Sequence, slotboom=True, workspaces=None,
+              outs=None, slots=None):
+        """Evaluate independent problems in shared launches.  Returns
+        (mu list, slot list, status list)."""
+        count = len(problems)
+        reqs, keep, mus, sls = self._requests(problems, rhos, slotboom, workspaces, outs, slots)
         st = self.lib.pnp_batch_mu_ex(self.ctx, count, reqs, self._stream())
         self._check(st)
         return mus, sls, [int(reqs[r].status) for r in range(count)]
+
+    def plan(self, problems: Sequence, rhos: Sequence, slotboom=True, workspaces=None, outs=None,
+             slots=None, relax=None):
+        """Capture the evaluation of these buffers in a HIP graph (see Plan)."""
+        return Plan(self, problems, rhos, slotboom, workspaces, outs, slots, relax)
 
     def profile(self, enable: bool = True, passes=None):
         """Pass timing on/off; `passes`: names of the passes that record
@@ -404,6 +429,51 @@ class Evaluator:
                                             self._stream()))
 
 
+class Plan:
+    """A captured evaluation (pnp_plan_* in the header): the requests' buffers
+    are bound at creation; launch() replays every kernel as one graph launch
+    on the current stream, status() waits and returns each request's status.
+    relax: None, or one (mu_bulk, lam, clip) per request: each replay then
+    also relaxes that request's rho in place after its evaluation."""
+
+    def __init__(self, ev, problems, rhos, slotboom=True, workspaces=None, outs=None, slots=None, relax=None):
+        self.ev = ev
+        self.lib = ev.lib
+        self.count = len(problems)
+        reqs, keep, self.mu, self.slot = ev._requests(problems, rhos, slotboom, workspaces, outs, slots)
+        self._keep = [keep, list(rhos)]
+        rspec = None
+        if relax is not None:
+            rspec = (RelaxSpecC * self.count)()
+            for r, (mb, lam, clip) in enumerate(relax):
+                arr = (ctypes.c_double * len(mb))(*[float(x) for x in mb])
+                self._keep.append(arr)
+                rspec[r] = RelaxSpecC(ctypes.cast(arr, ctypes.POINTER(ctypes.c_double)), float(lam), float(clip))
+        plan = ctypes.c_void_p()
+        ev._check(self.lib.pnp_plan_create(ev.ctx, self.count, reqs, rspec, ctypes.byref(plan)))
+        self.plan = plan
+        self.created_status = [int(reqs[r].status) for r in range(self.count)]
+
+    def launch(self):
+        self.ev._check(self.lib.pnp_plan_launch(self.plan, self.ev._stream()))
+
+    def status(self):
+        out = (ctypes.c_int32 * self.count)()
+        self.ev._check(self.lib.pnp_plan_status(self.plan, self.ev._stream(), out))
+        return [int(x) for x in out]
+
+    def close(self):
+        if getattr(self, "plan", None):
+            self.lib.pnp_plan_destroy(self.plan)
+            self.plan = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 def bulk_mu_ex(problem):
     """beta mu_ex of the uniform bulk state of `problem` (host arithmetic in
     the library; no device needed).  Returns a list of S floats."""
@@ -451,6 +521,10 @@ class Pool:
         self.ev._check(self.lib.pnp_session_bytes(self.ev.ctx, ctypes.byref(m.grid), m.S,
                                                   ctypes.byref(m.params), ctypes.byref(out)))
         return int(out.value)
+
+    def graphs(self, max_plans: int):
+        """Replay steps from captured graphs (up to max_plans id lists); 0: off."""
+        self.ev._check(self.lib.pnp_pool_graphs(self.pool, int(max_plans)))
 
     def usage(self):
         used, big, n = ctypes.c_size_t(), ctypes.c_size_t(), ctypes.c_int32()

@@ -33,6 +33,7 @@ struct pnp_ctx_s {
   std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_open;  // recorded, unread
   double prof_ms[PNP_NUM_PASSES] = {0};
   int32_t prof_n[PNP_NUM_PASSES] = {0};
+  bool capturing = false;  // a plan is being captured: no pass events
 };
 
 namespace {
@@ -71,7 +72,7 @@ struct PassTimer {
   int id = -1;
   hipEvent_t e0 = nullptr;
   void begin(int pass) {
-    if (!c || !c->prof || !((c->prof_mask >> pass) & 1u)) return;
+    if (!c || !c->prof || c->capturing || !((c->prof_mask >> pass) & 1u)) return;
     id = pass;
     e0 = take_event(c);
     if (e0) hipEventRecord(e0, s);
@@ -417,7 +418,79 @@ void run_sequence(pnp_ctx c, const Ops* op, const EvalArgs* ea, const TableArgs*
   pt.begin(9); op->zinv(ea, count, 2, s); pt.end();
 }
 
+// One launch group of a batch: the valid requests of one (precision, n),
+// with their argument records in request order.
+struct Group {
+  int precision = 0, n = 0;
+  std::vector<int> ids;
+  std::vector<TableArgs> ta;
+  std::vector<EvalArgs> ea;
+  int fmask = 0, maxS = 1, M = 0;
+};
+
+// Validate every request (its status field receives the result) and build
+// the argument records of the valid ones, grouped by (precision, n).
+void prepare_batch(pnp_ctx ctx, int count, pnp_request* reqs, std::vector<Layout>& lay, std::vector<Group>& out) {
+  std::map<std::pair<int, int>, std::vector<int>> groups;
+  std::vector<Derived> der(count);
+  lay.assign(count, Layout{});
+  for (int r = 0; r < count; ++r) {
+    pnp_request& q = reqs[r];
+    q.status = PNP_OK;
+    pnp_status st = validate(ctx, &q.grid, q.S, q.species, q.T, q.params, der[r], true);
+    if (st == PNP_OK && (!q.rho || !q.mu_ex || !q.workspace)) st = fail(ctx, PNP_E_ARG, "null device pointer");
+    if (st == PNP_OK && q.params->per_term) st = fail(ctx, PNP_E_ARG, "per_term is not available in batches");
+    if (st == PNP_OK && ((uintptr_t)q.workspace % kAlign)) st = fail(ctx, PNP_E_ARG, "workspace alignment");
+    if (st == PNP_OK) {
+      const Derived& d = der[r];
+      lay[r] = layout_of(d.n, q.S, d.precision, d.hs, d.ec || d.sw, false);
+      if (q.workspace_bytes < lay[r].total) st = fail(ctx, PNP_E_NOMEM, "workspace too small");
+    }
+    q.status = st;
+    if (st == PNP_OK) groups[{der[r].precision, der[r].n}].push_back(r);
+  }
+  out.clear();
+  for (auto& kv : groups) {
+    Group g;
+    g.precision = kv.first.first;
+    g.n = kv.first.second;
+    g.ids = kv.second;
+    const int cnt = (int)g.ids.size();
+    g.ta.resize(cnt);
+    g.ea.resize(cnt);
+    for (int k = 0; k < cnt; ++k) {
+      pnp_request& q = reqs[g.ids[k]];
+      const Derived& d = der[g.ids[k]];
+      const Layout& L = lay[g.ids[k]];
+      char* w = (char*)q.workspace;
+      const bool pairs = d.ec || d.sw;
+      fill_table_args(g.ta[k], d, q.species, q.grid.h, q.params->sw_prefactor, d.ec, d.sw, w + L.hs,
+                      pairs ? w + L.pair : nullptr, L.M);
+      fill_eval_args(g.ea[k], d, q.species, L, w, q.rho);
+      g.ea[k].out = q.mu_ex;
+      g.ea[k].slot = q.slotboom;
+      g.fmask |= hs_mask(d);
+      g.maxS = std::max(g.maxS, q.S);
+      g.M = std::max(g.M, L.M);
+    }
+    out.push_back(std::move(g));
+  }
+}
+
 }  // namespace
+
+// A captured evaluation: argument records in a device block of its own and a
+// HIP graph of every launch, replayed on any stream.
+struct pnp_plan_s {
+  pnp_ctx ctx = nullptr;
+  int count = 0;
+  std::vector<int32_t> valid;       // creation-time status of each request
+  std::vector<const void*> status;  // device status word of each valid request
+  void* block = nullptr;            // argument records (device)
+  size_t block_bytes = 0;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
 
 // ===========================================================================
 // C ABI
@@ -755,53 +828,15 @@ pnp_status pnp_batch_mu_ex(pnp_ctx ctx, int32_t count, pnp_request* reqs, void* 
   if (count < 0 || (count > 0 && !reqs)) return fail(ctx, PNP_E_ARG, "bad request array");
   if (hipSetDevice(ctx->device) != hipSuccess) return device_check(ctx, "set device");
   hipStream_t s = (hipStream_t)stream;
-  // validate each request; group the valid ones by (precision, n)
-  std::map<std::pair<int, int>, std::vector<int>> groups;
-  std::vector<Derived> der(count);
-  std::vector<Layout> lay(count);
-  for (int r = 0; r < count; ++r) {
-    pnp_request& q = reqs[r];
-    q.status = PNP_OK;
-    pnp_status st = validate(ctx, &q.grid, q.S, q.species, q.T, q.params, der[r], true);
-    if (st == PNP_OK && (!q.rho || !q.mu_ex || !q.workspace)) st = fail(ctx, PNP_E_ARG, "null device pointer");
-    if (st == PNP_OK && q.params->per_term) st = fail(ctx, PNP_E_ARG, "per_term is not available in batches");
-    if (st == PNP_OK && ((uintptr_t)q.workspace % kAlign)) st = fail(ctx, PNP_E_ARG, "workspace alignment");
-    if (st == PNP_OK) {
-      const Derived& d = der[r];
-      lay[r] = layout_of(d.n, q.S, d.precision, d.hs, d.ec || d.sw, false);
-      if (q.workspace_bytes < lay[r].total) st = fail(ctx, PNP_E_NOMEM, "workspace too small");
-    }
-    q.status = st;
-    if (st == PNP_OK) groups[{der[r].precision, der[r].n}].push_back(r);
-  }
-  for (auto& kv : groups) {
-    const std::vector<int>& ids = kv.second;
-    const int cnt = (int)ids.size();
-    std::vector<TableArgs> ta(cnt);
-    std::vector<EvalArgs> ea(cnt);
-    int fmask = 0;
-    int maxS = 1;
-    for (int k = 0; k < cnt; ++k) {
-      pnp_request& q = reqs[ids[k]];
-      const Derived& d = der[ids[k]];
-      const Layout& L = lay[ids[k]];
-      char* w = (char*)q.workspace;
-      const bool pairs = d.ec || d.sw;
-      fill_table_args(ta[k], d, q.species, q.grid.h, q.params->sw_prefactor, d.ec, d.sw, w + L.hs,
-                      pairs ? w + L.pair : nullptr, L.M);
-      fill_eval_args(ea[k], d, q.species, L, w, q.rho);
-      ea[k].out = q.mu_ex;
-      ea[k].slot = q.slotboom;
-      fmask |= hs_mask(d);
-      maxS = std::max(maxS, q.S);
-    }
-    const TableArgs* dta = (const TableArgs*)upload(ctx, ta.data(), sizeof(TableArgs) * cnt, s);
-    const EvalArgs* dea = (const EvalArgs*)upload(ctx, ea.data(), sizeof(EvalArgs) * cnt, s);
+  std::vector<Layout> lay;
+  std::vector<Group> groups;
+  prepare_batch(ctx, count, reqs, lay, groups);
+  for (const Group& g : groups) {
+    const int cnt = (int)g.ids.size();
+    const TableArgs* dta = (const TableArgs*)upload(ctx, g.ta.data(), sizeof(TableArgs) * cnt, s);
+    const EvalArgs* dea = (const EvalArgs*)upload(ctx, g.ea.data(), sizeof(EvalArgs) * cnt, s);
     if (!dta || !dea) return device_check(ctx, "argument upload");
-    const Ops* op = ops_for(kv.first.first, kv.first.second);
-    int M = 0;
-    for (int k = 0; k < cnt; ++k) M = std::max(M, lay[ids[k]].M);
-    run_sequence(ctx, op, dea, dta, cnt, M, fmask, maxS, s);
+    run_sequence(ctx, ops_for(g.precision, g.n), dea, dta, cnt, g.M, g.fmask, g.maxS, s);
   }
   pnp_status st = device_check(ctx, "batch launch");
   if (st != PNP_OK) return st;
@@ -820,6 +855,140 @@ pnp_status pnp_batch_mu_ex(pnp_ctx ctx, int32_t count, pnp_request* reqs, void* 
   for (int r = 0; r < count; ++r)
     if (reqs[r].status == PNP_OK) reqs[r].status = status_of(ctx, &words[2 * r]);
   return PNP_OK;
+}
+
+pnp_status pnp_plan_create(pnp_ctx ctx, int32_t count, pnp_request* reqs, const pnp_relax_spec* relax,
+                           pnp_plan* out) {
+  if (!ctx) return PNP_E_ARG;
+  if (!out || count < 1 || !reqs) return fail(ctx, PNP_E_ARG, "bad plan arguments");
+  *out = nullptr;
+  if (hipSetDevice(ctx->device) != hipSuccess) return device_check(ctx, "set device");
+  std::vector<Layout> lay;
+  std::vector<Group> groups;
+  prepare_batch(ctx, count, reqs, lay, groups);
+  if (relax)
+    for (int r = 0; r < count; ++r) {
+      if (reqs[r].status != PNP_OK) continue;
+      const pnp_relax_spec& x = relax[r];
+      if (!x.mu_bulk || !(x.lambda >= 0.0 && x.lambda <= 1.0) || std::isnan(x.clip))
+        return fail(ctx, PNP_E_ARG, "relax spec " + std::to_string(r) + ": mu_bulk, lambda in [0, 1], clip");
+    }
+  // one device block: each group's table and evaluation records, then the
+  // relax constants (rho_b, mu_b) of each request
+  std::vector<size_t> ta_off(groups.size()), ea_off(groups.size()), rb_off(count, 0);
+  size_t bytes = 0;
+  for (size_t k = 0; k < groups.size(); ++k) {
+    ta_off[k] = bytes;
+    bytes = up(bytes + sizeof(TableArgs) * groups[k].ids.size());
+    ea_off[k] = bytes;
+    bytes = up(bytes + sizeof(EvalArgs) * groups[k].ids.size());
+  }
+  if (relax)
+    for (int r = 0; r < count; ++r)
+      if (reqs[r].status == PNP_OK) {
+        rb_off[r] = bytes;
+        bytes = up(bytes + sizeof(double) * 2 * reqs[r].S);
+      }
+  std::vector<char> host(std::max<size_t>(bytes, 1), 0);
+  for (size_t k = 0; k < groups.size(); ++k) {
+    std::memcpy(host.data() + ta_off[k], groups[k].ta.data(), sizeof(TableArgs) * groups[k].ids.size());
+    std::memcpy(host.data() + ea_off[k], groups[k].ea.data(), sizeof(EvalArgs) * groups[k].ids.size());
+  }
+  if (relax)
+    for (int r = 0; r < count; ++r)
+      if (reqs[r].status == PNP_OK) {
+        double* rb = (double*)(host.data() + rb_off[r]);
+        for (int i = 0; i < reqs[r].S; ++i) {
+          rb[2 * i] = reqs[r].species[i].rho_bulk;
+          rb[2 * i + 1] = relax[r].mu_bulk[i];
+        }
+      }
+  pnp_plan p = new pnp_plan_s();
+  p->ctx = ctx;
+  p->count = count;
+  p->valid.resize(count);
+  p->status.assign(count, nullptr);
+  for (int r = 0; r < count; ++r) {
+    p->valid[r] = reqs[r].status;
+    if (reqs[r].status == PNP_OK) p->status[r] = (const char*)reqs[r].workspace + lay[r].status;
+  }
+  p->block_bytes = host.size();
+  if (hipMalloc(&p->block, p->block_bytes) != hipSuccess ||
+      hipMemcpy(p->block, host.data(), host.size(), hipMemcpyHostToDevice) != hipSuccess) {
+    pnp_plan_destroy(p);
+    return device_check(ctx, "plan block");
+  }
+  // capture every launch on a private stream of default priority
+  hipStream_t cs = nullptr;
+  if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) {
+    pnp_plan_destroy(p);
+    return device_check(ctx, "capture stream");
+  }
+  char* blk = (char*)p->block;
+  bool ok = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess;
+  if (ok) {
+    ctx->capturing = true;
+    for (size_t k = 0; k < groups.size(); ++k) {
+      const Group& g = groups[k];
+      run_sequence(ctx, ops_for(g.precision, g.n), (const EvalArgs*)(blk + ea_off[k]),
+                   (const TableArgs*)(blk + ta_off[k]), (int)g.ids.size(), g.M, g.fmask, g.maxS, cs);
+    }
+    if (relax)
+      for (int r = 0; r < count; ++r) {
+        if (reqs[r].status != PNP_OK) continue;
+        const pnp_request& q = reqs[r];
+        const long n3 = (long)q.grid.nx * q.grid.ny * q.grid.nz;
+        const int blocks = (int)std::min<long>((q.S * n3 + 255) / 256, 4096);
+        hipLaunchKernelGGL(k_relax, dim3(blocks), dim3(256), 0, cs, (double*)q.rho, (const double*)q.mu_ex, n3,
+                           (int)q.S, (const double*)(blk + rb_off[r]), relax[r].lambda, relax[r].clip,
+                           (const uint32_t*)p->status[r]);
+      }
+    ctx->capturing = false;
+    ok = hipStreamEndCapture(cs, &p->graph) == hipSuccess && p->graph;
+  }
+  if (ok) ok = hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0) == hipSuccess;
+  (void)hipStreamDestroy(cs);
+  if (!ok) {
+    pnp_plan_destroy(p);
+    return device_check(ctx, "graph capture");
+  }
+  *out = p;
+  return PNP_OK;
+}
+
+pnp_status pnp_plan_launch(pnp_plan plan, void* stream) {
+  if (!plan) return PNP_E_ARG;
+  if (hipSetDevice(plan->ctx->device) != hipSuccess) return device_check(plan->ctx, "set device");
+  if (hipGraphLaunch(plan->exec, (hipStream_t)stream) != hipSuccess) return device_check(plan->ctx, "graph launch");
+  return PNP_OK;
+}
+
+pnp_status pnp_plan_status(pnp_plan plan, void* stream, int32_t* status) {
+  if (!plan || !status) return plan ? fail(plan->ctx, PNP_E_ARG, "null status array") : PNP_E_ARG;
+  pnp_ctx ctx = plan->ctx;
+  if (hipSetDevice(ctx->device) != hipSuccess) return device_check(ctx, "set device");
+  hipStream_t s = (hipStream_t)stream;
+  std::vector<uint32_t> words(2 * (size_t)plan->count, 0u);
+  for (int r = 0; r < plan->count; ++r)
+    if (plan->status[r] &&
+        hipMemcpyAsync(&words[2 * r], plan->status[r], 8, hipMemcpyDeviceToHost, s) != hipSuccess)
+      return device_check(ctx, "status read");
+  if (hipStreamSynchronize(s) != hipSuccess) return device_check(ctx, "plan sync");
+  for (int r = 0; r < plan->count; ++r)
+    status[r] = plan->valid[r] != PNP_OK ? plan->valid[r] : status_of(ctx, &words[2 * r]);
+  return PNP_OK;
+}
+
+void pnp_plan_destroy(pnp_plan plan) {
+  if (!plan) return;
+  (void)hipSetDevice(plan->ctx->device);
+  if (plan->exec) (void)hipGraphExecDestroy(plan->exec);
+  if (plan->graph) (void)hipGraphDestroy(plan->graph);
+  if (plan->block) {
+    (void)hipDeviceSynchronize();  // a replay in flight may still read the block
+    (void)hipFree(plan->block);
+  }
+  delete plan;
 }
 
 pnp_status pnp_read_status(pnp_ctx ctx, const void* ws, void* stream) {
@@ -845,7 +1014,8 @@ pnp_status pnp_relax_densities(pnp_ctx ctx, const pnp_grid* g, int32_t S, const 
   if (!drb) return device_check(ctx, "argument upload");
   const long n3 = (long)g->nx * g->ny * g->nz;
   const int blocks = (int)std::min<long>((S * n3 + 255) / 256, 4096);
-  hipLaunchKernelGGL(k_relax, dim3(blocks), dim3(256), 0, s, rho, mu, n3, (int)S, drb, lambda, clip);
+  hipLaunchKernelGGL(k_relax, dim3(blocks), dim3(256), 0, s, rho, mu, n3, (int)S, drb, lambda, clip,
+                     (const uint32_t*)nullptr);
   return device_check(ctx, "relax launch");
 }
 

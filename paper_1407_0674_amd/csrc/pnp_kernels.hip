@@ -1377,8 +1377,11 @@ __global__ void __launch_bounds__(256) k_copy(const uint4* __restrict__ src, uin
 
 // relaxation of the consumer stub: rho <- (1 - l) rho + l rho_b exp(g),
 // g = mu_b - mu limited to [-clip, clip] when clip > 0
+// status: the evaluation's status word, or null; a raised status leaves rho
+// untouched (uniform over the grid)
 __global__ void k_relax(double* rho, const double* mu, long n3, int S, const double* rho_b_mu_b,
-                        double lambda, double clip) {
+                        double lambda, double clip, const uint32_t* status) {
+  if (status && status[0] != 0u) return;
   const long total = (long)S * n3;
   for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (long)gridDim.x * blockDim.x) {
     const int s = (int)(e / n3);

@@ -11,12 +11,16 @@
 //
 // The pool sub-allocates sessions first-fit from one device range and
 // coalesces free blocks on release; admission fails with PNP_E_BUDGET when
-// no free block is large enough.  Only host bookkeeping lives here: every
+// no free block is large enough.  With captured steps switched on
+// (pnp_pool_graphs) a step whose id list was seen before replays the graph
+// captured for it (pnp_plan_*).  Only host bookkeeping lives here: every
 // device operation goes through the public entry points or a stream-ordered
 // copy.
 #include <hip/hip_runtime_api.h>
 
+#include <algorithm>
 #include <cstring>
+#include <list>
 #include <map>
 #include <string>
 #include <vector>
@@ -55,6 +59,24 @@ struct pnp_pool_s {
   std::map<int64_t, Session> sessions;
   int64_t next_id = 1;
   size_t used = 0;
+  // captured steps, keyed by the exact id list, least recently used first
+  int32_t max_plans = 0;
+  std::list<std::pair<std::vector<int64_t>, pnp_plan>> plans;
+
+  void drop_plans_with(int64_t id) {
+    for (auto it = plans.begin(); it != plans.end();) {
+      if (std::find(it->first.begin(), it->first.end(), id) != it->first.end()) {
+        pnp_plan_destroy(it->second);
+        it = plans.erase(it);
+      } else {
+        ++it;
+      }
+    }
+  }
+  void drop_all_plans() {
+    for (auto& kv : plans) pnp_plan_destroy(kv.second);
+    plans.clear();
+  }
 
   bool take(size_t need, size_t& off) {
     for (auto it = free_blocks.begin(); it != free_blocks.end(); ++it) {
@@ -127,7 +149,21 @@ pnp_status pnp_pool_create(pnp_ctx ctx, void* arena, size_t arena_bytes, pnp_poo
   return PNP_OK;
 }
 
-void pnp_pool_destroy(pnp_pool pool) { delete pool; }
+void pnp_pool_destroy(pnp_pool pool) {
+  if (!pool) return;
+  pool->drop_all_plans();
+  delete pool;
+}
+
+pnp_status pnp_pool_graphs(pnp_pool pool, int32_t max_plans) {
+  if (!pool || max_plans < 0) return PNP_E_ARG;
+  pool->max_plans = max_plans;
+  while ((int32_t)pool->plans.size() > max_plans) {
+    pnp_plan_destroy(pool->plans.front().second);
+    pool->plans.pop_front();
+  }
+  return PNP_OK;
+}
 
 pnp_status pnp_pool_usage(pnp_pool pool, size_t* used, size_t* largest_free, int32_t* sessions) {
   if (!pool) return PNP_E_ARG;
@@ -218,6 +254,36 @@ pnp_status pnp_session_step(pnp_pool pool, int32_t count, const int64_t* ids, in
     r.workspace = s.ws;
     r.workspace_bytes = s.ws_bytes;
   }
+  if (pool->max_plans > 0 && count > 0) {
+    // captured step: evaluation and update replayed as one graph
+    const std::vector<int64_t> key(ids, ids + count);
+    auto hit = pool->plans.end();
+    for (auto it = pool->plans.begin(); it != pool->plans.end(); ++it)
+      if (it->first == key) hit = it;
+    pnp_plan plan = nullptr;
+    if (hit != pool->plans.end()) {
+      plan = hit->second;
+      pool->plans.splice(pool->plans.end(), pool->plans, hit);  // most recently used
+    } else {
+      std::vector<pnp_relax_spec> rx(count);
+      for (int32_t k = 0; k < count; ++k) rx[k] = pnp_relax_spec{ss[k]->mu_bulk.data(), ss[k]->lambda, ss[k]->clip};
+      pnp_status st = pnp_plan_create(pool->ctx, count, reqs.data(), rx.data(), &plan);
+      if (st != PNP_OK) return st;
+      if ((int32_t)pool->plans.size() >= pool->max_plans) {
+        pnp_plan_destroy(pool->plans.front().second);
+        pool->plans.pop_front();
+      }
+      pool->plans.emplace_back(key, plan);
+    }
+    pnp_status st = pnp_plan_launch(plan, stream);
+    if (st == PNP_OK) st = pnp_plan_status(plan, stream, status);
+    if (st != PNP_OK) return st;
+    for (int32_t k = 0; k < count; ++k) {
+      ss[k]->status = status[k];
+      if (status[k] == PNP_OK) ++ss[k]->steps;
+    }
+    return PNP_OK;
+  }
   pnp_status st = pnp_batch_mu_ex(pool->ctx, count, reqs.data(), stream);
   if (st != PNP_OK) return st;
   for (int32_t k = 0; k < count; ++k) {
@@ -249,6 +315,7 @@ pnp_status pnp_session_close(pnp_pool pool, int64_t id) {
   if (!pool) return PNP_E_ARG;
   auto it = pool->sessions.find(id);
   if (it == pool->sessions.end()) return PNP_E_ARG;
+  pool->drop_plans_with(id);
   pool->give(it->second.offset, it->second.bytes);
   pool->sessions.erase(it);
   return PNP_OK;
