@@ -173,7 +173,7 @@ def bench_batch(ev, steps, warmup):
     slots = [torch.empty_like(r) for r in rhos]
     wss = [torch.empty(ev.workspace_bytes(p), dtype=torch.uint8, device="cuda:0") for p in probs]
     pts = sum(p.n ** 3 * p.S for p in probs)
-    bytes_model = sum((60 * p.S + 32 * F) * p.n ** 3 for p in probs)
+    bytes_model = sum(sum(pass_bytes_per_point(p.S, p.precision).values()) * p.n ** 3 for p in probs)
 
     probs64 = [p.with_(precision=0) for p in probs]
     wss64 = [torch.empty(ev.workspace_bytes(p), dtype=torch.uint8, device="cuda:0") for p in probs64]
@@ -190,7 +190,24 @@ def bench_batch(ev, steps, warmup):
     for _ in range(steps):
         run_batch()
     torch.cuda.synchronize()
+    ms_call = (time.perf_counter() - t0) * 1e3 / steps
+    # the same evaluation captured once and replayed as one HIP graph per step
+    plan = ev.plan(probs, rhos, outs=outs, slots=slots, workspaces=wss)
+    for _ in range(warmup):
+        plan.launch()
+    assert plan.status() == [0] * len(probs)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        plan.launch()
+    st = plan.status()
     ms = (time.perf_counter() - t0) * 1e3 / steps
+    assert st == [0] * len(probs), st
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        plan.launch()
+        plan.status()
+    ms_graph_sync = (time.perf_counter() - t0) * 1e3 / steps
+    plan.close()
     # one call per instance (each waits for its status, as a caller without the batch call would)
     for p, r, o, s_, w in zip(probs, rhos, outs, slots, wss):
         ev.mu_ex(p, r, out=o, slot=s_, workspace=w)
@@ -221,23 +238,28 @@ def bench_batch(ev, steps, warmup):
         "hbm": {"model_bytes_per_step": bytes_model, "GBps": bytes_model / 1e9 / (ms / 1e3),
                 "pct_peak": 100.0 * bytes_model / 1e9 / (ms / 1e3) / HBM_PEAK_GBS,
                 "note": "instances up to 128^3 partly stay in the 256 MB Infinity Cache between passes"},
+        "timing": "one captured HIP graph (pnp_plan) replayed per step, statuses read after the last",
+        "graph_replay_with_status_each_ms": ms_graph_sync, "batch_call_ms": ms_call,
         "one_call_per_instance_ms": ms_alone, "speedup_vs_one_call_per_instance": ms_alone / ms,
         "fp64_batch_ms": ms64, "speedup_vs_fp64": ms64 / ms,
     }
 
 
-def serve_trace(ev, reqs, precision, budget, max_active, work_cap=None):
+def serve_trace(ev, reqs, precision, budget, max_active, work_cap=None, graphs=0):
     """Replay a request trace against a session pool: requests are admitted in
     arrival order when their session fits the budget (at most max_active at a
     time); every loop runs one step of the oldest active sessions whose
     grid-pt*species sum stays within work_cap (at least one; all when None),
-    and a request completes after its iterations.  Returns per-request
+    and a request completes after its iterations.  graphs > 0: steps replay
+    captured graphs (the pool keeps that many id lists).  Returns per-request
     latency (arrival to completion, ms), the makespan and the evaluated
     grid-pt*species."""
     import collections
     import torch
     from paper_1407_0674_amd import Pool
     pool = Pool(ev, budget)
+    if graphs:
+        pool.graphs(graphs)
     pending = collections.deque(reqs)
     active = {}
     lat = []
@@ -314,6 +336,7 @@ def bench_serve(ev, duration, rate):
     lat, span, work = serve_trace(ev, reqs, None, budget, 1 << 30, work_cap=cap)
     lat_all, span_all, _ = serve_trace(ev, reqs, None, budget, 1 << 30)
     lat1, span1, _ = serve_trace(ev, reqs, None, budget, 1)
+    lat1g, span1g, _ = serve_trace(ev, reqs, None, budget, 1, graphs=4)
     lat64, span64, work64 = serve_trace(ev, reqs, 0, budget, 1)
     return {
         "metric": "served requests: p50/p99 latency (arrival to done) and grid-pts*species/s",
@@ -332,6 +355,9 @@ def bench_serve(ev, duration, rate):
                                        "throughput_req_s": len(lat_all) / span_all},
         "mixed_one_at_a_time": {"latency_ms": {"p50": percentile(lat1, 50), "p99": percentile(lat1, 99)},
                                 "throughput_req_s": len(lat1) / span1},
+        "mixed_one_at_a_time_captured_steps": {"latency_ms": {"p50": percentile(lat1g, 50),
+                                                              "p99": percentile(lat1g, 99)},
+                                               "throughput_req_s": len(lat1g) / span1g},
         "fp64_one_at_a_time": {"latency_ms": {"p50": percentile(lat64, 50), "p99": percentile(lat64, 99),
                                               "max": max(lat64)},
                                "throughput_req_s": len(lat64) / span64, "value": work64 / span64},
@@ -354,7 +380,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build evaluates on one GPU; --gpus must be 1 "
-                                   "(independent instances shard with no communication, see DESIGN.md)"}))
+                                   "(independent instances shard with no communication)"}))
         sys.exit(2)
 
     import numpy as np
