@@ -191,17 +191,27 @@ def bench_batch(ev, steps, warmup):
         run_batch()
     torch.cuda.synchronize()
     ms_call = (time.perf_counter() - t0) * 1e3 / steps
-    # the same evaluation captured once and replayed as one HIP graph per step
-    plan = ev.plan(probs, rhos, outs=outs, slots=slots, workspaces=wss)
-    for _ in range(warmup):
-        plan.launch()
-    assert plan.status() == [0] * len(probs)
+    # the same evaluation captured once and replayed as one HIP graph per step,
+    # first in the default tile shapes, then after the autotuner has chosen
+    # per pass and size (results are bit-identical either way)
+    def time_plan():
+        plan = ev.plan(probs, rhos, outs=outs, slots=slots, workspaces=wss)
+        for _ in range(warmup):
+            plan.launch()
+        assert plan.status() == [0] * len(probs)
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            plan.launch()
+        st = plan.status()
+        assert st == [0] * len(probs), st
+        return plan, (time.perf_counter() - t0) * 1e3 / steps
+
+    plan, ms_default_tiles = time_plan()
+    plan.close()
     t0 = time.perf_counter()
-    for _ in range(steps):
-        plan.launch()
-    st = plan.status()
-    ms = (time.perf_counter() - t0) * 1e3 / steps
-    assert st == [0] * len(probs), st
+    assert ev.autotune(probs, rhos, reps=3) == [0] * len(probs)
+    tune_s = time.perf_counter() - t0
+    plan, ms = time_plan()
     t0 = time.perf_counter()
     for _ in range(steps):
         plan.launch()
@@ -238,7 +248,10 @@ def bench_batch(ev, steps, warmup):
         "hbm": {"model_bytes_per_step": bytes_model, "GBps": bytes_model / 1e9 / (ms / 1e3),
                 "pct_peak": 100.0 * bytes_model / 1e9 / (ms / 1e3) / HBM_PEAK_GBS,
                 "note": "instances up to 128^3 partly stay in the 256 MB Infinity Cache between passes"},
-        "timing": "one captured HIP graph (pnp_plan) replayed per step, statuses read after the last",
+        "timing": "one captured HIP graph (pnp_plan) replayed per step, statuses read after the last; "
+                  "tile shapes from the autotuner",
+        "graph_replay_default_tiles_ms": ms_default_tiles, "autotune_s": tune_s,
+        "tuning": ev.tune_export().strip().splitlines(),
         "graph_replay_with_status_each_ms": ms_graph_sync, "batch_call_ms": ms_call,
         "one_call_per_instance_ms": ms_alone, "speedup_vs_one_call_per_instance": ms_alone / ms,
         "fp64_batch_ms": ms64, "speedup_vs_fp64": ms64 / ms,
@@ -330,6 +343,16 @@ def bench_serve(ev, duration, rate):
     for r in reqs:
         sizes.setdefault((r.problem().n, r.problem().S), r)
     warm = list(sizes.values())
+    # tile shapes per size for single-session steps (the autotuner's single-instance class)
+    import torch
+    for prec in (None, 0):
+        for r in warm:
+            prob, prof = r.build_profile()
+            if prec is not None:
+                prob = prob.with_(precision=prec)
+            n = prob.n
+            rho0 = torch.from_numpy(prof).to("cuda:0")[:, :, None, :].expand(prob.S, n, n, n).contiguous()
+            ev.autotune([prob], [rho0], reps=2)
     for prec in (None, 0):
         serve_trace(ev, [P.Request(k, 0.0, r.seed, r.n_choices, r.precision, 1) for k, r in enumerate(warm)],
                     prec, budget, 1 << 30)

@@ -275,6 +275,34 @@ pnp_status pnp_plan_launch(pnp_plan plan, void* stream);
 pnp_status pnp_plan_status(pnp_plan plan, void* stream, int32_t* status);
 void pnp_plan_destroy(pnp_plan plan);
 
+/*
+ * Autotuner of tile shapes.  Every pass of the evaluation has a default tile
+ * shape (workgroups carrying 16 pencils or rows, for full-width HBM bursts
+ * on large grids) and, for grids up to 128^3, a narrow one with a quarter of
+ * the pencils per workgroup and four times the workgroups (small grids
+ * otherwise leave most of the 256 compute units idle).  pnp_autotune
+ * evaluates the requests (validated and grouped as pnp_batch_mu_ex; their
+ * outputs receive real results) `reps` times in each shape after one
+ * warm-up round, times every pass with HIP events, and keeps per pass the
+ * narrow shape only where it is faster by more than 3 %.  The choice is
+ * stored in the context under (precision, n, instance-count class of the
+ * launch: 1, 2-3, 4-15, >= 16) and used by every later evaluation with that
+ * key (single calls, batches, plans, sessions, the equilibrium solve).
+ * Tile shapes do not change the arithmetic: results are bit-identical under
+ * any choice.  The call waits for its work.  Accumulated pass timings
+ * (pnp_profile_read) are left as they were.
+ */
+pnp_status pnp_autotune(pnp_ctx ctx, int32_t count, pnp_request* reqs, int32_t reps, void* stream);
+
+/* The stored tuning as text, one line "precision n class mask" per key
+ * (mask: bit p set = pass p of pnp_profile_read's order runs narrow).
+ * pnp_tune_export writes it into buf (NUL-terminated; *len = its length
+ * without the NUL; with buf NULL only *len is set; PNP_E_ARG if cap is too
+ * small).  pnp_tune_import merges such text into the context (PNP_E_ARG on
+ * malformed or out-of-range lines, and then nothing is merged). */
+pnp_status pnp_tune_export(pnp_ctx ctx, char* buf, size_t cap, size_t* len);
+pnp_status pnp_tune_import(pnp_ctx ctx, const char* text);
+
 /* Read the status word left by an asynchronous call (after the stream has
  * finished the work).  workspace: the one passed to that call. */
 pnp_status pnp_read_status(pnp_ctx ctx, const void* workspace, void* stream);

@@ -29,6 +29,7 @@ EXPORTED = [
     "pnp_profile_select", "pnp_profile_read", "pnp_free_energy", "pnp_equilibrium", "pnp_bulk_mu_ex", "pnp_session_bytes", "pnp_pool_create", "pnp_pool_destroy",
     "pnp_pool_usage", "pnp_session_open", "pnp_session_step", "pnp_session_view", "pnp_session_close",
     "pnp_plan_create", "pnp_plan_launch", "pnp_plan_status", "pnp_plan_destroy", "pnp_pool_graphs",
+    "pnp_autotune", "pnp_tune_export", "pnp_tune_import",
 ]
 
 PASS_NAMES = ["tables", "z_fwd_rho", "y_fwd_rho", "x_fwd_weights", "y_inv_n", "z_deriv",
@@ -143,6 +144,9 @@ def load_library():
     lib.pnp_plan_destroy.argtypes = [P]
     lib.pnp_plan_destroy.restype = None
     lib.pnp_pool_graphs.argtypes = [P, ctypes.c_int32]
+    lib.pnp_autotune.argtypes = [P, ctypes.c_int32, ctypes.POINTER(RequestC), ctypes.c_int32, P]
+    lib.pnp_tune_export.argtypes = [P, ctypes.c_char_p, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)]
+    lib.pnp_tune_import.argtypes = [P, ctypes.c_char_p]
     lib.pnp_profile_enable.argtypes = [P, ctypes.c_int32]
     lib.pnp_profile_select.argtypes = [P, ctypes.c_uint32]
     lib.pnp_profile_read.argtypes = [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32),
@@ -194,6 +198,10 @@ class Evaluator:
             raise PnpError(st, "pnp_create failed")
         self.ctx = ctx
         self._ws = {}
+        cache = os.environ.get("PNP_TUNE_CACHE")
+        if cache and os.path.exists(cache):
+            with open(cache) as f:
+                self.tune_import(f.read())
 
     def close(self):
         if getattr(self, "ctx", None):
@@ -348,6 +356,29 @@ class Evaluator:
         st = self.lib.pnp_batch_mu_ex(self.ctx, count, reqs, self._stream())
         self._check(st)
         return mus, sls, [int(reqs[r].status) for r in range(count)]
+
+    def autotune(self, problems: Sequence, rhos: Sequence, reps: int = 3):
+        """Time both tile shapes of every pass on these problems (evaluated as
+        one batch) and keep the faster per pass in this context; returns the
+        statuses.  Saved to $PNP_TUNE_CACHE when that is set."""
+        count = len(problems)
+        reqs, keep, _, _ = self._requests(problems, rhos, True, None, None, None)
+        self._check(self.lib.pnp_autotune(self.ctx, count, reqs, int(reps), self._stream()))
+        cache = os.environ.get("PNP_TUNE_CACHE")
+        if cache:
+            with open(cache, "w") as f:
+                f.write(self.tune_export())
+        return [int(reqs[r].status) for r in range(count)]
+
+    def tune_export(self) -> str:
+        n = ctypes.c_size_t()
+        self._check(self.lib.pnp_tune_export(self.ctx, None, 0, ctypes.byref(n)))
+        buf = ctypes.create_string_buffer(n.value + 1)
+        self._check(self.lib.pnp_tune_export(self.ctx, buf, n.value + 1, ctypes.byref(n)))
+        return buf.value.decode()
+
+    def tune_import(self, text: str):
+        self._check(self.lib.pnp_tune_import(self.ctx, text.encode()))
 
     def plan(self, problems: Sequence, rhos: Sequence, slotboom=True, workspaces=None, outs=None,
              slots=None, relax=None):

@@ -34,6 +34,8 @@ struct pnp_ctx_s {
   double prof_ms[PNP_NUM_PASSES] = {0};
   int32_t prof_n[PNP_NUM_PASSES] = {0};
   bool capturing = false;  // a plan is being captured: no pass events
+  // autotuned tile shapes: (precision, n, count class) -> narrow-pass mask
+  std::map<uint64_t, uint32_t> tune;
 };
 
 namespace {
@@ -309,37 +311,40 @@ struct Ops {
   void (*xport)(const EvalArgs*, int, double*, int, hipStream_t);
 };
 
-template <typename T, int N> struct Launch {
-  using G = Geo<T, N>;
+template <typename T, int N, int V = 0> struct Launch {
+  using G = Geo<T, N, V>;
+  using GD = GeoD<T, N, default_ezd<T, N>(), V>;
+  static constexpr int EZD = default_ezd<T, N>();
   // maxS: the largest species count among the launch's instances
   static void tables(const TableArgs* a, int count, int M, int maxS, hipStream_t s) {
     const int items = maxS * ((maxS + 3) / 4 * 4) + maxS;  // pair-table entries + hs species
     hipLaunchKernelGGL(k_tables<T>, dim3((M + 255) / 256, items, count), dim3(256), 0, s, a);
   }
   static void zfwd(const EvalArgs* a, int count, hipStream_t s) {
-    hipLaunchKernelGGL((k_zfwd<T, N>), dim3(count * G::tiles_z), dim3(G::RZ * G::TZ), 0, s, a);
+    hipLaunchKernelGGL((k_zfwd<T, N, V>), dim3(count * G::tiles_z), dim3(G::RZ * G::TZ), 0, s, a);
   }
   static void ystep(const EvalArgs* a, int count, int sel, int nf, bool fwd, hipStream_t s) {
     if (fwd)
-      hipLaunchKernelGGL((k_ystep<T, N, true>), dim3(count * G::tiles_y), dim3(G::PY * G::TY), 0, s, a, sel, nf);
+      hipLaunchKernelGGL((k_ystep<T, N, true, V>), dim3(count * G::tiles_y), dim3(G::PY * G::TY), 0, s, a, sel, nf);
     else
-      hipLaunchKernelGGL((k_ystep<T, N, false>), dim3(count * G::tiles_y), dim3(G::PY * G::TY), 0, s, a, sel, nf);
+      hipLaunchKernelGGL((k_ystep<T, N, false, V>), dim3(count * G::tiles_y), dim3(G::PY * G::TY), 0, s, a, sel,
+                         nf);
   }
   static void xfwd(const EvalArgs* a, int count, hipStream_t s) {
-    hipLaunchKernelGGL((k_xfwd<T, N>), dim3(count * G::tiles_x), dim3(G::PX * G::TX), 0, s, a);
+    hipLaunchKernelGGL((k_xfwd<T, N, G::EX, G::PX>), dim3(count * G::tiles_x), dim3(G::PX * G::TX), 0, s, a);
   }
   // phi: also sum Phi_hs per workgroup (free-energy calls); fmask: the
   // hard-sphere functionals among the instances (1 Rosenfeld, 2 White Bear),
   // one launch of the matching variant each
   static void zderiv(const EvalArgs* a, int count, bool phi, int fmask, hipStream_t s) {
-    const dim3 g(count * GeoD<T, N>::tiles), b(GeoD<T, N>::RDD * GeoD<T, N>::TZD);
+    const dim3 g(count * GD::tiles), b(GD::RDD * GD::TZD);
     if (fmask & 1) {
-      if (phi) hipLaunchKernelGGL((k_zderiv<T, N, true, false>), g, b, 0, s, a);
-      else hipLaunchKernelGGL((k_zderiv<T, N, false, false>), g, b, 0, s, a);
+      if (phi) hipLaunchKernelGGL((k_zderiv<T, N, true, false, EZD, V>), g, b, 0, s, a);
+      else hipLaunchKernelGGL((k_zderiv<T, N, false, false, EZD, V>), g, b, 0, s, a);
     }
     if (fmask & 2) {
-      if (phi) hipLaunchKernelGGL((k_zderiv<T, N, true, true>), g, b, 0, s, a);
-      else hipLaunchKernelGGL((k_zderiv<T, N, false, true>), g, b, 0, s, a);
+      if (phi) hipLaunchKernelGGL((k_zderiv<T, N, true, true, EZD, V>), g, b, 0, s, a);
+      else hipLaunchKernelGGL((k_zderiv<T, N, false, true, EZD, V>), g, b, 0, s, a);
     }
   }
   // maxS: the largest species count among the launch's instances
@@ -348,74 +353,105 @@ template <typename T, int N> struct Launch {
     if constexpr (sizeof(T) == 8) {
       // FP64: the streamed kernel does not fit the register file; the chunked
       // one keeps every spectrum in registers without spilling
-      hipLaunchKernelGGL((k_xback_chunked<T, N, 4>), g, b, 0, s, a);
+      hipLaunchKernelGGL((k_xback_chunked<T, N, 4, G::EX, G::PX>), g, b, 0, s, a);
     } else {
       switch (maxS) {
-        case 1: hipLaunchKernelGGL((k_xback<T, N, 1>), g, b, 0, s, a); break;
-        case 2: hipLaunchKernelGGL((k_xback<T, N, 2>), g, b, 0, s, a); break;
-        case 3: hipLaunchKernelGGL((k_xback<T, N, 3>), g, b, 0, s, a); break;
-        case 4: hipLaunchKernelGGL((k_xback<T, N, 4>), g, b, 0, s, a); break;
-        default: hipLaunchKernelGGL((k_xback_chunked<T, N, 4>), g, b, 0, s, a); break;
+        case 1: hipLaunchKernelGGL((k_xback<T, N, 1, G::EX, G::PX>), g, b, 0, s, a); break;
+        case 2: hipLaunchKernelGGL((k_xback<T, N, 2, G::EX, G::PX>), g, b, 0, s, a); break;
+        case 3: hipLaunchKernelGGL((k_xback<T, N, 3, G::EX, G::PX>), g, b, 0, s, a); break;
+        case 4: hipLaunchKernelGGL((k_xback<T, N, 4, G::EX, G::PX>), g, b, 0, s, a); break;
+        default: hipLaunchKernelGGL((k_xback_chunked<T, N, 4, G::EX, G::PX>), g, b, 0, s, a); break;
       }
     }
   }
   static void zinv(const EvalArgs* a, int count, int sel, hipStream_t s) {
-    hipLaunchKernelGGL((k_zinv<T, N>), dim3(count * G::tiles_z), dim3(G::RZ * G::TZ), 0, s, a, sel);
+    hipLaunchKernelGGL((k_zinv<T, N, V>), dim3(count * G::tiles_z), dim3(G::RZ * G::TZ), 0, s, a, sel);
   }
   static void xplain(const EvalArgs* a, int count, int nf, bool fwd, hipStream_t s) {
     if (fwd)
-      hipLaunchKernelGGL((k_xplain<T, N, true>), dim3(count * G::tiles_x), dim3(G::PX * G::TX), 0, s, a, 0, nf);
+      hipLaunchKernelGGL((k_xplain<T, N, true, G::EX, G::PX>), dim3(count * G::tiles_x), dim3(G::PX * G::TX), 0, s,
+                         a, 0, nf);
     else
-      hipLaunchKernelGGL((k_xplain<T, N, false>), dim3(count * G::tiles_x), dim3(G::PX * G::TX), 0, s, a, 0, nf);
+      hipLaunchKernelGGL((k_xplain<T, N, false, G::EX, G::PX>), dim3(count * G::tiles_x), dim3(G::PX * G::TX), 0,
+                         s, a, 0, nf);
   }
   static void xport(const EvalArgs* a, int nf, double* buf, int to_numpy, hipStream_t s) {
     const long total = (long)nf * N * N * (N / 2 + 1);
     const int blocks = (int)std::min<long>((total + 255) / 256, 4096);
     hipLaunchKernelGGL((k_export<T, N>), dim3(blocks), dim3(256), 0, s, a, nf, buf, to_numpy);
   }
-  static constexpr Ops ops{tables, zfwd, ystep, xfwd, zderiv, xback, GeoD<T, N>::tiles, zinv, xplain, xport};
+  static constexpr Ops ops{tables, zfwd, ystep, xfwd, zderiv, xback, GD::tiles, zinv, xplain, xport};
 };
 
-template <typename T>
+// Grids up to kNarrowMax also have the narrow tile shape (V = 1); larger
+// ones already launch thousands of workgroups per pass.
+constexpr int kNarrowMax = 128;
+
+template <typename T, int V>
 const Ops* ops_for_n(int n) {
+  if (V == 1 && n > kNarrowMax) return nullptr;
   switch (n) {
-    case 8: return &Launch<T, 8>::ops;
-    case 16: return &Launch<T, 16>::ops;
-    case 24: return &Launch<T, 24>::ops;
-    case 32: return &Launch<T, 32>::ops;
-    case 48: return &Launch<T, 48>::ops;
-    case 64: return &Launch<T, 64>::ops;
-    case 96: return &Launch<T, 96>::ops;
-    case 128: return &Launch<T, 128>::ops;
-    case 192: return &Launch<T, 192>::ops;
-    case 256: return &Launch<T, 256>::ops;
+    case 8: return &Launch<T, 8, V>::ops;
+    case 16: return &Launch<T, 16, V>::ops;
+    case 24: return &Launch<T, 24, V>::ops;
+    case 32: return &Launch<T, 32, V>::ops;
+    case 48: return &Launch<T, 48, V>::ops;
+    case 64: return &Launch<T, 64, V>::ops;
+    case 96: return &Launch<T, 96, V>::ops;
+    case 128: return &Launch<T, 128, V>::ops;
+    case 192: return V == 0 ? &Launch<T, 192, 0>::ops : nullptr;
+    case 256: return V == 0 ? &Launch<T, 256, 0>::ops : nullptr;
     default: return nullptr;
   }
 }
 
-const Ops* ops_for(int precision, int n) {
-  return precision == PNP_MIXED ? ops_for_n<float>(n) : ops_for_n<double>(n);
+const Ops* ops_for(int precision, int n, int variant = 0) {
+  if (variant == 1) return precision == PNP_MIXED ? ops_for_n<float, 1>(n) : ops_for_n<double, 1>(n);
+  return precision == PNP_MIXED ? ops_for_n<float, 0>(n) : ops_for_n<double, 0>(n);
 }
+
+// The tile shape of each pass of one launch sequence: pass p runs the narrow
+// launcher when bit p of mask is set and one exists.
+struct OpsSel {
+  const Ops* v[2] = {nullptr, nullptr};
+  uint32_t mask = 0;
+  const Ops* at(int pass) const { return ((mask >> pass) & 1u) && v[1] ? v[1] : v[0]; }
+};
+
+// instance-count class of a launch, part of the tuning key
+int count_class(int count) { return count <= 1 ? 0 : count <= 3 ? 1 : count <= 15 ? 2 : 3; }
+
+uint64_t tune_key(int precision, int n, int cls) { return ((uint64_t)precision << 40) | ((uint64_t)n << 8) | cls; }
 
 // The full launch sequence for `count` instances of one size and precision.
 // ea: device arg tables; fmask: the hard-sphere functionals among the
 // instances (1 Rosenfeld, 2 White Bear, 0 no HS term); ch: output chunk of
 // the back pass.
-void run_sequence(pnp_ctx c, const Ops* op, const EvalArgs* ea, const TableArgs* ta, int count, int M,
+void run_sequence(pnp_ctx c, const OpsSel& op, const EvalArgs* ea, const TableArgs* ta, int count, int M,
                   int fmask, int ch, hipStream_t s) {
   PassTimer pt{c, s};
-  pt.begin(0); op->tables(ta, count, M, ch, s); pt.end();
-  pt.begin(1); op->zfwd(ea, count, s); pt.end();
-  pt.begin(2); op->ystep(ea, count, 0, -1, true, s); pt.end();
+  pt.begin(0); op.at(0)->tables(ta, count, M, ch, s); pt.end();
+  pt.begin(1); op.at(1)->zfwd(ea, count, s); pt.end();
+  pt.begin(2); op.at(2)->ystep(ea, count, 0, -1, true, s); pt.end();
   if (fmask) {
-    pt.begin(3); op->xfwd(ea, count, s); pt.end();
-    pt.begin(4); op->ystep(ea, count, 1, kVecMode, false, s); pt.end();
-    pt.begin(5); op->zderiv(ea, count, false, fmask, s); pt.end();
-    pt.begin(6); op->ystep(ea, count, 1, kVecMode, true, s); pt.end();
+    pt.begin(3); op.at(3)->xfwd(ea, count, s); pt.end();
+    pt.begin(4); op.at(4)->ystep(ea, count, 1, kVecMode, false, s); pt.end();
+    pt.begin(5); op.at(5)->zderiv(ea, count, false, fmask, s); pt.end();
+    pt.begin(6); op.at(6)->ystep(ea, count, 1, kVecMode, true, s); pt.end();
   }
-  pt.begin(7); op->xback(ea, count, ch, s); pt.end();
-  pt.begin(8); op->ystep(ea, count, 2, -1, false, s); pt.end();
-  pt.begin(9); op->zinv(ea, count, 2, s); pt.end();
+  pt.begin(7); op.at(7)->xback(ea, count, ch, s); pt.end();
+  pt.begin(8); op.at(8)->ystep(ea, count, 2, -1, false, s); pt.end();
+  pt.begin(9); op.at(9)->zinv(ea, count, 2, s); pt.end();
+}
+
+// the tuned tile shapes for a launch of `count` instances of (precision, n)
+OpsSel select_ops(pnp_ctx c, int precision, int n, int count) {
+  OpsSel o;
+  o.v[0] = ops_for(precision, n, 0);
+  o.v[1] = ops_for(precision, n, 1);
+  auto it = c->tune.find(tune_key(precision, n, count_class(count)));
+  if (it != c->tune.end()) o.mask = it->second;
+  return o;
 }
 
 // One launch group of a batch: the valid requests of one (precision, n),
@@ -664,7 +700,7 @@ pnp_status pnp_cdft_mu_ex(pnp_ctx ctx, const pnp_grid* g, int32_t S, const pnp_s
     const TableArgs* dta = (const TableArgs*)upload(ctx, &ta, sizeof(ta), s);
     const EvalArgs* dea = (const EvalArgs*)upload(ctx, &ea, sizeof(ea), s);
     if (!dta || !dea) return device_check(ctx, "argument upload");
-    run_sequence(ctx, op, dea, dta, 1, L.M, hs_mask(d), ch, s);
+    run_sequence(ctx, select_ops(ctx, d.precision, d.n, 1), dea, dta, 1, L.M, hs_mask(d), ch, s);
   } else {
     st = enqueue_per_term(ctx, d, g, sp, rho, p, L, w, mu, slot, nullptr, s);
     if (st != PNP_OK) return st;
@@ -741,7 +777,6 @@ pnp_status pnp_equilibrium(pnp_ctx ctx, const pnp_grid* g, int32_t S, const pnp_
   if (hipSetDevice(ctx->device) != hipSuccess) return device_check(ctx, "set device");
   hipStream_t s = (hipStream_t)stream;
   char* w = (char*)ws;
-  const Ops* op = ops_for(d.precision, d.n);
   unsigned long long* res = (unsigned long long*)(w + L.energy);
   const long n3 = (long)d.n * d.n * d.n;
   double rbmb[2 * kMaxSpecies];
@@ -760,7 +795,7 @@ pnp_status pnp_equilibrium(pnp_ctx ctx, const pnp_grid* g, int32_t S, const pnp_
   *iters = 0;
   *residual = INFINITY;
   for (int it = 1; it <= max_iter; ++it) {
-    run_sequence(ctx, op, dea, dta, 1, L.M, hs_mask(d), S, s);
+    run_sequence(ctx, select_ops(ctx, d.precision, d.n, 1), dea, dta, 1, L.M, hs_mask(d), S, s);
     if (hipMemsetAsync(res, 0, sizeof(unsigned long long), s) != hipSuccess) return device_check(ctx, "reset");
     hipLaunchKernelGGL(k_picard, dim3(blocks), dim3(256), 0, s, rho, (const double*)mu, beta_v, n3, (int)S, drb,
                        lambda, res);
@@ -836,7 +871,7 @@ pnp_status pnp_batch_mu_ex(pnp_ctx ctx, int32_t count, pnp_request* reqs, void* 
     const TableArgs* dta = (const TableArgs*)upload(ctx, g.ta.data(), sizeof(TableArgs) * cnt, s);
     const EvalArgs* dea = (const EvalArgs*)upload(ctx, g.ea.data(), sizeof(EvalArgs) * cnt, s);
     if (!dta || !dea) return device_check(ctx, "argument upload");
-    run_sequence(ctx, ops_for(g.precision, g.n), dea, dta, cnt, g.M, g.fmask, g.maxS, s);
+    run_sequence(ctx, select_ops(ctx, g.precision, g.n, cnt), dea, dta, cnt, g.M, g.fmask, g.maxS, s);
   }
   pnp_status st = device_check(ctx, "batch launch");
   if (st != PNP_OK) return st;
@@ -930,7 +965,7 @@ pnp_status pnp_plan_create(pnp_ctx ctx, int32_t count, pnp_request* reqs, const 
     ctx->capturing = true;
     for (size_t k = 0; k < groups.size(); ++k) {
       const Group& g = groups[k];
-      run_sequence(ctx, ops_for(g.precision, g.n), (const EvalArgs*)(blk + ea_off[k]),
+      run_sequence(ctx, select_ops(ctx, g.precision, g.n, (int)g.ids.size()), (const EvalArgs*)(blk + ea_off[k]),
                    (const TableArgs*)(blk + ta_off[k]), (int)g.ids.size(), g.M, g.fmask, g.maxS, cs);
     }
     if (relax)
@@ -989,6 +1024,95 @@ void pnp_plan_destroy(pnp_plan plan) {
     (void)hipFree(plan->block);
   }
   delete plan;
+}
+
+pnp_status pnp_autotune(pnp_ctx ctx, int32_t count, pnp_request* reqs, int32_t reps, void* stream) {
+  if (!ctx) return PNP_E_ARG;
+  if (count < 1 || !reqs || reps < 1) return fail(ctx, PNP_E_ARG, "bad autotune arguments");
+  if (hipSetDevice(ctx->device) != hipSuccess) return device_check(ctx, "set device");
+  hipStream_t s = (hipStream_t)stream;
+  std::vector<Layout> lay;
+  std::vector<Group> groups;
+  prepare_batch(ctx, count, reqs, lay, groups);
+  // the pass timers are borrowed: keep the caller's accumulated figures
+  const bool prof0 = ctx->prof;
+  const uint32_t mask0 = ctx->prof_mask;
+  double ms0[PNP_NUM_PASSES];
+  int32_t n0[PNP_NUM_PASSES];
+  pnp_status st = pnp_profile_read(ctx, ms0, n0, PNP_NUM_PASSES, 1);
+  if (st != PNP_OK) return st;
+  ctx->prof = true;
+  ctx->prof_mask = ~0u;
+  for (const Group& g : groups) {
+    const int cnt = (int)g.ids.size();
+    const TableArgs* dta = (const TableArgs*)upload(ctx, g.ta.data(), sizeof(TableArgs) * cnt, s);
+    const EvalArgs* dea = (const EvalArgs*)upload(ctx, g.ea.data(), sizeof(EvalArgs) * cnt, s);
+    if (!dta || !dea) { st = device_check(ctx, "argument upload"); break; }
+    OpsSel sel;
+    sel.v[0] = ops_for(g.precision, g.n, 0);
+    sel.v[1] = ops_for(g.precision, g.n, 1);
+    uint32_t best = 0;
+    if (sel.v[1]) {
+      double t[2][PNP_NUM_PASSES] = {};
+      for (int r = 0; r <= reps && st == PNP_OK; ++r)  // the first round warms up and is not counted
+        for (int v = 0; v < 2 && st == PNP_OK; ++v) {
+          sel.mask = v ? ~0u : 0u;
+          run_sequence(ctx, sel, dea, dta, cnt, g.M, g.fmask, g.maxS, s);
+          double ms[PNP_NUM_PASSES];
+          st = pnp_profile_read(ctx, ms, nullptr, PNP_NUM_PASSES, 1);
+          if (r > 0)
+            for (int p = 0; p < PNP_NUM_PASSES; ++p) t[v][p] += ms[p];
+        }
+      // narrow only where it wins clearly
+      for (int p = 1; p < PNP_NUM_PASSES; ++p)
+        if (t[1][p] < 0.97 * t[0][p]) best |= 1u << p;
+    }
+    if (st != PNP_OK) break;
+    ctx->tune[tune_key(g.precision, g.n, count_class(cnt))] = best;
+  }
+  ctx->prof = prof0;
+  ctx->prof_mask = mask0;
+  for (int p = 0; p < PNP_NUM_PASSES; ++p) { ctx->prof_ms[p] = ms0[p]; ctx->prof_n[p] = n0[p]; }
+  if (st != PNP_OK) return st;
+  if (hipStreamSynchronize(s) != hipSuccess) return device_check(ctx, "autotune sync");
+  return PNP_OK;
+}
+
+pnp_status pnp_tune_export(pnp_ctx ctx, char* buf, size_t cap, size_t* len) {
+  if (!ctx || !len) return PNP_E_ARG;
+  std::string out;
+  for (const auto& kv : ctx->tune) {
+    const int precision = (int)(kv.first >> 40), n = (int)((kv.first >> 8) & 0xffffffffu),
+              cls = (int)(kv.first & 0xff);
+    out += std::to_string(precision) + " " + std::to_string(n) + " " + std::to_string(cls) + " " +
+           std::to_string(kv.second) + "\n";
+  }
+  *len = out.size();
+  if (buf && cap > out.size()) std::memcpy(buf, out.c_str(), out.size() + 1);
+  else if (buf) return fail(ctx, PNP_E_ARG, "buffer too small");
+  return PNP_OK;
+}
+
+pnp_status pnp_tune_import(pnp_ctx ctx, const char* text) {
+  if (!ctx || !text) return PNP_E_ARG;
+  std::map<uint64_t, uint32_t> parsed;
+  const char* p = text;
+  while (*p) {
+    int precision, n, cls, used = 0;
+    unsigned mask;
+    if (std::sscanf(p, " %d %d %d %u%n", &precision, &n, &cls, &mask, &used) != 4) {
+      while (*p == ' ' || *p == '\n' || *p == '\t' || *p == '\r') ++p;
+      if (!*p) break;
+      return fail(ctx, PNP_E_ARG, "tuning text: expected lines 'precision n class mask'");
+    }
+    if ((precision != PNP_FP64 && precision != PNP_MIXED) || !size_ok(n) || cls < 0 || cls > 3 ||
+        (mask & 1u) || (mask >> PNP_NUM_PASSES))
+      return fail(ctx, PNP_E_ARG, "tuning text: entry out of range");
+    parsed[tune_key(precision, n, cls)] = mask;
+    p += used;
+  }
+  for (const auto& kv : parsed) ctx->tune[kv.first] = kv.second;
+  return PNP_OK;
 }
 
 pnp_status pnp_read_status(pnp_ctx ctx, const void* ws, void* stream) {

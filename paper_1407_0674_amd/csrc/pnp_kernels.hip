@@ -43,21 +43,27 @@ constexpr int pow2_divisor_le(long v, int cap) {
   return r;
 }
 
-template <typename T, int N> struct Geo {
+// V selects the tile shape: 0 the default (wide rows for full HBM bursts),
+// 1 narrow (a quarter of the rows or pencils per workgroup: four times the
+// workgroups, for grids too small to fill the chip).  The shape only changes
+// how many pencils a workgroup carries; every pencil's arithmetic is the same.
+constexpr int narrow(int v, int V) { return V == 0 ? v : (v / 4 > 1 ? v / 4 : 1); }
+
+template <typename T, int N, int V = 0> struct Geo {
   static constexpr int H = N / 2;
   static constexpr bool R3 = (N % 3 == 0);
   // z passes (P1, P9): complex FFT of length H, EZ elements per thread
   static constexpr int EZ = R3 ? 12 : (H >= 16 ? 16 : H);
   static constexpr int TZ = H / EZ;
-  static constexpr int RZ = pow2_divisor_le((long)N * N, 256 / TZ);  // rows per block
+  static constexpr int RZ = narrow(pow2_divisor_le((long)N * N, 256 / TZ), V);  // rows per block
   // y passes
   static constexpr int EY = R3 ? 12 : (N >= 16 ? 16 : N);
   static constexpr int TY = N / EY;
-  static constexpr int PY = pow2_divisor_le(N, sizeof(T) == 4 ? 16 : 8);
+  static constexpr int PY = narrow(pow2_divisor_le(N, sizeof(T) == 4 ? 16 : 8), V);
   // x passes
   static constexpr int EX = R3 ? 6 : (sizeof(T) == 4 ? (N >= 8 ? 8 : N) : (N >= 4 ? 4 : N));
   static constexpr int TX = N / EX;
-  static constexpr int PX = pow2_divisor_le(N, sizeof(T) == 4 ? 16 : 8);
+  static constexpr int PX = narrow(pow2_divisor_le(N, sizeof(T) == 4 ? 16 : 8), V);
   // tiles per instance
   static constexpr int tiles_z = (N * N) / RZ;
   static constexpr int tiles_y = (N * H) / PY + N / PY;
@@ -347,10 +353,10 @@ __device__ __forceinline__ uint64_t spec_bytes(const EvalArgs& a, int nf) {
 }
 
 // P1: z r2c of the S input densities (float64) into specA
-template <typename T, int N>
-__global__ void __launch_bounds__((Geo<T, N>::RZ * Geo<T, N>::TZ))
+template <typename T, int N, int V = 0>
+__global__ void __launch_bounds__((Geo<T, N, V>::RZ * Geo<T, N, V>::TZ))
     k_zfwd(const EvalArgs* __restrict__ args) {
-  using G = Geo<T, N>;
+  using G = Geo<T, N, V>;
   constexpr int H = G::H, TZ = G::TZ, EZ = G::EZ, RZ = G::RZ;
   __shared__ cx<T> twH[H];
   __shared__ cx<T> twN[N];
@@ -387,10 +393,10 @@ __global__ void __launch_bounds__((Geo<T, N>::RZ * Geo<T, N>::TZ))
 // P9 (final_mode = 1): z c2r of the S chemical-potential spectra in `sel`,
 // + constants, write beta mu_ex and exp(-beta mu_ex) in float64.
 // final_mode = 0: z c2r of `nreal` spectra of `sel` into out (no constant).
-template <typename T, int N>
-__global__ void __launch_bounds__((Geo<T, N>::RZ * Geo<T, N>::TZ))
+template <typename T, int N, int V = 0>
+__global__ void __launch_bounds__((Geo<T, N, V>::RZ * Geo<T, N, V>::TZ))
     k_zinv(const EvalArgs* __restrict__ args, int sel) {
-  using G = Geo<T, N>;
+  using G = Geo<T, N, V>;
   constexpr int H = G::H, TZ = G::TZ, EZ = G::EZ, RZ = G::RZ;
   __shared__ cx<T> twH[H];
   __shared__ cx<T> twN[N];
@@ -453,11 +459,11 @@ constexpr int default_ezd() {
   return ((N / 2) % 3 == 0) ? 6 : ((N / 2) >= (sizeof(T) == 4 ? 4 : 2) ? (sizeof(T) == 4 ? 4 : 2) : N / 2);
 }
 
-template <typename T, int N, int EZ = default_ezd<T, N>()> struct GeoD {
+template <typename T, int N, int EZ = default_ezd<T, N>(), int V = 0> struct GeoD {
   static constexpr int H = N / 2;
   static constexpr int EZD = EZ;
   static constexpr int TZD = H / EZD;
-  static constexpr int RDD = pow2_divisor_le((long)N * N, 256 / TZD < 1 ? 1 : 256 / TZD);
+  static constexpr int RDD = narrow(pow2_divisor_le((long)N * N, 256 / TZD < 1 ? 1 : 256 / TZD), V);
   static constexpr int tiles = (N * N) / RDD;
 };
 
@@ -540,10 +546,10 @@ __device__ __forceinline__ void wb_coeff(double x, double inv, double lnu, doubl
 // of instances that select the other one exit, so a launch list holding both
 // runs each variant over it and every instance gets the same arithmetic as
 // when evaluated alone
-template <typename T, int N, bool PHI = false, bool WB = false, int EZD = default_ezd<T, N>()>
-__global__ void __launch_bounds__((GeoD<T, N, EZD>::RDD * GeoD<T, N, EZD>::TZD))
+template <typename T, int N, bool PHI = false, bool WB = false, int EZD = default_ezd<T, N>(), int V = 0>
+__global__ void __launch_bounds__((GeoD<T, N, EZD, V>::RDD * GeoD<T, N, EZD, V>::TZD))
     k_zderiv(const EvalArgs* __restrict__ args) {
-  using D = GeoD<T, N, EZD>;
+  using D = GeoD<T, N, EZD, V>;
   constexpr int H = D::H, TZ = D::TZD, EZ = D::EZD, RD = D::RDD;
   __shared__ cx<T> twH[H];
   __shared__ cx<T> twN[N];
@@ -671,10 +677,10 @@ __device__ __forceinline__ void mul_isy(cx<T>* v, int t) {
   }
 }
 
-template <typename T, int N, bool FWD>
-__global__ void __launch_bounds__((Geo<T, N>::PY * Geo<T, N>::TY))
+template <typename T, int N, bool FWD, int V = 0>
+__global__ void __launch_bounds__((Geo<T, N, V>::PY * Geo<T, N, V>::TY))
     k_ystep(const EvalArgs* __restrict__ args, int sel, int nf_code) {
-  using G = Geo<T, N>;
+  using G = Geo<T, N, V>;
   constexpr int H = G::H, TY = G::TY, EY = G::EY, PY = G::PY;
   __shared__ cx<T> tw[N];
   __shared__ cx<T> xch[PY * N];

@@ -1,0 +1,76 @@
+"""GPU autotuner of tile shapes (pnp_autotune, pnp_tune_export/import).
+
+Tile shapes only change how many pencils a workgroup carries, so the bar is
+bit identity: every pass forced into the narrow shape gives the same bits
+as the default shape, at every size that has one, in both precisions, for
+single calls and batches; a tuned context equals an untuned one; the text
+form round-trips and malformed text is rejected without changing anything.
+"""
+import numpy as np
+import pytest
+import torch
+
+import pnp_inputs as P
+from conftest import to_dev
+from paper_1407_0674_amd import Evaluator, PnpError
+
+pytestmark = pytest.mark.gpu
+
+ALL_NARROW = sum(1 << p for p in range(1, 10))
+
+
+@pytest.fixture(scope="module")
+def ev2():
+    e = Evaluator(0)
+    yield e
+    e.close()
+
+
+@pytest.mark.parametrize("precision", [P.FP64, P.MIXED])
+def test_forced_narrow_equals_default(ev, ev2, precision):
+    sizes = (8, 16, 24, 32, 48, 64, 96, 128)
+    ev2.tune_import("".join(f"{precision} {n} {c} {ALL_NARROW}\n" for n in sizes for c in range(4)))
+    for n in sizes:
+        prob, rho = P.channel_problem(n, 6000 + n, precision=precision)
+        rd = to_dev(rho)
+        a_mu, a_sl = ev.mu_ex(prob, rd)
+        a_mu, a_sl = a_mu.clone(), a_sl.clone()
+        b_mu, b_sl = ev2.mu_ex(prob, rd)
+        assert torch.equal(a_mu, b_mu) and torch.equal(a_sl, b_sl), n
+    # batches (count classes 2-3 and 4-15) through both contexts
+    rng = np.random.default_rng(6100)
+    inst = [P.random_instance(rng, (16, 24, 32, 64), precision) for _ in range(6)]
+    probs = [p for p, _ in inst]
+    rhos = [to_dev(r) for _, r in inst]
+    ma, sa, st = ev.batch(probs, rhos)
+    mb, sb, st2 = ev2.batch(probs, rhos)
+    assert st == st2 == [0] * len(inst)
+    for k in range(len(inst)):
+        assert torch.equal(ma[k], mb[k]) and torch.equal(sa[k], sb[k]), k
+
+
+def test_autotune_keeps_results_and_exports(ev2):
+    fresh = Evaluator(0)
+    rng = np.random.default_rng(6200)
+    inst = [P.random_instance(rng, (32, 64), P.MIXED) for _ in range(3)]
+    probs = [p for p, _ in inst]
+    rhos = [to_dev(r) for _, r in inst]
+    assert fresh.autotune(probs[:1], rhos[:1], reps=2) == [0]
+    assert fresh.autotune(probs, rhos, reps=2) == [0, 0, 0]
+    text = fresh.tune_export()
+    lines = [l.split() for l in text.strip().splitlines()]
+    assert lines and all(len(l) == 4 for l in lines)
+    assert all(int(l[3]) & 1 == 0 and int(l[3]) < (1 << 10) for l in lines)
+    m1, s1, _ = fresh.batch(probs, rhos)
+    other = Evaluator(0)
+    m0, s0, _ = other.batch(probs, rhos)
+    for k in range(3):
+        assert torch.equal(m1[k], m0[k]) and torch.equal(s1[k], s0[k])
+    other.tune_import(text)
+    assert other.tune_export() == text
+    for bad in ("1 64 0", "2 64 0 0\n", "1 65 0 0\n", "1 64 7 0\n", "1 64 0 1\n", "1 64 0 4096\n"):
+        with pytest.raises(PnpError):
+            other.tune_import(bad)
+    assert other.tune_export() == text
+    other.close()
+    fresh.close()
