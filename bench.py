@@ -343,6 +343,10 @@ def bench_serve(ev, duration, rate):
     for r in reqs:
         sizes.setdefault((r.problem().n, r.problem().S), r)
     warm = list(sizes.values())
+    for prec in (None, 0):
+        serve_trace(ev, [P.Request(k, 0.0, r.seed, r.n_choices, r.precision, 1) for k, r in enumerate(warm)],
+                    prec, budget, 1 << 30)
+    lat1d, span1d, _ = serve_trace(ev, reqs, None, budget, 1)
     # tile shapes per size for single-session steps (the autotuner's single-instance class)
     import torch
     for prec in (None, 0):
@@ -352,10 +356,7 @@ def bench_serve(ev, duration, rate):
                 prob = prob.with_(precision=prec)
             n = prob.n
             rho0 = torch.from_numpy(prof).to("cuda:0")[:, :, None, :].expand(prob.S, n, n, n).contiguous()
-            ev.autotune([prob], [rho0], reps=2)
-    for prec in (None, 0):
-        serve_trace(ev, [P.Request(k, 0.0, r.seed, r.n_choices, r.precision, 1) for k, r in enumerate(warm)],
-                    prec, budget, 1 << 30)
+            ev.autotune([prob], [rho0], reps=5)
     lat, span, work = serve_trace(ev, reqs, None, budget, 1 << 30, work_cap=cap)
     lat_all, span_all, _ = serve_trace(ev, reqs, None, budget, 1 << 30)
     lat1, span1, _ = serve_trace(ev, reqs, None, budget, 1)
@@ -378,6 +379,9 @@ def bench_serve(ev, duration, rate):
                                        "throughput_req_s": len(lat_all) / span_all},
         "mixed_one_at_a_time": {"latency_ms": {"p50": percentile(lat1, 50), "p99": percentile(lat1, 99)},
                                 "throughput_req_s": len(lat1) / span1},
+        "mixed_one_at_a_time_default_tiles": {"latency_ms": {"p50": percentile(lat1d, 50),
+                                                             "p99": percentile(lat1d, 99)}},
+        "tuning": ev.tune_export().strip().splitlines(),
         "mixed_one_at_a_time_captured_steps": {"latency_ms": {"p50": percentile(lat1g, 50),
                                                               "p99": percentile(lat1g, 99)},
                                                "throughput_req_s": len(lat1g) / span1g},
