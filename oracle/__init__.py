@@ -10,11 +10,16 @@ What it computes (paper Sec. 2.3 and Sec. 3.4): for S species with densities
 rho_i on a periodic n^3 grid of spacing h,
 
   * the FMT weighted densities n_0..n_3, n_1v, n_2v  (Sec. 2.3.1),
-  * the ten partial derivatives of the Rosenfeld free-energy density,
+  * the ten partial derivatives of the Rosenfeld free-energy density (or of
+    the modified White Bear form),
   * the hard-sphere chemical potential by back-convolution (Sec. 2.3.1),
   * the MSA electrostatic-correlation term (Sec. 2.3.4),
   * the mean-field square-well term (Sec. 2.3.2),
   * beta*mu_ex and the Slotboom factor exp(-beta*mu_ex) (Sec. 2.1).
+
+An aperiodic mode (``mu_ex_aperiodic``: integrands zero outside the domain,
+convolutions on the doubled grid, Sec. 3.4) sits on top of the periodic
+operator.
 
 Two evaluation routes of the same discrete operator are provided:
 ``direct`` (O(N^2) real-space sums with kernels built by an explicit inverse
@@ -33,6 +38,7 @@ from .direct import correlate_direct, convolve_direct
 from .mu_ex import mu_ex, weighted_densities, free_energy
 from .relax import relax_densities
 from .equilibrium import picard, bulk_mu_ex
+from .aperiodic import mu_ex_aperiodic, extend, linear_convolution_1d, split_convolution_1d
 
 STATUS = {
     "units": "pinned: tests/test_oracle_units.py (Table 1 beta and l_B)",
@@ -43,6 +49,8 @@ STATUS = {
     "mu_ex": "pinned: tests/test_oracle_mu_ex.py (bulk closed forms, FD consistency, symmetry)",
     "relax": "pinned: tests/test_oracle_relax.py (lambda 0 and 1, bulk fixed point)",
     "equilibrium": "pinned: tests/test_oracle_equilibrium.py (bulk fixed point, dilute Boltzmann limit, self-consistency)",
+    "aperiodic": "pinned: tests/test_oracle_aperiodic.py (1D trapezoidal sum, domain sums of the linear terms, "
+                 "direct route, mirror covariance)",
 }
 
 __all__ = [
@@ -50,5 +58,6 @@ __all__ = [
     "ball_ft", "shell_ft", "shell_vec_ft", "r_ball_ft", "inv_r_ball_ft", "j0", "j1",
     "j1_over_x", "Operator", "build_operator", "real_space_kernel", "wavevectors",
     "phi_hs", "dphi_hs", "phi_hs_wb", "dphi_hs_wb", "correlate_direct", "convolve_direct", "mu_ex",
-    "weighted_densities", "free_energy", "relax_densities", "picard", "bulk_mu_ex", "STATUS",
+    "weighted_densities", "free_energy", "relax_densities", "picard", "bulk_mu_ex", "mu_ex_aperiodic",
+    "extend", "linear_convolution_1d", "split_convolution_1d", "STATUS",
 ]

@@ -84,9 +84,11 @@ def weighted_densities(problem, rho, route="direct", op=None, kernels=None):
     return _unpack_n(vals)
 
 
-def mu_ex(problem, rho, route="direct"):
+def mu_ex(problem, rho, route="direct", drho=None):
     """Returns a dict with 'n' (weighted densities), 'dphi', and per-term
-    arrays 'hs', 'el', 'sh', 'total', 'slotboom', each (S, n, n, n)."""
+    arrays 'hs', 'el', 'sh', 'total', 'slotboom', each (S, n, n, n).
+    drho: the density deviation the EC convolution integrates (default
+    rho - rho_bulk everywhere)."""
     rho = np.asarray(rho, dtype=np.float64)
     S, n = rho.shape[0], rho.shape[1]
     terms = problem.terms
@@ -94,7 +96,10 @@ def mu_ex(problem, rho, route="direct"):
     op = build_operator(problem, half=half)
     zero = np.zeros_like(rho)
     res = {"hs": zero.copy(), "el": zero.copy(), "sh": zero.copy(), "n": None, "dphi": None}
-    drho = rho - op.rho_bulk[:, None, None, None]
+    if drho is None:
+        drho = rho - op.rho_bulk[:, None, None, None]
+    else:
+        drho = np.asarray(drho, dtype=np.float64)
 
     hs_fn = _hs_functional(terms)
     if route == "direct":
