@@ -88,8 +88,19 @@ enum {
 
 /* flags */
 enum {
-  PNP_FLAG_ASYNC = 1  /* do not wait for the status word; read it later with
-                         pnp_read_status() */
+  PNP_FLAG_ASYNC = 1,     /* do not wait for the status word; read it later with
+                             pnp_read_status() */
+  PNP_FLAG_APERIODIC = 2  /* the grid is the domain of a non-periodic problem
+                             (Sec. 3.4): every convolution integrates over the
+                             domain only, its integrand (rho, or rho - rho_bulk
+                             for the EC term) zero outside, and runs on the
+                             doubled grid (2n)^3 of the same spacing with the
+                             domain at its corner; results are the domain's.
+                             n may be any size whose double is supported
+                             (4, 8, 12, 16, 24, 32, 48, 64, 96, 128).
+                             pnp_cdft_mu_ex and pnp_workspace_bytes only;
+                             pnp_bulk_mu_ex ignores it; every other entry
+                             point returns PNP_E_ARG. */
 };
 
 typedef struct pnp_ctx_s* pnp_ctx;

@@ -15,6 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 TERM_HS, TERM_EC, TERM_SW, TERM_ALL, TERM_HS_WB = 1, 2, 4, 7, 8
 FP64, MIXED = 0, 1
 FLAG_ASYNC = 1
+FLAG_APERIODIC = 2  # non-periodic domain: zero extension onto the doubled grid
 
 STATUS_NAMES = {
     0: "PNP_OK", -1: "PNP_E_ARG", -2: "PNP_E_UNSUPPORTED_SIZE", -3: "PNP_E_NOMEM",
@@ -222,8 +223,8 @@ class Evaluator:
     def _stream(self):
         return ctypes.c_void_p(_torch().cuda.current_stream().cuda_stream)
 
-    def workspace_bytes(self, problem, per_term=False, precision=None) -> int:
-        m = _Marshal(problem, per_term, precision=precision)
+    def workspace_bytes(self, problem, per_term=False, precision=None, flags=0) -> int:
+        m = _Marshal(problem, per_term, flags, precision=precision)
         out = ctypes.c_size_t()
         self._check(self.lib.pnp_workspace_bytes(self.ctx, ctypes.byref(m.grid), m.S,
                                                  ctypes.byref(m.params), ctypes.byref(out)))
@@ -259,7 +260,7 @@ class Evaluator:
             out = torch.empty(shape, dtype=torch.float64, device=rho.device)
         if slotboom and slot is None:
             slot = torch.empty((m.S, problem.n, problem.n, problem.n), dtype=torch.float64, device=rho.device)
-        nb = self.workspace_bytes(problem, per_term, precision)
+        nb = self.workspace_bytes(problem, per_term, precision, flags)
         ws = self.workspace(nb) if workspace is None else workspace
         st = self.lib.pnp_cdft_mu_ex(
             self.ctx, ctypes.byref(m.grid), m.S, m.species, self._dev(rho, "rho"), m.T,

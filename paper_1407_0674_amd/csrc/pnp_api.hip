@@ -106,6 +106,8 @@ struct Derived {
   int n = 0, S = 0, np = 0, precision = 0;
   double h = 0;
   bool hs = false, wb = false, ec = false, sw = false;  // wb: hard spheres by the White Bear form
+  bool aperiodic = false;  // n is the doubled grid; n_dom the domain (n_dom = n when periodic)
+  int n_dom = 0;
   double beta = 0, lB = 0, kappa = 0;
   double sigma[kMaxPairs], B[kMaxPairs], rout[kMaxPairs], eps[kMaxPairs];
   int pi[kMaxSpecies][kMaxSpecies];
@@ -146,13 +148,41 @@ Layout layout_of(int n, int S, int precision, bool hs, bool pairs, bool per_term
   return L;
 }
 
+// aperiodic_ok: the entry point accepts PNP_FLAG_APERIODIC (the evaluation
+// then runs on the doubled grid, and d.n is that grid's size)
+// The aperiodic mode adds, after the evaluation workspace of the doubled
+// grid n2: the zero-extended densities, the extended bulk densities of the
+// domain (EC only), the doubled-grid output, and the doubled-grid EC
+// response to those bulk densities (EC only); all float64 [S][n2^3], the
+// output [3][S][n2^3] in per-term mode.
+struct LayoutAp {
+  Layout L;
+  size_t rho, chi, muA, muB, total;
+};
+
+LayoutAp layout_aperiodic(int n2, int S, int precision, bool hs, bool pairs, bool ec, bool per_term) {
+  LayoutAp A;
+  A.L = layout_of(n2, S, precision, hs, pairs, per_term);
+  const size_t f = sizeof(double) * (size_t)S * n2 * n2 * n2;
+  size_t o = A.L.total;
+  A.rho = o; o = up(o + f);
+  A.chi = o; if (ec) o = up(o + f);
+  A.muA = o; o = up(o + (per_term ? 3 : 1) * f);
+  A.muB = o; if (ec) o = up(o + f);
+  A.total = o;
+  return A;
+}
+
 pnp_status validate(pnp_ctx ctx, const pnp_grid* g, int S, const pnp_species* sp, double T,
-                    const pnp_params* p, Derived& d, bool need_T) {
+                    const pnp_params* p, Derived& d, bool need_T, bool aperiodic_ok = false) {
   if (!ctx) return PNP_E_ARG;
   if (!g || !sp || !p) return fail(ctx, PNP_E_ARG, "null grid, species or params");
   if (g->nx != g->ny || g->ny != g->nz) return fail(ctx, PNP_E_UNSUPPORTED_SIZE, "grid must be cubic (nx = ny = nz)");
-  if (!size_ok(g->nx))
-    return fail(ctx, PNP_E_UNSUPPORTED_SIZE, "grid size " + std::to_string(g->nx) + " not supported");
+  const bool aperiodic = p->flags & PNP_FLAG_APERIODIC;
+  if (aperiodic && !aperiodic_ok) return fail(ctx, PNP_E_ARG, "PNP_FLAG_APERIODIC is not available here");
+  if (aperiodic ? !(g->nx >= 4 && g->nx <= 128 && size_ok(2 * g->nx)) : !size_ok(g->nx))
+    return fail(ctx, PNP_E_UNSUPPORTED_SIZE, "grid size " + std::to_string(g->nx) + " not supported" +
+                                                 (aperiodic ? " in the aperiodic mode (2n must be supported)" : ""));
   if (!(g->h > 0.0) || !std::isfinite(g->h)) return fail(ctx, PNP_E_ARG, "spacing h must be > 0");
   if (S < 1 || S > kMaxSpecies) return fail(ctx, PNP_E_ARG, "species count must be in [1, 8]");
   if (p->terms == 0 || (p->terms & ~15u)) return fail(ctx, PNP_E_ARG, "terms must be a non-empty PNP_TERM_* mask");
@@ -164,7 +194,10 @@ pnp_status validate(pnp_ctx ctx, const pnp_grid* g, int S, const pnp_species* sp
     if (!(sp[i].d > 0.0) || !std::isfinite(sp[i].q) || !std::isfinite(sp[i].rho_bulk) ||
         !std::isfinite(sp[i].mu_el_bulk))
       return fail(ctx, PNP_E_ARG, "species " + std::to_string(i) + ": bad diameter, valence or bulk density");
-  d.n = g->nx; d.h = g->h; d.S = S; d.np = S * (S + 1) / 2; d.precision = p->precision;
+  d.aperiodic = aperiodic;
+  d.n_dom = g->nx;
+  d.n = aperiodic ? 2 * g->nx : g->nx;
+  d.h = g->h; d.S = S; d.np = S * (S + 1) / 2; d.precision = p->precision;
   d.hs = p->terms & (PNP_TERM_HS | PNP_TERM_HS_WB); d.wb = p->terms & PNP_TERM_HS_WB; d.ec = p->terms & PNP_TERM_EC; d.sw = p->terms & PNP_TERM_SW;
   if (need_T) {
     if (d.ec && !(p->eps_r > 0.0)) return fail(ctx, PNP_E_ARG, "eps_r must be > 0");
@@ -195,9 +228,11 @@ pnp_status validate(pnp_ctx ctx, const pnp_grid* g, int S, const pnp_species* sp
     }
   for (int i = 0; i < S; ++i) {
     // the EC term's constant: its bulk value plus the k = 0 part of
-    // -sum_j C_ij rho_j^bulk; nothing when the EC term is off
+    // -sum_j C_ij rho_j^bulk; nothing when the EC term is off.  In the
+    // aperiodic mode the bulk densities are not uniform over the doubled grid
+    // (they fill the domain only), so that part is a separate convolution.
     double c = d.ec ? sp[i].mu_el_bulk : 0.0;
-    if (d.ec)
+    if (d.ec && !d.aperiodic)
       for (int j = 0; j < S; ++j) {
         const int pq = d.pi[i][j];
         const double s = d.sigma[pq], b = d.B[pq];
@@ -662,23 +697,96 @@ int pnp_supported_size(int32_t n) { return size_ok(n) ? 1 : 0; }
 
 pnp_status pnp_workspace_bytes(pnp_ctx ctx, const pnp_grid* g, int32_t S, const pnp_params* p, size_t* bytes) {
   if (!ctx || !g || !p || !bytes) return fail(ctx, PNP_E_ARG, "null argument");
-  if (g->nx != g->ny || g->ny != g->nz || !size_ok(g->nx))
+  const bool aperiodic = p->flags & PNP_FLAG_APERIODIC;
+  if (g->nx != g->ny || g->ny != g->nz ||
+      (aperiodic ? !(g->nx >= 4 && g->nx <= 128 && size_ok(2 * g->nx)) : !size_ok(g->nx)))
     return fail(ctx, PNP_E_UNSUPPORTED_SIZE, "unsupported grid");
   if (S < 1 || S > kMaxSpecies) return fail(ctx, PNP_E_ARG, "species count must be in [1, 8]");
   if (p->precision != PNP_FP64 && p->precision != PNP_MIXED) return fail(ctx, PNP_E_ARG, "bad precision");
   const bool hs = p->terms & (PNP_TERM_HS | PNP_TERM_HS_WB), pairs = p->terms & (PNP_TERM_EC | PNP_TERM_SW);
-  *bytes = layout_of(g->nx, S, p->precision, hs, pairs, p->per_term).total;
+  *bytes = aperiodic ? layout_aperiodic(2 * g->nx, S, p->precision, hs, pairs, p->terms & PNP_TERM_EC, p->per_term).total
+                     : layout_of(g->nx, S, p->precision, hs, pairs, p->per_term).total;
   return PNP_OK;
+}
+
+// The aperiodic evaluation (Sec. 3.4): extend, the EC response to the
+// domain's bulk densities (EC only), the evaluation of the extended densities
+// on the doubled grid, and the domain part of their difference.
+static pnp_status enqueue_aperiodic(pnp_ctx ctx, const Derived& d, const pnp_grid* g, const pnp_species* sp,
+                                    const double* rho, const pnp_params* p, const LayoutAp& A, char* w, double* mu,
+                                    double* slot, hipStream_t s) {
+  const int S = d.S;
+  const Layout& L = A.L;
+  const bool pairs = d.ec || d.sw;
+  double* ext = (double*)(w + A.rho);
+  double* chi = d.ec ? (double*)(w + A.chi) : nullptr;
+  double* muA = (double*)(w + A.muA);
+  double* muB = d.ec ? (double*)(w + A.muB) : nullptr;
+  double rb[kMaxSpecies];
+  for (int i = 0; i < S; ++i) rb[i] = sp[i].rho_bulk;
+  const double* drb = (const double*)upload(ctx, rb, sizeof(double) * S, s);
+  if (!drb) return device_check(ctx, "argument upload");
+  const long N2 = (long)d.n * d.n * d.n;
+  const int xb = (int)std::min<long>((S * N2 + 255) / 256, 8192);
+  hipLaunchKernelGGL(k_extend, dim3(xb), dim3(256), 0, s, rho, ext, chi, drb, S, d.n_dom);
+  const OpsSel ops = select_ops(ctx, d.precision, d.n, 1);
+  if (d.ec) {
+    // -sum_j C_ij (*) rho_b,j chi_domain: the EC term alone, no constant
+    Derived dB = d;
+    dB.hs = dB.wb = dB.sw = false;
+    TableArgs ta;
+    fill_table_args(ta, dB, sp, g->h, p->sw_prefactor, true, false, w + L.hs, w + L.pair, L.M);
+    EvalArgs ea;
+    fill_eval_args(ea, dB, sp, L, w, chi);
+    for (int i = 0; i < S; ++i) ea.cfin[i] = 0.0;
+    ea.out = muB;
+    ea.slot = nullptr;
+    const TableArgs* dta = (const TableArgs*)upload(ctx, &ta, sizeof(ta), s);
+    const EvalArgs* dea = (const EvalArgs*)upload(ctx, &ea, sizeof(ea), s);
+    if (!dta || !dea) return device_check(ctx, "argument upload");
+    run_sequence(ctx, ops, dea, dta, 1, L.M, 0, S, s);
+  }
+  // the extended densities (their status word starts clean here)
+  if (!p->per_term) {
+    TableArgs ta;
+    fill_table_args(ta, d, sp, g->h, p->sw_prefactor, d.ec, d.sw, w + L.hs, pairs ? w + L.pair : nullptr, L.M);
+    EvalArgs ea;
+    fill_eval_args(ea, d, sp, L, w, ext);
+    ea.out = muA;
+    ea.slot = nullptr;
+    const TableArgs* dta = (const TableArgs*)upload(ctx, &ta, sizeof(ta), s);
+    const EvalArgs* dea = (const EvalArgs*)upload(ctx, &ea, sizeof(ea), s);
+    if (!dta || !dea) return device_check(ctx, "argument upload");
+    run_sequence(ctx, ops, dea, dta, 1, L.M, hs_mask(d), S, s);
+  } else {
+    const pnp_status st = enqueue_per_term(ctx, d, g, sp, ext, p, L, w, muA, nullptr, nullptr, s);
+    if (st != PNP_OK) return st;
+  }
+  const long N = (long)d.n_dom * d.n_dom * d.n_dom;
+  const int cb = (int)std::min<long>((S * N + 255) / 256, 8192);
+  hipLaunchKernelGGL(k_crop, dim3(cb), dim3(256), 0, s, (const double*)muA, (const double*)muB,
+                     p->per_term ? 3 : 1, S, d.n_dom, mu, slot, (uint32_t*)(w + L.status));
+  return device_check(ctx, "launch");
 }
 
 pnp_status pnp_cdft_mu_ex(pnp_ctx ctx, const pnp_grid* g, int32_t S, const pnp_species* sp, const double* rho,
                           double T, const pnp_params* p, double* mu, double* slot, void* ws, size_t ws_bytes,
                           void* stream) {
   Derived d;
-  pnp_status st = validate(ctx, g, S, sp, T, p, d, true);
+  pnp_status st = validate(ctx, g, S, sp, T, p, d, true, true);
   if (st != PNP_OK) return st;
   if (!rho || !mu || !ws) return fail(ctx, PNP_E_ARG, "null device pointer");
   if ((uintptr_t)ws % kAlign) return fail(ctx, PNP_E_ARG, "workspace must be 256-byte aligned");
+  if (d.aperiodic) {
+    const LayoutAp A = layout_aperiodic(d.n, S, d.precision, d.hs, d.ec || d.sw, d.ec, p->per_term);
+    if (ws_bytes < A.total) return fail(ctx, PNP_E_NOMEM, "workspace too small: need " + std::to_string(A.total));
+    if (hipSetDevice(ctx->device) != hipSuccess) return device_check(ctx, "set device");
+    hipStream_t s = (hipStream_t)stream;
+    st = enqueue_aperiodic(ctx, d, g, sp, rho, p, A, (char*)ws, mu, slot, s);
+    if (st != PNP_OK) return st;
+    if (p->flags & PNP_FLAG_ASYNC) return PNP_OK;
+    return read_status(ctx, (char*)ws + A.L.status, s);
+  }
   const bool pairs = d.ec || d.sw;
   const Layout L = layout_of(d.n, S, d.precision, d.hs, pairs, p->per_term);
   if (ws_bytes < L.total) return fail(ctx, PNP_E_NOMEM, "workspace too small: need " + std::to_string(L.total));
@@ -1186,8 +1294,11 @@ pnp_status pnp_bulk_mu_ex(pnp_ctx ctx, int32_t S, const pnp_species* sp, double 
   if (!ctx) ctx = &local;
   if (!mu) return fail(ctx, PNP_E_ARG, "null output");
   const pnp_grid g{8, 8, 8, 1.0};  // the bulk value does not depend on the grid
+  if (!p) return fail(ctx, PNP_E_ARG, "null params");
+  pnp_params q = *p;
+  q.flags &= ~(uint32_t)PNP_FLAG_APERIODIC;  // nor on the boundary mode
   Derived d;
-  pnp_status st = validate(ctx, &g, S, sp, T, p, d, true);
+  pnp_status st = validate(ctx, &g, S, sp, T, &q, d, true);
   if (st != PNP_OK) return st;
   // FMT at uniform densities: n_a = sum_i rho_i w_i^a(k = 0), the vector
   // densities vanish, and mu_i = sum_a dPhi/dn_a w_i^a(0) (Sec. 2.3.1)

@@ -1474,8 +1474,61 @@ __global__ void k_sum_exp(const double* mu3, double* slot, long sn3, uint32_t* s
   for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < sn3; e += (long)gridDim.x * blockDim.x) {
     const double m = mu3[e] + mu3[sn3 + e] + mu3[2 * sn3 + e];
     if (!isfinite(m)) { bad |= kStNonFinite; badidx = min(badidx, (uint32_t)e); }
-    if (-m > 709.782712893384) { bad |= kStOverflow; badidx = min(badidx, (uint32_t)e); }
+    if (slot && -m > 709.782712893384) { bad |= kStOverflow; badidx = min(badidx, (uint32_t)e); }
     if (slot) slot[e] = exp(-m);
+  }
+  if (bad) raise_status(status, bad, badidx);
+}
+
+// Aperiodic mode (Sec. 3.4): the domain's n^3 densities [S][n][n][n] placed at
+// the corner of the doubled grid [S][2n][2n][2n], zero elsewhere; with chi,
+// also the domain's bulk densities rb[s] extended the same way (the EC term
+// integrates rho - rho_bulk over the domain only).
+__global__ void k_extend(const double* rho, double* ext, double* chi, const double* rb, int S, int n) {
+  const long n2 = 2L * n, N2 = n2 * n2 * n2, total = (long)S * N2;
+  for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (long)gridDim.x * blockDim.x) {
+    const int s = (int)(e / N2);
+    long r = e - (long)s * N2;
+    const long z = r % n2;
+    r /= n2;
+    const long y = r % n2, x = r / n2;
+    const bool in = x < n && y < n && z < n;
+    ext[e] = in ? rho[(((long)s * n + x) * n + y) * n + z] : 0.0;
+    if (chi) chi[e] = in ? rb[s] : 0.0;
+  }
+}
+
+// Aperiodic mode: the domain part of the doubled-grid result.
+//   muA  [nterm][S][(2n)^3]: the evaluation of the extended densities
+//        (nterm = 3: hs, el, sh; 1: the total)
+//   muB  [S][(2n)^3] or null: the EC response to the extended bulk densities,
+//        subtracted from the EC term (from the total when nterm = 1)
+//   out  [nterm][S][n^3]; slot [S][n^3] = exp(-total) or null
+// Status as the final pass: non-finite totals, and exp(-mu) overflow when
+// slot is requested.
+__global__ void k_crop(const double* muA, const double* muB, int nterm, int S, int n, double* out, double* slot,
+                       uint32_t* status) {
+  const long n2 = 2L * n, N2 = n2 * n2 * n2, N = (long)n * n * n, total = (long)S * N;
+  uint32_t bad = 0u, badidx = 0xffffffffu;
+  for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (long)gridDim.x * blockDim.x) {
+    const int s = (int)(e / N);
+    long r = e - (long)s * N;
+    const long z = r % n;
+    r /= n;
+    const long y = r % n, x = r / n;
+    const long e2 = (long)s * N2 + (x * n2 + y) * n2 + z;
+    double tot = 0.0;
+    for (int t = 0; t < nterm; ++t) {
+      double v = muA[(long)t * S * N2 + e2];
+      if (muB && (nterm == 1 || t == 1)) v -= muB[e2];
+      out[(long)t * total + e] = v;
+      tot += v;
+    }
+    if (!isfinite(tot)) { bad |= kStNonFinite; badidx = min(badidx, (uint32_t)e); }
+    if (slot) {
+      if (-tot > 709.782712893384) { bad |= kStOverflow; badidx = min(badidx, (uint32_t)e); }
+      slot[e] = exp(-tot);
+    }
   }
   if (bad) raise_status(status, bad, badidx);
 }

@@ -1,0 +1,77 @@
+"""GPU aperiodic mode (PNP_FLAG_APERIODIC, Sec. 3.4): the domain's densities
+zero-extended onto the doubled grid, EC integrating rho - rho_bulk over the
+domain only, results read back on the domain; against the oracle's
+mu_ex_aperiodic per term and in total, FP64 (1e-10) and mixed (1e-5), at
+domain sizes whose double is supported (including 12, which is not a
+periodic size), with the White Bear functional, and the error paths."""
+import numpy as np
+import pytest
+
+import pnp_inputs as P
+from conftest import relerr, to_dev
+from oracle.aperiodic import mu_ex_aperiodic
+from paper_1407_0674_amd import FLAG_APERIODIC, PnpError
+
+pytestmark = pytest.mark.gpu
+
+
+def _check(ev, prob, rho, tol):
+    ref = mu_ex_aperiodic(prob, rho, "fft")
+    rd = to_dev(rho)
+    mu3, slot3 = ev.mu_ex(prob, rd, per_term=True, flags=FLAG_APERIODIC)
+    mu3 = mu3.cpu().numpy()
+    for k, name in enumerate(("hs", "el", "sh")):
+        for i in range(prob.S):
+            assert relerr(mu3[k, i], ref[name][i]) < tol, (name, i, relerr(mu3[k, i], ref[name][i]))
+    mu, slot = ev.mu_ex(prob, rd, flags=FLAG_APERIODIC)
+    assert relerr(mu.cpu().numpy(), ref["total"]) < tol
+    stol = tol * max(1.0, float(np.max(np.abs(ref["total"]))))
+    assert relerr(slot.cpu().numpy(), ref["slotboom"]) < stol
+    assert relerr(slot3.cpu().numpy(), ref["slotboom"]) < stol
+
+
+@pytest.mark.parametrize("n", [4, 8, 12, 16, 24])
+def test_aperiodic_fp64(ev, n):
+    prob, rho = P.channel_problem(n, 7000 + n)
+    sp = [P.Species(s.d, s.q, s.rho_bulk, 0.1 * (i + 1)) for i, s in enumerate(prob.species)]
+    _check(ev, prob.with_(species=sp), rho, 1e-10)
+
+
+@pytest.mark.parametrize("n", [16, 32])
+def test_aperiodic_mixed(ev, n):
+    prob, rho = P.channel_problem(n, 7100 + n, precision=P.MIXED)
+    _check(ev, prob, rho, 1e-5)
+
+
+def test_aperiodic_white_bear_and_subsets(ev):
+    prob, rho = P.channel_problem(12, 7200, terms=P.TERM_HS_WB | P.TERM_EC | P.TERM_SW)
+    _check(ev, prob, rho, 1e-10)
+    for terms in (P.TERM_HS, P.TERM_EC, P.TERM_SW, P.TERM_EC | P.TERM_SW):
+        _check(ev, prob.with_(terms=terms), rho, 1e-10)
+
+
+def test_aperiodic_64(ev):
+    prob, rho = P.config2(n=64)
+    _check(ev, prob, rho, 1e-10)
+
+
+def test_aperiodic_errors(ev):
+    prob, rho = P.channel_problem(16, 7300)
+    bad = prob.with_(n=20)  # 40 is not a supported size
+    with pytest.raises(PnpError) as e:
+        ev.mu_ex(bad, to_dev(np.zeros((3, 20, 20, 20)) + 1.0), flags=FLAG_APERIODIC)
+    assert e.value.status == -2
+    # entry points other than the single evaluation reject the flag
+    import ctypes
+    from paper_1407_0674_amd.binding import _Marshal
+    m = _Marshal(prob, True, FLAG_APERIODIC)
+    rd = to_dev(rho)
+    mu3 = to_dev(np.zeros((3,) + rho.shape))
+    ws = ev.workspace(ev.workspace_bytes(prob, True))
+    out = (ctypes.c_double * 4)()
+    st = ev.lib.pnp_free_energy(ev.ctx, ctypes.byref(m.grid), m.S, m.species, ctypes.c_void_p(rd.data_ptr()), m.T,
+                                ctypes.byref(m.params), out, ctypes.c_void_p(mu3.data_ptr()),
+                                ctypes.c_void_p(ws.data_ptr()), ctypes.c_size_t(ws.numel()), ev._stream())
+    assert st == -1
+    # the workspace query knows the mode: larger than the periodic one of the domain
+    assert ev.workspace_bytes(prob, False, None, FLAG_APERIODIC) > 8 * ev.workspace_bytes(prob)
