@@ -151,13 +151,13 @@ Layout layout_of(int n, int S, int precision, bool hs, bool pairs, bool per_term
 // aperiodic_ok: the entry point accepts PNP_FLAG_APERIODIC (the evaluation
 // then runs on the doubled grid, and d.n is that grid's size)
 // The aperiodic mode adds, after the evaluation workspace of the doubled
-// grid n2: the zero-extended densities, the extended bulk densities of the
-// domain (EC only), the doubled-grid output, and the doubled-grid EC
-// response to those bulk densities (EC only); all float64 [S][n2^3], the
-// output [3][S][n2^3] in per-term mode.
+// grid n2: the doubled-grid output and the doubled-grid EC response to the
+// domain's bulk densities (EC only); float64 [S][n2^3], the output
+// [3][S][n2^3] in per-term mode.  (The zero extension itself is read on the
+// fly by the first pass.)
 struct LayoutAp {
   Layout L;
-  size_t rho, chi, muA, muB, total;
+  size_t muA, muB, total;
 };
 
 LayoutAp layout_aperiodic(int n2, int S, int precision, bool hs, bool pairs, bool ec, bool per_term) {
@@ -165,8 +165,6 @@ LayoutAp layout_aperiodic(int n2, int S, int precision, bool hs, bool pairs, boo
   A.L = layout_of(n2, S, precision, hs, pairs, per_term);
   const size_t f = sizeof(double) * (size_t)S * n2 * n2 * n2;
   size_t o = A.L.total;
-  A.rho = o; o = up(o + f);
-  A.chi = o; if (ec) o = up(o + f);
   A.muA = o; o = up(o + (per_term ? 3 : 1) * f);
   A.muB = o; if (ec) o = up(o + f);
   A.total = o;
@@ -271,6 +269,7 @@ void fill_eval_args(EvalArgs& e, const Derived& d, const pnp_species* sp, const 
   std::memset(&e, 0, sizeof(e));
   e.n = d.n; e.S = d.S; e.np = d.np;
   e.hs_on = d.hs; e.hs_wb = d.wb; e.pair_on = d.ec || d.sw;
+  e.ext_n = d.aperiodic ? d.n_dom : 0;  // the first pass zero-extends the domain
   e.fstride = L.fstride;
   e.inv_n3 = 1.0 / ((double)d.n * d.n * d.n);
   e.kscale = 2.0 * M_PI / (d.n * d.h);
@@ -718,17 +717,8 @@ static pnp_status enqueue_aperiodic(pnp_ctx ctx, const Derived& d, const pnp_gri
   const int S = d.S;
   const Layout& L = A.L;
   const bool pairs = d.ec || d.sw;
-  double* ext = (double*)(w + A.rho);
-  double* chi = d.ec ? (double*)(w + A.chi) : nullptr;
   double* muA = (double*)(w + A.muA);
   double* muB = d.ec ? (double*)(w + A.muB) : nullptr;
-  double rb[kMaxSpecies];
-  for (int i = 0; i < S; ++i) rb[i] = sp[i].rho_bulk;
-  const double* drb = (const double*)upload(ctx, rb, sizeof(double) * S, s);
-  if (!drb) return device_check(ctx, "argument upload");
-  const long N2 = (long)d.n * d.n * d.n;
-  const int xb = (int)std::min<long>((S * N2 + 255) / 256, 8192);
-  hipLaunchKernelGGL(k_extend, dim3(xb), dim3(256), 0, s, rho, ext, chi, drb, S, d.n_dom);
   const OpsSel ops = select_ops(ctx, d.precision, d.n, 1);
   if (d.ec) {
     // -sum_j C_ij (*) rho_b,j chi_domain: the EC term alone, no constant
@@ -737,8 +727,12 @@ static pnp_status enqueue_aperiodic(pnp_ctx ctx, const Derived& d, const pnp_gri
     TableArgs ta;
     fill_table_args(ta, dB, sp, g->h, p->sw_prefactor, true, false, w + L.hs, w + L.pair, L.M);
     EvalArgs ea;
-    fill_eval_args(ea, dB, sp, L, w, chi);
-    for (int i = 0; i < S; ++i) ea.cfin[i] = 0.0;
+    fill_eval_args(ea, dB, sp, L, w, nullptr);
+    ea.ext_bulk = 1;
+    for (int i = 0; i < S; ++i) {
+      ea.cfin[i] = 0.0;
+      ea.ext_val[i] = sp[i].rho_bulk;
+    }
     ea.out = muB;
     ea.slot = nullptr;
     const TableArgs* dta = (const TableArgs*)upload(ctx, &ta, sizeof(ta), s);
@@ -751,7 +745,7 @@ static pnp_status enqueue_aperiodic(pnp_ctx ctx, const Derived& d, const pnp_gri
     TableArgs ta;
     fill_table_args(ta, d, sp, g->h, p->sw_prefactor, d.ec, d.sw, w + L.hs, pairs ? w + L.pair : nullptr, L.M);
     EvalArgs ea;
-    fill_eval_args(ea, d, sp, L, w, ext);
+    fill_eval_args(ea, d, sp, L, w, rho);
     ea.out = muA;
     ea.slot = nullptr;
     const TableArgs* dta = (const TableArgs*)upload(ctx, &ta, sizeof(ta), s);
@@ -759,7 +753,7 @@ static pnp_status enqueue_aperiodic(pnp_ctx ctx, const Derived& d, const pnp_gri
     if (!dta || !dea) return device_check(ctx, "argument upload");
     run_sequence(ctx, ops, dea, dta, 1, L.M, hs_mask(d), S, s);
   } else {
-    const pnp_status st = enqueue_per_term(ctx, d, g, sp, ext, p, L, w, muA, nullptr, nullptr, s);
+    const pnp_status st = enqueue_per_term(ctx, d, g, sp, rho, p, L, w, muA, nullptr, nullptr, s);
     if (st != PNP_OK) return st;
   }
   const long N = (long)d.n_dom * d.n_dom * d.n_dom;

@@ -375,18 +375,42 @@ __global__ void __launch_bounds__((Geo<T, N, V>::RZ * Geo<T, N, V>::TZ))
   const uint32_t row = (uint32_t)(tile * RZ + r);
   cx<T>* lrow = xch + r * H;
   const LdsPencil<T, row_in_wave<TZ>()> lp{lrow, 1};
-  constexpr uint32_t n3b = (uint32_t)N * N * N * sizeof(double);
-  const Buf rho = make_buf(a.rho, (uint64_t)a.S * n3b);
   const Buf A = make_buf(a.specA, spec_bytes<T>(a, a.S));
-  for (int s = 0; s < a.S; ++s) {
-    cx<T> v[EZ];
+  if (a.ext_n == 0) {
+    constexpr uint32_t n3b = (uint32_t)N * N * N * sizeof(double);
+    const Buf rho = make_buf(a.rho, (uint64_t)a.S * n3b);
+    for (int s = 0; s < a.S; ++s) {
+      cx<T> v[EZ];
 #pragma unroll
-    for (int m = 0; m < EZ; ++m) {
-      const cf64 p = rho.ld<cf64>((row * H + t + TZ * m) * (uint32_t)sizeof(cf64), (uint32_t)s * n3b);
-      v[m] = mk<T>((T)p.x, (T)p.y);
+      for (int m = 0; m < EZ; ++m) {
+        const cf64 p = rho.ld<cf64>((row * H + t + TZ * m) * (uint32_t)sizeof(cf64), (uint32_t)s * n3b);
+        v[m] = mk<T>((T)p.x, (T)p.y);
+      }
+      fft_pencil<T, H, EZ, true>(v, t, twH, lp);
+      r2c_post<T, N, TZ, EZ>(v, t, twN, lrow, A, (uint32_t)(s * a.fstride * sizeof(cx<T>)), row);
     }
-    fft_pencil<T, H, EZ, true>(v, t, twH, lp);
-    r2c_post<T, N, TZ, EZ>(v, t, twN, lrow, A, (uint32_t)(s * a.fstride * sizeof(cx<T>)), row);
+  } else {
+    // zero extension of the (even-sized) domain: the point pair (2j, 2j+1)
+    // lies inside or outside it as a whole
+    const uint32_t nd = (uint32_t)a.ext_n, x = row / N, y = row % N;
+    const bool row_in = x < nd && y < nd;
+    const uint32_t d3b = nd * nd * nd * (uint32_t)sizeof(double);
+    const Buf rho = make_buf(a.rho, a.ext_bulk ? 0 : (uint64_t)a.S * d3b);
+    for (int s = 0; s < a.S; ++s) {
+      cx<T> v[EZ];
+#pragma unroll
+      for (int m = 0; m < EZ; ++m) {
+        const uint32_t j = t + TZ * m;
+        cf64 p{0.0, 0.0};
+        if (row_in && 2 * j < nd) {
+          if (a.ext_bulk) p = cf64{a.ext_val[s], a.ext_val[s]};
+          else p = rho.ld<cf64>(((x * nd + y) * nd + 2 * j) * (uint32_t)sizeof(double), (uint32_t)s * d3b);
+        }
+        v[m] = mk<T>((T)p.x, (T)p.y);
+      }
+      fft_pencil<T, H, EZ, true>(v, t, twH, lp);
+      r2c_post<T, N, TZ, EZ>(v, t, twN, lrow, A, (uint32_t)(s * a.fstride * sizeof(cx<T>)), row);
+    }
   }
 }
 
@@ -1478,24 +1502,6 @@ __global__ void k_sum_exp(const double* mu3, double* slot, long sn3, uint32_t* s
     if (slot) slot[e] = exp(-m);
   }
   if (bad) raise_status(status, bad, badidx);
-}
-
-// Aperiodic mode (Sec. 3.4): the domain's n^3 densities [S][n][n][n] placed at
-// the corner of the doubled grid [S][2n][2n][2n], zero elsewhere; with chi,
-// also the domain's bulk densities rb[s] extended the same way (the EC term
-// integrates rho - rho_bulk over the domain only).
-__global__ void k_extend(const double* rho, double* ext, double* chi, const double* rb, int S, int n) {
-  const long n2 = 2L * n, N2 = n2 * n2 * n2, total = (long)S * N2;
-  for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (long)gridDim.x * blockDim.x) {
-    const int s = (int)(e / N2);
-    long r = e - (long)s * N2;
-    const long z = r % n2;
-    r /= n2;
-    const long y = r % n2, x = r / n2;
-    const bool in = x < n && y < n && z < n;
-    ext[e] = in ? rho[(((long)s * n + x) * n + y) * n + z] : 0.0;
-    if (chi) chi[e] = in ? rb[s] : 0.0;
-  }
 }
 
 // Aperiodic mode: the domain part of the doubled-grid result.

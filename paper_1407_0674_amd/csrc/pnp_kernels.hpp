@@ -56,6 +56,12 @@ struct EvalArgs {
   double* slot;       // [S][n^3] exp(-mu) or null
   uint32_t* status;   // two words
   double* phi_part;   // per-workgroup sums of Phi_hs from the derivative pass, or null
+  // aperiodic mode: the first pass reads an ext_n^3 domain [S][ext_n]^3 and
+  // treats it as zero-extended onto the n^3 grid (domain at the corner); with
+  // ext_bulk the domain holds ext_val[s] everywhere instead of rho
+  int32_t ext_n;
+  int32_t ext_bulk;
+  double ext_val[kMaxSpecies];
 };
 
 // Per-instance arguments of the radial table builder.
