@@ -338,7 +338,7 @@ struct Ops {
   void (*ystep)(const EvalArgs*, int, int, int, bool, hipStream_t);
   void (*xfwd)(const EvalArgs*, int, hipStream_t);
   void (*zderiv)(const EvalArgs*, int, bool, int, hipStream_t);
-  void (*xback)(const EvalArgs*, int, int, hipStream_t);
+  void (*xback)(const EvalArgs*, int, int, bool, hipStream_t);
   int zderiv_tiles;  // workgroups of the derivative pass per instance
   void (*zinv)(const EvalArgs*, int, int, hipStream_t);
   void (*xplain)(const EvalArgs*, int, int, bool, hipStream_t);
@@ -381,21 +381,26 @@ template <typename T, int N, int V = 0> struct Launch {
       else hipLaunchKernelGGL((k_zderiv<T, N, false, true, EZD, V>), g, b, 0, s, a);
     }
   }
-  // maxS: the largest species count among the launch's instances
-  static void xback(const EvalArgs* a, int count, int maxS, hipStream_t s) {
+  // smax: the largest species count among the launch's instances with at
+  // most four species (0: none); large: some instance has more than four.
+  // The FP32 path runs the streamed kernel for the former and the chunked one
+  // for the latter (each skips the other's instances), so an instance gets
+  // the arithmetic of its single call in any launch list.
+  static void xback(const EvalArgs* a, int count, int smax, bool large, hipStream_t s) {
     const dim3 g(count * G::tiles_x), b(G::PX * G::TX);
     if constexpr (sizeof(T) == 8) {
       // FP64: the streamed kernel does not fit the register file; the chunked
       // one keeps every spectrum in registers without spilling
-      hipLaunchKernelGGL((k_xback_chunked<T, N, 4, G::EX, G::PX>), g, b, 0, s, a);
+      hipLaunchKernelGGL((k_xback_chunked<T, N, 4, G::EX, G::PX>), g, b, 0, s, a, 1);
     } else {
-      switch (maxS) {
+      switch (smax) {
         case 1: hipLaunchKernelGGL((k_xback<T, N, 1, G::EX, G::PX>), g, b, 0, s, a); break;
         case 2: hipLaunchKernelGGL((k_xback<T, N, 2, G::EX, G::PX>), g, b, 0, s, a); break;
         case 3: hipLaunchKernelGGL((k_xback<T, N, 3, G::EX, G::PX>), g, b, 0, s, a); break;
         case 4: hipLaunchKernelGGL((k_xback<T, N, 4, G::EX, G::PX>), g, b, 0, s, a); break;
-        default: hipLaunchKernelGGL((k_xback_chunked<T, N, 4, G::EX, G::PX>), g, b, 0, s, a); break;
+        default: break;
       }
+      if (large) hipLaunchKernelGGL((k_xback_chunked<T, N, 4, G::EX, G::PX>), g, b, 0, s, a, 5);
     }
   }
   static void zinv(const EvalArgs* a, int count, int sel, hipStream_t s) {
@@ -458,13 +463,30 @@ int count_class(int count) { return count <= 1 ? 0 : count <= 3 ? 1 : count <= 1
 uint64_t tune_key(int precision, int n, int cls) { return ((uint64_t)precision << 40) | ((uint64_t)n << 8) | cls; }
 
 // The full launch sequence for `count` instances of one size and precision.
+// Species counts of a launch list: the largest, and the largest among the
+// instances with at most four species (0: none), which select the back-pass
+// kernels.
+struct SpeciesMix {
+  int maxS = 1, small = 0;
+  void add(int S) {
+    maxS = std::max(maxS, S);
+    if (S <= 4) small = std::max(small, S);
+  }
+};
+
+inline SpeciesMix mix_of(int S) {
+  SpeciesMix m;
+  m.add(S);
+  return m;
+}
+
 // ea: device arg tables; fmask: the hard-sphere functionals among the
-// instances (1 Rosenfeld, 2 White Bear, 0 no HS term); ch: output chunk of
-// the back pass.
+// instances (1 Rosenfeld, 2 White Bear, 0 no HS term); sm: their species
+// counts.
 void run_sequence(pnp_ctx c, const OpsSel& op, const EvalArgs* ea, const TableArgs* ta, int count, int M,
-                  int fmask, int ch, hipStream_t s) {
+                  int fmask, const SpeciesMix& sm, hipStream_t s) {
   PassTimer pt{c, s};
-  pt.begin(0); op.at(0)->tables(ta, count, M, ch, s); pt.end();
+  pt.begin(0); op.at(0)->tables(ta, count, M, sm.maxS, s); pt.end();
   pt.begin(1); op.at(1)->zfwd(ea, count, s); pt.end();
   pt.begin(2); op.at(2)->ystep(ea, count, 0, -1, true, s); pt.end();
   if (fmask) {
@@ -473,7 +495,7 @@ void run_sequence(pnp_ctx c, const OpsSel& op, const EvalArgs* ea, const TableAr
     pt.begin(5); op.at(5)->zderiv(ea, count, false, fmask, s); pt.end();
     pt.begin(6); op.at(6)->ystep(ea, count, 1, kVecMode, true, s); pt.end();
   }
-  pt.begin(7); op.at(7)->xback(ea, count, ch, s); pt.end();
+  pt.begin(7); op.at(7)->xback(ea, count, sm.small, sm.maxS > 4, s); pt.end();
   pt.begin(8); op.at(8)->ystep(ea, count, 2, -1, false, s); pt.end();
   pt.begin(9); op.at(9)->zinv(ea, count, 2, s); pt.end();
 }
@@ -495,7 +517,8 @@ struct Group {
   std::vector<int> ids;
   std::vector<TableArgs> ta;
   std::vector<EvalArgs> ea;
-  int fmask = 0, maxS = 1, M = 0;
+  int fmask = 0, M = 0;
+  SpeciesMix mix;
 };
 
 // Validate every request (its status field receives the result) and build
@@ -540,7 +563,7 @@ void prepare_batch(pnp_ctx ctx, int count, pnp_request* reqs, std::vector<Layout
       g.ea[k].out = q.mu_ex;
       g.ea[k].slot = q.slotboom;
       g.fmask |= hs_mask(d);
-      g.maxS = std::max(g.maxS, q.S);
+      g.mix.add(q.S);
       g.M = std::max(g.M, L.M);
     }
     out.push_back(std::move(g));
@@ -575,7 +598,6 @@ static pnp_status enqueue_per_term(pnp_ctx ctx, const Derived& d, const pnp_grid
   const bool pairs = d.ec || d.sw;
   const Ops* op = ops_for(d.precision, d.n);
   const double sw_c = p->sw_prefactor;
-  const int ch = S;
   const long n3 = (long)d.n * d.n * d.n;
   // tables: HS (+ EC pairs into pair), SW pairs into pair2
   TableArgs ta[2];
@@ -614,7 +636,7 @@ static pnp_status enqueue_per_term(pnp_ctx ctx, const Derived& d, const pnp_grid
     pt.begin(6); op->ystep(dea, 1, 1, kVecMode, true, s); pt.end();
   }
   for (int k = 1; k < 4; ++k) {
-    pt.begin(7); op->xback(dea + k, 1, ch, s); pt.end();
+    pt.begin(7); op->xback(dea + k, 1, S <= 4 ? S : 0, S > 4, s); pt.end();
     pt.begin(8); op->ystep(dea + k, 1, 2, -1, false, s); pt.end();
     pt.begin(9); op->zinv(dea + k, 1, 2, s); pt.end();
   }
@@ -738,7 +760,7 @@ static pnp_status enqueue_aperiodic(pnp_ctx ctx, const Derived& d, const pnp_gri
     const TableArgs* dta = (const TableArgs*)upload(ctx, &ta, sizeof(ta), s);
     const EvalArgs* dea = (const EvalArgs*)upload(ctx, &ea, sizeof(ea), s);
     if (!dta || !dea) return device_check(ctx, "argument upload");
-    run_sequence(ctx, ops, dea, dta, 1, L.M, 0, S, s);
+    run_sequence(ctx, ops, dea, dta, 1, L.M, 0, mix_of(S), s);
   }
   // the extended densities (their status word starts clean here)
   if (!p->per_term) {
@@ -751,7 +773,7 @@ static pnp_status enqueue_aperiodic(pnp_ctx ctx, const Derived& d, const pnp_gri
     const TableArgs* dta = (const TableArgs*)upload(ctx, &ta, sizeof(ta), s);
     const EvalArgs* dea = (const EvalArgs*)upload(ctx, &ea, sizeof(ea), s);
     if (!dta || !dea) return device_check(ctx, "argument upload");
-    run_sequence(ctx, ops, dea, dta, 1, L.M, hs_mask(d), S, s);
+    run_sequence(ctx, ops, dea, dta, 1, L.M, hs_mask(d), mix_of(S), s);
   } else {
     const pnp_status st = enqueue_per_term(ctx, d, g, sp, rho, p, L, w, muA, nullptr, nullptr, s);
     if (st != PNP_OK) return st;
@@ -789,7 +811,6 @@ pnp_status pnp_cdft_mu_ex(pnp_ctx ctx, const pnp_grid* g, int32_t S, const pnp_s
   const Ops* op = ops_for(d.precision, d.n);
   char* w = (char*)ws;
   const double sw_c = p->sw_prefactor;
-  const int ch = S;  // largest species count of the launch (selects the back-pass kernel)
   const long n3 = (long)d.n * d.n * d.n;
 
   if (!p->per_term) {
@@ -802,7 +823,7 @@ pnp_status pnp_cdft_mu_ex(pnp_ctx ctx, const pnp_grid* g, int32_t S, const pnp_s
     const TableArgs* dta = (const TableArgs*)upload(ctx, &ta, sizeof(ta), s);
     const EvalArgs* dea = (const EvalArgs*)upload(ctx, &ea, sizeof(ea), s);
     if (!dta || !dea) return device_check(ctx, "argument upload");
-    run_sequence(ctx, select_ops(ctx, d.precision, d.n, 1), dea, dta, 1, L.M, hs_mask(d), ch, s);
+    run_sequence(ctx, select_ops(ctx, d.precision, d.n, 1), dea, dta, 1, L.M, hs_mask(d), mix_of(S), s);
   } else {
     st = enqueue_per_term(ctx, d, g, sp, rho, p, L, w, mu, slot, nullptr, s);
     if (st != PNP_OK) return st;
@@ -897,7 +918,7 @@ pnp_status pnp_equilibrium(pnp_ctx ctx, const pnp_grid* g, int32_t S, const pnp_
   *iters = 0;
   *residual = INFINITY;
   for (int it = 1; it <= max_iter; ++it) {
-    run_sequence(ctx, select_ops(ctx, d.precision, d.n, 1), dea, dta, 1, L.M, hs_mask(d), S, s);
+    run_sequence(ctx, select_ops(ctx, d.precision, d.n, 1), dea, dta, 1, L.M, hs_mask(d), mix_of(S), s);
     if (hipMemsetAsync(res, 0, sizeof(unsigned long long), s) != hipSuccess) return device_check(ctx, "reset");
     hipLaunchKernelGGL(k_picard, dim3(blocks), dim3(256), 0, s, rho, (const double*)mu, beta_v, n3, (int)S, drb,
                        lambda, res);
@@ -973,7 +994,7 @@ pnp_status pnp_batch_mu_ex(pnp_ctx ctx, int32_t count, pnp_request* reqs, void* 
     const TableArgs* dta = (const TableArgs*)upload(ctx, g.ta.data(), sizeof(TableArgs) * cnt, s);
     const EvalArgs* dea = (const EvalArgs*)upload(ctx, g.ea.data(), sizeof(EvalArgs) * cnt, s);
     if (!dta || !dea) return device_check(ctx, "argument upload");
-    run_sequence(ctx, select_ops(ctx, g.precision, g.n, cnt), dea, dta, cnt, g.M, g.fmask, g.maxS, s);
+    run_sequence(ctx, select_ops(ctx, g.precision, g.n, cnt), dea, dta, cnt, g.M, g.fmask, g.mix, s);
   }
   pnp_status st = device_check(ctx, "batch launch");
   if (st != PNP_OK) return st;
@@ -1068,7 +1089,7 @@ pnp_status pnp_plan_create(pnp_ctx ctx, int32_t count, pnp_request* reqs, const 
     for (size_t k = 0; k < groups.size(); ++k) {
       const Group& g = groups[k];
       run_sequence(ctx, select_ops(ctx, g.precision, g.n, (int)g.ids.size()), (const EvalArgs*)(blk + ea_off[k]),
-                   (const TableArgs*)(blk + ta_off[k]), (int)g.ids.size(), g.M, g.fmask, g.maxS, cs);
+                   (const TableArgs*)(blk + ta_off[k]), (int)g.ids.size(), g.M, g.fmask, g.mix, cs);
     }
     if (relax)
       for (int r = 0; r < count; ++r) {
@@ -1159,7 +1180,7 @@ pnp_status pnp_autotune(pnp_ctx ctx, int32_t count, pnp_request* reqs, int32_t r
       for (int r = 0; r <= reps && st == PNP_OK; ++r)  // the first round warms up and is not counted
         for (int v = 0; v < 2 && st == PNP_OK; ++v) {
           sel.mask = v ? ~0u : 0u;
-          run_sequence(ctx, sel, dea, dta, cnt, g.M, g.fmask, g.maxS, s);
+          run_sequence(ctx, sel, dea, dta, cnt, g.M, g.fmask, g.mix, s);
           double ms[PNP_NUM_PASSES];
           st = pnp_profile_read(ctx, ms, nullptr, PNP_NUM_PASSES, 1);
           if (r > 0)

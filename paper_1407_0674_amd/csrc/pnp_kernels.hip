@@ -1048,6 +1048,8 @@ __global__ void __launch_bounds__((PX * (N / EX)))
 // stream through two register buffers (the next pencil, and the next pair-
 // table row, are in flight during each transform); the derivative spectra
 // fold into the CH outputs before the density phase starts.
+// Instances with more species than CH belong to the chunked kernel of the
+// same launch list and are skipped here.
 template <typename T, int N, int CH, int EX = Geo<T, N>::EX, int PX = Geo<T, N>::PX>
 __global__ void __launch_bounds__((PX * (N / EX)))
     k_xback(const EvalArgs* __restrict__ args) {
@@ -1057,6 +1059,7 @@ __global__ void __launch_bounds__((PX * (N / EX)))
   __shared__ cx<T> xch[PX * N];
   int tile;
   const EvalArgs& a = args[inst_of(x_tiles<N, PX>(), tile)];
+  if (a.S > CH) return;  // uniform per block
   init_twiddles<T, N>(tw);
   __syncthreads();
   const int p = threadIdx.x % PX, t = threadIdx.x / PX;
@@ -1213,15 +1216,18 @@ __global__ void __launch_bounds__((PX * (N / EX)))
 // P7 for S > 4 species: the same operator with the outputs in chunks of 4
 // (the derivative spectra stay in registers; each chunk re-streams the
 // density pencils).
+// min_s: instances with fewer species run the streamed kernel of the same
+// launch list and are skipped here (1: every instance runs here).
 template <typename T, int N, int CH, int EX = Geo<T, N>::EX, int PX = Geo<T, N>::PX>
 __global__ void __launch_bounds__((PX * (N / EX)))
-    k_xback_chunked(const EvalArgs* __restrict__ args) {
+    k_xback_chunked(const EvalArgs* __restrict__ args, int min_s) {
   static_assert(CH >= 1 && CH <= 4, "output chunk");
   constexpr int TX = N / EX;
   __shared__ cx<T> tw[N];
   __shared__ cx<T> xch[PX * N];
   int tile;
   const EvalArgs& a = args[inst_of(x_tiles<N, PX>(), tile)];
+  if (a.S < min_s) return;  // uniform per block
   init_twiddles<T, N>(tw);
   __syncthreads();
   const int p = threadIdx.x % PX, t = threadIdx.x / PX;

@@ -221,6 +221,21 @@ def random_instance(rng, n_choices, precision: int = MIXED, h: float = 0.05,
     return prob, gaussian_channel(rng, n, h, [s.rho_bulk for s in sp], list(q), 0.5)
 
 
+def many_species(n: int, S: int, seed: int, precision: int = FP64, h: float = 0.05, terms: int = TERMS_ALL):
+    """S species (1..8) of the random-instance recipe with bulk ~ U(0.1, 1.0) M
+    (lower, so that eight species stay well below close packing), 300 K,
+    channel pattern."""
+    rng = np.random.default_rng(seed)
+    d = rng.uniform(0.15, 0.45, size=S)
+    rb = rng.uniform(0.1, 1.0, size=S) * MOLAR_TO_NM3
+    q = rng.choice(np.array([-2.0, -1.0, 1.0, 2.0]), size=S)
+    sp = [Species(float(d[i]), float(q[i]), float(rb[i])) for i in range(S)]
+    eps, rout = uniform_well(sp, 0.3, 0.3)
+    prob = Problem(n=n, h=h, species=sp, T=300.0, terms=terms, sw_eps=eps, sw_rout=rout,
+                   precision=precision, name=f"many-{n}^3-S{S}")
+    return prob, gaussian_channel(rng, n, h, [s.rho_bulk for s in sp], list(q), 0.5)
+
+
 def config4(seed: int = BASE_SEED + 4, count: int = 64, n_choices=(32, 48, 64, 96, 128),
             precision: int = MIXED):
     """64 uneven instances for one batched launch."""
@@ -276,5 +291,5 @@ __all__ = [
     "MOLAR_TO_NM3", "TERM_HS", "TERM_EC", "TERM_SW", "TERM_HS_WB", "TERMS_ALL", "FP64", "MIXED",
     "Species", "Problem", "Request", "uniform_well", "uniform_noise",
     "gaussian_channel", "gaussian_channel_profile", "local_packing_max", "config1", "config2", "config3",
-    "config4", "config5", "channel_problem", "random_instance", "BASE_SEED",
+    "config4", "config5", "channel_problem", "random_instance", "many_species", "BASE_SEED",
 ]
