@@ -808,11 +808,8 @@ pnp_status pnp_cdft_mu_ex(pnp_ctx ctx, const pnp_grid* g, int32_t S, const pnp_s
   if (ws_bytes < L.total) return fail(ctx, PNP_E_NOMEM, "workspace too small: need " + std::to_string(L.total));
   if (hipSetDevice(ctx->device) != hipSuccess) return device_check(ctx, "set device");
   hipStream_t s = (hipStream_t)stream;
-  const Ops* op = ops_for(d.precision, d.n);
   char* w = (char*)ws;
   const double sw_c = p->sw_prefactor;
-  const long n3 = (long)d.n * d.n * d.n;
-
   if (!p->per_term) {
     TableArgs ta;
     fill_table_args(ta, d, sp, g->h, sw_c, d.ec, d.sw, w + L.hs, pairs ? w + L.pair : nullptr, L.M);
