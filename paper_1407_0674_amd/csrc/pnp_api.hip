@@ -1372,7 +1372,8 @@ pnp_status pnp_debug_copy(pnp_ctx ctx, const void* src, void* dst, size_t bytes,
   if (bytes == 0) return PNP_OK;
   if (hipSetDevice(ctx->device) != hipSuccess) return device_check(ctx, "set device");
   const long words = (long)(bytes / 16);
-  const int blocks = (int)std::min<long>((words + 255) / 256, 8192);
+  if ((words + 255) / 256 > 0x7fffffffL) return fail(ctx, PNP_E_ARG, "copy too large");
+  const int blocks = (int)((words + 255) / 256);
   hipLaunchKernelGGL(k_copy, dim3(blocks), dim3(256), 0, (hipStream_t)stream, (const uint4*)src, (uint4*)dst, words);
   return device_check(ctx, "copy launch");
 }
