@@ -102,9 +102,11 @@ constexpr int kBufWord3 = 0x00020000;  // raw (untyped) 32-bit data on gfx9-fami
 // hold has gone by, so its lines are not worth keeping (measured: 5 % less
 // time per evaluation at 256^3).  Smaller grids keep the default policy
 // (measured: non-temporal stores made the batch of 32^3-128^3 instances 8 %
-// slower).  Loads keep the default policy except where measured faster (the
-// density input of the first pass and the derivative pass); gathers of the
-// small tables always stay cached.
+// slower).  Loads keep the default policy except where measured faster: the
+// density input of the first pass, the derivative pass, and the field loads
+// of the back pass (there the pair-table rows then stay cached for the
+// gathers: 428 -> 389 us at 256^3).  Gathers of the small tables always keep
+// the default policy.
 constexpr int kPolicyNT = 2;
 template <int N> constexpr int stream_policy() { return N >= 192 ? kPolicyNT : 0; }
 typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
@@ -1116,7 +1118,7 @@ __global__ void __launch_bounds__((PX * (N / EX)))
     // (i s_x F_bx + [z]) / |j| (see the field-slot layout)
     cx<T> F[6][EX];
 #pragma unroll
-    for (int m = 0; m < EX; ++m) b0[m] = B.template ld<cx<T>>(xa.vo, m * xa.mstride);
+    for (int m = 0; m < EX; ++m) b0[m] = B.template ldnt<cx<T>>(xa.vo, m * xa.mstride);
 #pragma unroll
     for (int q = 0; q < kBackFields; ++q) {
       cx<T>* cur = (q & 1) ? b1 : b0;
@@ -1124,7 +1126,7 @@ __global__ void __launch_bounds__((PX * (N / EX)))
       if (q + 1 < kBackFields) {
         const int f1 = back_field(q + 1);
 #pragma unroll
-        for (int m = 0; m < EX; ++m) nxt[m] = B.template ld<cx<T>>(xa.vo, (uint32_t)f1 * fbytes + m * xa.mstride);
+        for (int m = 0; m < EX; ++m) nxt[m] = B.template ldnt<cx<T>>(xa.vo, (uint32_t)f1 * fbytes + m * xa.mstride);
       }
       fft_pencil<T, N, EX, true>(cur, t, tw, lp);
       const int f = back_field(q);
@@ -1170,7 +1172,7 @@ __global__ void __launch_bounds__((PX * (N / EX)))
   }
   if (pair_on) {  // the density stream starts in b0
 #pragma unroll
-    for (int m = 0; m < EX; ++m) b0[m] = A.template ld<cx<T>>(xa.vo, m * xa.mstride);
+    for (int m = 0; m < EX; ++m) b0[m] = A.template ldnt<cx<T>>(xa.vo, m * xa.mstride);
   }
   if (pair_on && sizeof(T) == 8) {
     // FP64: pair-table rows gathered after each transform (two buffers of
@@ -1182,7 +1184,7 @@ __global__ void __launch_bounds__((PX * (N / EX)))
         cx<T>* nxt = (j & 1) ? b0 : b1;
         if (j + 1 < S) {
 #pragma unroll
-          for (int m = 0; m < EX; ++m) nxt[m] = A.template ld<cx<T>>(xa.vo, (uint32_t)(j + 1) * fbytes + m * xa.mstride);
+          for (int m = 0; m < EX; ++m) nxt[m] = A.template ldnt<cx<T>>(xa.vo, (uint32_t)(j + 1) * fbytes + m * xa.mstride);
         }
         fft_pencil<T, N, EX, true>(cur, t, tw, lp);
 #pragma unroll
@@ -1209,7 +1211,7 @@ __global__ void __launch_bounds__((PX * (N / EX)))
         v4<T>* gn = (j & 1) ? g0 : g1;
         if (j + 1 < S) {
 #pragma unroll
-          for (int m = 0; m < EX; ++m) nxt[m] = A.template ld<cx<T>>(xa.vo, (uint32_t)(j + 1) * fbytes + m * xa.mstride);
+          for (int m = 0; m < EX; ++m) nxt[m] = A.template ldnt<cx<T>>(xa.vo, (uint32_t)(j + 1) * fbytes + m * xa.mstride);
 #pragma unroll
           for (int m = 0; m < EX; ++m)
             gn[m] = pt.template ld<v4<T>>((uint32_t)((mm[m] * S + j + 1) * a.Sp) * (uint32_t)sizeof(T));
@@ -1280,7 +1282,7 @@ __global__ void __launch_bounds__((PX * (N / EX)))
     for (int f = 0; f < 4; ++f) {
       cx<T> v[EX];
 #pragma unroll
-      for (int m = 0; m < EX; ++m) v[m] = B.template ld<cx<T>>(eo[m], (uint32_t)f * fbytes);
+      for (int m = 0; m < EX; ++m) v[m] = B.template ldnt<cx<T>>(eo[m], (uint32_t)f * fbytes);
       fft_pencil<T, N, EX, true>(v, t, tw, lp);
 #pragma unroll
       for (int m = 0; m < EX; ++m) {
@@ -1300,7 +1302,7 @@ __global__ void __launch_bounds__((PX * (N / EX)))
         cx<T> v[EX];
         const int slot = (c == 0 ? kSlotX : kSlotZ) + kVecStride * b;
 #pragma unroll
-        for (int m = 0; m < EX; ++m) v[m] = B.template ld<cx<T>>(eo[m], (uint32_t)slot * fbytes);
+        for (int m = 0; m < EX; ++m) v[m] = B.template ldnt<cx<T>>(eo[m], (uint32_t)slot * fbytes);
         fft_pencil<T, N, EX, true>(v, t, tw, lp);
 #pragma unroll
         for (int m = 0; m < EX; ++m) {
@@ -1324,7 +1326,7 @@ __global__ void __launch_bounds__((PX * (N / EX)))
       for (int j = 0; j < S; ++j) {
         cx<T> v[EX];
 #pragma unroll
-        for (int m = 0; m < EX; ++m) v[m] = A.template ld<cx<T>>(eo[m], (uint32_t)j * fbytes);
+        for (int m = 0; m < EX; ++m) v[m] = A.template ldnt<cx<T>>(eo[m], (uint32_t)j * fbytes);
         fft_pencil<T, N, EX, true>(v, t, tw, lp);
 #pragma unroll
         for (int m = 0; m < EX; ++m) {
