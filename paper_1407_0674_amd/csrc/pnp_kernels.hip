@@ -609,9 +609,6 @@ __global__ void __launch_bounds__((GeoD<T, N, EZD, V>::RDD * GeoD<T, N, EZD, V>:
   int tile;
   const EvalArgs& a = args[inst_of(D::tiles, tile)];
   if (!a.hs_on || (a.hs_wb != 0) != WB) return;  // uniform per block
-  init_twiddles<T, H>(twH);
-  init_twiddles<T, N>(twN);
-  __syncthreads();
   const int t = threadIdx.x % TZ, r = threadIdx.x / TZ;
   const uint32_t row = (uint32_t)(tile * RD + r);
   cx<T>* lrow = xch + r * H;
@@ -620,9 +617,13 @@ __global__ void __launch_bounds__((GeoD<T, N, EZD, V>::RDD * GeoD<T, N, EZD, V>:
   const uint32_t fbytes = __builtin_amdgcn_readfirstlane((uint32_t)(a.fstride * sizeof(cx<T>)));
   cx<T> val[kFields * EZ];
   {
-    // the raw values of field q + 1 are in flight while field q is transformed
+    // the raw values of field q + 1 are in flight while field q is transformed;
+    // those of field 0 while the twiddle tables are built
     cx<T> k0[EZ], m0[EZ], k1[EZ], m1[EZ];
     c2r_load<T, N, TZ, EZ>(k0, m0, t, B, 0, row);
+    init_twiddles<T, H>(twH);
+    init_twiddles<T, N>(twN);
+    __syncthreads();
 #pragma unroll
     for (int q = 0; q < kFields; ++q) {
       cx<T>* kc = (q & 1) ? k1 : k0;
@@ -978,8 +979,6 @@ __global__ void __launch_bounds__((PX * (N / EX)))
   int tile;
   const EvalArgs& a = args[inst_of(x_tiles<N, PX>(), tile)];
   if (!a.hs_on) return;  // uniform per block
-  init_twiddles<T, N>(tw);
-  __syncthreads();
   const int p = threadIdx.x % PX, t = threadIdx.x / PX;
   const XPencil<N, PX> pc(tile, p);
   const LdsPencil<T> lp{xch + p, PX};
@@ -1000,8 +999,11 @@ __global__ void __launch_bounds__((PX * (N / EX)))
   }
   cx<T> acc[6][EX];
   cx<T> b0[EX], b1[EX];
+  // the first species' pencil is in flight while the twiddle table is built
 #pragma unroll
   for (int m = 0; m < EX; ++m) b0[m] = A.template ld<cx<T>>(xa.vo, m * xa.mstride);
+  init_twiddles<T, N>(tw);
+  __syncthreads();
 #pragma unroll
   for (int i = 0; i < kMaxSpecies; ++i) {
     if (i < S) {  // uniform
@@ -1088,8 +1090,6 @@ __global__ void __launch_bounds__((PX * (N / EX)))
   int tile;
   const EvalArgs& a = args[inst_of(x_tiles<N, PX>(), tile)];
   if (a.S > CH) return;  // uniform per block
-  init_twiddles<T, N>(tw);
-  __syncthreads();
   const int p = threadIdx.x % PX, t = threadIdx.x / PX;
   const XPencil<N, PX> pc(tile, p);
   const LdsPencil<T> lp{xch + p, PX};
@@ -1113,12 +1113,20 @@ __global__ void __launch_bounds__((PX * (N / EX)))
   }
   cx<T> out[CH][EX];
   cx<T> b0[EX], b1[EX];
+  // the first pencil of the stream is in flight while the twiddle table is built
+  if (hs_on) {
+#pragma unroll
+    for (int m = 0; m < EX; ++m) b0[m] = B.template ldnt<cx<T>>(xa.vo, m * xa.mstride);
+  } else if (pair_on) {
+#pragma unroll
+    for (int m = 0; m < EX; ++m) b0[m] = A.template ldnt<cx<T>>(xa.vo, m * xa.mstride);
+  }
+  init_twiddles<T, N>(tw);
+  __syncthreads();
   if (hs_on) {
     // F[0..3]: scalar derivative spectra; F[4 + b] = i (khat . F_bv) =
     // (i s_x F_bx + [z]) / |j| (see the field-slot layout)
     cx<T> F[6][EX];
-#pragma unroll
-    for (int m = 0; m < EX; ++m) b0[m] = B.template ldnt<cx<T>>(xa.vo, m * xa.mstride);
 #pragma unroll
     for (int q = 0; q < kBackFields; ++q) {
       cx<T>* cur = (q & 1) ? b1 : b0;
@@ -1170,7 +1178,7 @@ __global__ void __launch_bounds__((PX * (N / EX)))
 #pragma unroll
       for (int m = 0; m < EX; ++m) out[c][m] = mk<T>((T)0, (T)0);
   }
-  if (pair_on) {  // the density stream starts in b0
+  if (pair_on && hs_on) {  // the density stream starts in b0 (already there without HS)
 #pragma unroll
     for (int m = 0; m < EX; ++m) b0[m] = A.template ldnt<cx<T>>(xa.vo, m * xa.mstride);
   }
