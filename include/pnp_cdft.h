@@ -11,8 +11,9 @@
  * spacing h (all outputs dimensionless, in units of k_B T):
  *   - FMT weighted densities n0..n3, n1v, n2v (Sec. 2.3.1, correlations of
  *     rho_i with the weight functions omega_i);
- *   - the ten partial derivatives of the Rosenfeld free-energy density
- *     (Sec. 2.3.1), evaluated pointwise in FP64;
+ *   - the ten partial derivatives of the Rosenfeld free-energy density, or
+ *     of its modified White Bear form (Sec. 2.3.1), evaluated pointwise in
+ *     FP64;
  *   - beta mu_hs_i by back-convolution (Sec. 2.3.1);
  *   - beta mu_el_i, the MSA electrostatic-correlation term (Sec. 2.3.4):
  *     mu_el_bulk_i - sum_j C_ij (*) (rho_j - rho_j^bulk);
@@ -21,7 +22,14 @@
  *   - beta mu_ex = hs + el + sh and the Slotboom factor exp(-beta mu_ex),
  *     the mu_ex part of the transformed diffusion coefficient (Sec. 2.1).
  * The Coulomb term of Sec. 2.3.3 is not part of mu_ex here: in a PNP solve it
- * is the Poisson potential.
+ * is the Poisson potential.  With PNP_FLAG_APERIODIC the grid is instead the
+ * domain of a non-periodic problem (Sec. 3.4: convolutions over the domain
+ * only, through zero extension onto the doubled grid).
+ *
+ * Around the evaluation: batches of independent requests, captured replays
+ * (HIP graphs), resident sessions in a device pool, free energies, the
+ * equilibrium (Picard) solve, the bulk chemical potentials, a tile-shape
+ * autotuner, pass timing and a calibration copy.
  *
  * Discrete operator: each weight / pair kernel is the inverse DFT of its
  * continuous Fourier transform sampled at the grid wave-vectors (exact bulk
@@ -36,7 +44,9 @@
  * allocates, frees or retains caller memory.  The context owns a 4 MiB
  * device ring for per-call argument records (allocated by pnp_create) and a
  * few host records; when the ring wraps (after thousands of calls) the call
- * that wraps it waits for the device to drain.  Scratch space comes in through `workspace`, sized by
+ * that wraps it waits for the device to drain.  A captured plan owns a small
+ * device block for its argument records (allocated by pnp_plan_create, freed
+ * by pnp_plan_destroy).  Scratch space comes in through `workspace`, sized by
  * pnp_workspace_bytes().
  *
  * Errors: every function returns a pnp_status; nothing aborts or throws
