@@ -75,3 +75,34 @@ def test_aperiodic_errors(ev):
     assert st == -1
     # the workspace query knows the mode: larger than the periodic one of the domain
     assert ev.workspace_bytes(prob, False, None, FLAG_APERIODIC) > 8 * ev.workspace_bytes(prob)
+
+
+def test_aperiodic_128_domain_sampled(ev):
+    """The 128^3 domain of the benchmark's electrolyte (packing 0.45) on the
+    doubled 256^3 grid, mixed precision as the aperiodic benchmark times it,
+    against oracle values at 512 points per species (half of them within four
+    points of a face), stored by tests/golden/make_aperiodic_samples.py:
+    within 1e-5 of each term's largest magnitude."""
+    import json
+    import os
+    import torch
+    with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "aperiodic_128_samples.json")) as f:
+        golden = json.load(f)
+    prob, rho = P.config3(n=128)
+    rd = to_dev(rho)
+    mu3, _ = ev.mu_ex(prob, rd, per_term=True, flags=FLAG_APERIODIC)
+    idx = torch.tensor(golden["flat_index"], device=rd.device)
+    for k, term in enumerate(("hs", "el", "sh")):
+        got = mu3[k].reshape(prob.S, -1)[:, idx].cpu().numpy()
+        ref = np.asarray(golden[term])
+        for s in range(prob.S):
+            err = np.max(np.abs(got[s] - ref[s])) / golden["max_abs"][term][s]
+            assert err < 1e-5, (term, s, err)
+    mu, slot = ev.mu_ex(prob, rd, flags=FLAG_APERIODIC)
+    tot = mu.reshape(prob.S, -1)[:, idx].cpu().numpy()
+    ref = sum(np.asarray(golden[t]) for t in ("hs", "el", "sh"))
+    scale = sum(np.asarray(golden["max_abs"][t]) for t in ("hs", "el", "sh"))
+    for s in range(prob.S):
+        assert np.max(np.abs(tot[s] - ref[s])) / scale[s] < 1e-5, s
+    del mu3, mu, slot
+    torch.cuda.empty_cache()
