@@ -17,6 +17,10 @@ rho_i on a periodic n^3 grid of spacing h,
   * the mean-field square-well term (Sec. 2.3.2),
   * beta*mu_ex and the Slotboom factor exp(-beta*mu_ex) (Sec. 2.1).
 
+The delta-shell integrals can also be taken by the product quadrature over
+spheres of Sec. 3.5 (``shell_integrals``), with the smoothed-delta
+alternative beside it for comparison.
+
 An aperiodic mode (``mu_ex_aperiodic``: integrands zero outside the domain,
 convolutions on the doubled grid, Sec. 3.4) sits on top of the periodic
 operator.
@@ -39,6 +43,8 @@ from .mu_ex import mu_ex, weighted_densities, free_energy
 from .relax import relax_densities
 from .equilibrium import picard, bulk_mu_ex
 from .aperiodic import mu_ex_aperiodic, extend, linear_convolution_1d, split_convolution_1d
+from .sphere_quad import (sphere_rule, shell_integrals, shell_weighted_densities,
+                          gaussian_bump_shell, shell_integral_gaussian_delta)
 
 STATUS = {
     "units": "pinned: tests/test_oracle_units.py (Table 1 beta and l_B)",
@@ -51,6 +57,8 @@ STATUS = {
     "equilibrium": "pinned: tests/test_oracle_equilibrium.py (bulk fixed point, dilute Boltzmann limit, self-consistency)",
     "aperiodic": "pinned: tests/test_oracle_aperiodic.py (1D trapezoidal sum, domain sums of the linear terms, "
                  "direct route, mirror covariance)",
+    "sphere_quad": "pinned: tests/test_oracle_sphere_quad.py (constant and affine fields, Gaussian bump closed "
+                   "form at O(h^2), quarter turn, zero extension vs padded periodic grid, uniform-fluid FMT values)",
 }
 
 __all__ = [
@@ -59,5 +67,6 @@ __all__ = [
     "j1_over_x", "Operator", "build_operator", "real_space_kernel", "wavevectors",
     "phi_hs", "dphi_hs", "phi_hs_wb", "dphi_hs_wb", "correlate_direct", "convolve_direct", "mu_ex",
     "weighted_densities", "free_energy", "relax_densities", "picard", "bulk_mu_ex", "mu_ex_aperiodic",
-    "extend", "linear_convolution_1d", "split_convolution_1d", "STATUS",
+    "extend", "linear_convolution_1d", "split_convolution_1d", "sphere_rule", "shell_integrals",
+    "shell_weighted_densities", "gaussian_bump_shell", "shell_integral_gaussian_delta", "STATUS",
 ]
