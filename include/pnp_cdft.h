@@ -230,6 +230,44 @@ pnp_status pnp_weighted_densities(pnp_ctx ctx, const pnp_grid* grid, int32_t S,
                                   const pnp_params* params, double* n_out,
                                   void* workspace, size_t workspace_bytes, void* stream);
 
+/*
+ * Surface integrals over spheres by the product quadrature of Sec. 3.5: the
+ * delta-shell integrals of the FMT weights taken in real space, as an
+ * alternative to the spectral weights of the evaluation above.  For each
+ * field f and grid point r, with the radius R of that field,
+ *   I(r)   = int f(r') delta(|r' - r| - R) dr'
+ *          ~ R^2 sum_i sum_j f(r + R n_ij) sin(phi_j) w_i w~_j,
+ *   I_a(r) ~ the same sum with f(r + R n_ij) n_ij,a,  a = x, y, z,
+ * n_ij = (cos theta_i sin phi_j, sin theta_i sin phi_j, cos phi_j), over
+ * theta_i = 2 pi i / k (weights 2 pi / k) and the k Gauss-Legendre points
+ * phi_j of [0, pi]; f between grid points is the trilinear interpolant of
+ * the grid values.  The paper fixes neither the 1D rules nor the
+ * interpolation; these are the readings taken.  I_a is the correlation with
+ * the vector weight x/|x| delta(|x| - R) (x = r' - r), the convention of
+ * pnp_weighted_densities, so with R_s = d_s / 2:
+ *   n2 = sum_s I_s, n1 = sum_s I_s / (4 pi R_s), n0 = sum_s I_s / (4 pi R_s^2),
+ *   n2v = sum_s I_s,a, n1v = sum_s I_s,a / (4 pi R_s).
+ *   grid       nx, ny, nz >= 1 (any extents, nx ny nz < 2^31), spacing h > 0 [nm]
+ *   F          number of fields, 1..64
+ *   f          device, float64 [F][nx][ny][nz], z fastest; read-only
+ *   radius     host, F radii [nm], 0 < R <= 16 h; the stencil reach
+ *              (about R / h + 1 grid points) must fit the LDS tile: up to 7
+ *              points in PNP_MIXED, 4 in PNP_FP64 (else PNP_E_UNSUPPORTED_SIZE)
+ *   order      k in [1, 64] (k*k nodes per sphere)
+ *   precision  PNP_FP64 (double arithmetic) or PNP_MIXED (float arithmetic,
+ *              float weights; inputs and outputs stay double)
+ *   flags      PNP_FLAG_APERIODIC: f is zero outside the grid (the paper's
+ *              zero extension); otherwise periodic images.  PNP_FLAG_ASYNC:
+ *              do not wait for the kernel.
+ *   out        device, float64 [F][4][nx][ny][nz]: (I, I_x, I_y, I_z) per field
+ * The stencil (at most a few hundred offsets per field) is built on the host
+ * in double and uploaded to the context's ring.  Errors: PNP_E_ARG,
+ * PNP_E_UNSUPPORTED_SIZE, PNP_E_DEVICE.
+ */
+pnp_status pnp_sphere_quadrature(pnp_ctx ctx, const pnp_grid* grid, int32_t F, const double* f,
+                                 const double* radius, int32_t order, int32_t precision,
+                                 uint32_t flags, double* out, void* stream);
+
 /* One request of a batch: an independent evaluation with its own shape. */
 typedef struct {
   pnp_grid grid;

@@ -43,7 +43,7 @@ from .mu_ex import mu_ex, weighted_densities, free_energy
 from .relax import relax_densities
 from .equilibrium import picard, bulk_mu_ex
 from .aperiodic import mu_ex_aperiodic, extend, linear_convolution_1d, split_convolution_1d
-from .sphere_quad import (sphere_rule, shell_integrals, shell_weighted_densities,
+from .sphere_quad import (sphere_rule, shell_integrals, shell_integrals_at, shell_weighted_densities,
                           gaussian_bump_shell, shell_integral_gaussian_delta)
 
 STATUS = {
@@ -67,6 +67,6 @@ __all__ = [
     "j1_over_x", "Operator", "build_operator", "real_space_kernel", "wavevectors",
     "phi_hs", "dphi_hs", "phi_hs_wb", "dphi_hs_wb", "correlate_direct", "convolve_direct", "mu_ex",
     "weighted_densities", "free_energy", "relax_densities", "picard", "bulk_mu_ex", "mu_ex_aperiodic",
-    "extend", "linear_convolution_1d", "split_convolution_1d", "sphere_rule", "shell_integrals",
+    "extend", "linear_convolution_1d", "split_convolution_1d", "sphere_rule", "shell_integrals", "shell_integrals_at",
     "shell_weighted_densities", "gaussian_bump_shell", "shell_integral_gaussian_delta", "STATUS",
 ]

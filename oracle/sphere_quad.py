@@ -116,6 +116,50 @@ def shell_integrals(f, R, h, k, aperiodic=False):
     return scalar, vector
 
 
+def shell_integrals_at(f, R, h, k, points, aperiodic=False):
+    """The same sums as `shell_integrals`, at chosen grid points only.
+
+    points: [P, 3] integer grid indices.  Each node position r + R n / h is
+    interpolated on its own (floor, fractions, eight corners), for sampled
+    checks on grids too large for the whole-grid form.
+    Returns (I [P], Iv [3, P]).
+    """
+    f = np.asarray(f, dtype=np.float64)
+    pts = np.asarray(points, dtype=np.int64)
+    shape = np.array(f.shape)
+    theta, w_theta, phi, w_phi = sphere_rule(k)
+    scalar = np.zeros(len(pts))
+    vector = np.zeros((3, len(pts)))
+    for i in range(k):
+        for j in range(k):
+            n = np.array([math.cos(theta[i]) * math.sin(phi[j]),
+                          math.sin(theta[i]) * math.sin(phi[j]),
+                          math.cos(phi[j])])
+            weight = R * R * math.sin(phi[j]) * w_theta[i] * w_phi[j]
+            pos = pts + (R / h) * n
+            base = np.floor(pos).astype(np.int64)
+            t = pos - base
+            g = np.zeros(len(pts))
+            for cx in (0, 1):
+                for cy in (0, 1):
+                    for cz in (0, 1):
+                        c = np.array([cx, cy, cz])
+                        wgt = np.prod(np.where(c == 1, t, 1.0 - t), axis=1)
+                        idx = base + c
+                        if aperiodic:
+                            inside = np.all((idx >= 0) & (idx < shape), axis=1)
+                            idx = np.clip(idx, 0, shape - 1)
+                            val = np.where(inside, f[idx[:, 0], idx[:, 1], idx[:, 2]], 0.0)
+                        else:
+                            idx = np.mod(idx, shape)
+                            val = f[idx[:, 0], idx[:, 1], idx[:, 2]]
+                        g += wgt * val
+            scalar += weight * g
+            for a in range(3):
+                vector[a] += (weight * n[a]) * g
+    return scalar, vector
+
+
 def shell_weighted_densities(rho, radii, h, k, aperiodic=False):
     """n0, n1, n2, n1v, n2v of Sec. 2.3.1 from the sphere quadrature (n3 is a volume integral, not here).
 

@@ -30,7 +30,7 @@ EXPORTED = [
     "pnp_profile_select", "pnp_profile_read", "pnp_free_energy", "pnp_equilibrium", "pnp_bulk_mu_ex", "pnp_session_bytes", "pnp_pool_create", "pnp_pool_destroy",
     "pnp_pool_usage", "pnp_session_open", "pnp_session_step", "pnp_session_view", "pnp_session_close",
     "pnp_plan_create", "pnp_plan_launch", "pnp_plan_status", "pnp_plan_destroy", "pnp_pool_graphs",
-    "pnp_autotune", "pnp_tune_export", "pnp_tune_import",
+    "pnp_autotune", "pnp_tune_export", "pnp_tune_import", "pnp_sphere_quadrature",
 ]
 
 PASS_NAMES = ["tables", "z_fwd_rho", "y_fwd_rho", "x_fwd_weights", "y_inv_n", "z_deriv",
@@ -106,6 +106,9 @@ def load_library():
                                            ctypes.POINTER(SpeciesC), P, ctypes.POINTER(ParamsC), P,
                                            P, ctypes.c_size_t, P]
     lib.pnp_batch_mu_ex.argtypes = [P, ctypes.c_int32, ctypes.POINTER(RequestC), P]
+    lib.pnp_sphere_quadrature.argtypes = [P, ctypes.POINTER(Grid), ctypes.c_int32, P,
+                                          ctypes.POINTER(ctypes.c_double), ctypes.c_int32, ctypes.c_int32,
+                                          ctypes.c_uint32, P, P]
     lib.pnp_equilibrium.argtypes = [P, ctypes.POINTER(Grid), ctypes.c_int32, ctypes.POINTER(SpeciesC),
                                     ctypes.c_double, ctypes.POINTER(ParamsC), P, P, P, ctypes.c_double,
                                     ctypes.c_double, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
@@ -314,6 +317,28 @@ class Evaluator:
             self.ctx, ctypes.byref(m.grid), m.S, m.species, self._dev(rho, "rho"),
             ctypes.byref(m.params), self._dev(out, "n_out"), ctypes.c_void_p(ws.data_ptr()),
             ctypes.c_size_t(ws.numel()), self._stream())
+        self._check(st)
+        return out
+
+    def sphere_quadrature(self, f, radius, h, order=8, precision=MIXED, flags=0, out=None):
+        """Sphere integrals (I, I_x, I_y, I_z) of each field by the product rule of
+        Sec. 3.5; f is [F, nx, ny, nz] float64 on the device, radius F values [nm].
+        Returns out [F, 4, nx, ny, nz]."""
+        torch = _torch()
+        if f.dim() != 4:
+            raise PnpError(-1, f"f has shape {tuple(f.shape)}, expected [F, nx, ny, nz]")
+        F, nx, ny, nz = (int(v) for v in f.shape)
+        radii = [float(r) for r in radius]
+        if len(radii) != F:
+            raise PnpError(-1, f"{len(radii)} radii for {F} fields")
+        if out is None:
+            out = torch.empty((F, 4, nx, ny, nz), dtype=torch.float64, device=f.device)
+        elif tuple(out.shape) != (F, 4, nx, ny, nz):
+            raise PnpError(-1, f"out has shape {tuple(out.shape)}")
+        g = Grid(nx, ny, nz, float(h))
+        r = (ctypes.c_double * F)(*radii)
+        st = self.lib.pnp_sphere_quadrature(self.ctx, ctypes.byref(g), F, self._dev(f, "f"), r, int(order),
+                                            int(precision), int(flags), self._dev(out, "out"), self._stream())
         self._check(st)
         return out
 

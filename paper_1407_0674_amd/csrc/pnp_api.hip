@@ -17,6 +17,7 @@
 
 #include "pnp_cdft.h"
 #include "pnp_kernels.hip"
+#include "sphere_quad.hip"
 
 using namespace pnp;
 
@@ -976,6 +977,65 @@ pnp_status pnp_weighted_densities(pnp_ctx ctx, const pnp_grid* g, int32_t S, con
   if (st != PNP_OK) return st;
   if (p->flags & PNP_FLAG_ASYNC) return PNP_OK;
   return read_status(ctx, w + L.status, s);
+}
+
+pnp_status pnp_sphere_quadrature(pnp_ctx ctx, const pnp_grid* g, int32_t F, const double* f,
+                                 const double* radius, int32_t order, int32_t precision,
+                                 uint32_t flags, double* out, void* stream) {
+  if (!ctx) return PNP_E_ARG;
+  if (!g || !f || !radius || !out) return fail(ctx, PNP_E_ARG, "null pointer");
+  if (g->nx < 1 || g->ny < 1 || g->nz < 1) return fail(ctx, PNP_E_ARG, "grid extents must be >= 1");
+  const size_t N = (size_t)g->nx * g->ny * g->nz;
+  if (N > (size_t)INT32_MAX) return fail(ctx, PNP_E_UNSUPPORTED_SIZE, "grid has more than 2^31 - 1 points");
+  if (!(g->h > 0.0) || !std::isfinite(g->h)) return fail(ctx, PNP_E_ARG, "grid spacing must be positive");
+  if (F < 1 || F > kQuadMaxFields) return fail(ctx, PNP_E_ARG, "field count must be in [1, 64]");
+  if (order < 1 || order > 64) return fail(ctx, PNP_E_ARG, "order must be in [1, 64]");
+  if (precision != PNP_FP64 && precision != PNP_MIXED) return fail(ctx, PNP_E_ARG, "bad precision");
+  if (flags & ~(uint32_t)(PNP_FLAG_APERIODIC | PNP_FLAG_ASYNC)) return fail(ctx, PNP_E_ARG, "unsupported flag");
+  for (int i = 0; i < F; ++i)
+    if (!(radius[i] > 0.0) || !std::isfinite(radius[i]) || radius[i] / g->h > 16.0)
+      return fail(ctx, PNP_E_ARG, "field " + std::to_string(i) + ": radius must be in (0, 16 h]");
+  std::vector<QuadStencil> st;
+  int H = 0;
+  for (int i = 0; i < F; ++i) {
+    st.push_back(build_quad_stencil(radius[i] / g->h, radius[i], order));
+    H = std::max(H, st.back().reach);
+  }
+  const size_t elem = precision == PNP_FP64 ? sizeof(double) : sizeof(float);
+  const int tx = quad_tx(H, elem);
+  if (tx == 0)
+    return fail(ctx, PNP_E_UNSUPPORTED_SIZE, "sphere reach " + std::to_string(H) +
+                                                 " grid points does not fit the LDS tile (R / h too large)");
+  QuadArgs a;
+  a.f = f;
+  a.out = out;
+  a.nx = g->nx;
+  a.ny = g->ny;
+  a.nz = g->nz;
+  a.H = H;
+  a.lx = tx + 2 * H;
+  a.ly = kQuadTY + 2 * H;
+  a.lz = kQuadTZ + 2 * H;
+  a.tiles_y = (g->ny + kQuadTY - 1) / kQuadTY;
+  a.tiles_z = (g->nz + kQuadTZ - 1) / kQuadTZ;
+  a.aperiodic = (flags & PNP_FLAG_APERIODIC) ? 1 : 0;
+  size_t entries_at = 0;
+  std::vector<unsigned char> buf = precision == PNP_FP64 ? pack_quad<double>(st, a.ly, a.lz, entries_at)
+                                                         : pack_quad<float>(st, a.ly, a.lz, entries_at);
+  if (buf.size() > ctx->arena_bytes / 2)
+    return fail(ctx, PNP_E_UNSUPPORTED_SIZE, "stencils too large for one call: pass fewer fields");
+  if (hipSetDevice(ctx->device) != hipSuccess) return device_check(ctx, "set device");
+  hipStream_t s = (hipStream_t)stream;
+  const char* dev = (const char*)upload(ctx, buf.data(), buf.size(), s);
+  if (!dev) return device_check(ctx, "stencil upload");
+  a.begin = (const int32_t*)dev;
+  a.entries = dev + entries_at;
+  const hipError_t e = precision == PNP_FP64 ? launch_sphere_quad<double>(a, tx, F, s)
+                                             : launch_sphere_quad<float>(a, tx, F, s);
+  if (e != hipSuccess) return fail(ctx, PNP_E_DEVICE, std::string("sphere quadrature launch: ") + hipGetErrorString(e));
+  if (flags & PNP_FLAG_ASYNC) return PNP_OK;
+  if (hipStreamSynchronize(s) != hipSuccess) return device_check(ctx, "sphere quadrature");
+  return PNP_OK;
 }
 
 pnp_status pnp_batch_mu_ex(pnp_ctx ctx, int32_t count, pnp_request* reqs, void* stream) {

@@ -139,3 +139,15 @@ def test_gaussian_delta_constant_field():
     # int_R^3 delta_alpha(|x| - R) dx = 4 pi (R^2 + alpha^2 / 2), less a tail of order erfc(R / alpha)
     exact = 4.0 * math.pi * (R * R + 0.5 * alpha * alpha) * c
     assert np.max(np.abs(I - exact)) < 1e-4 * exact
+
+
+@pytest.mark.parametrize("aperiodic", [False, True])
+def test_pointwise_form_matches_whole_grid(aperiodic):
+    rng = np.random.default_rng(7)
+    shape, h, R = (6, 9, 5), 0.1, 0.33
+    f = rng.random(shape)
+    I, Iv = Q.shell_integrals(f, R, h, 6, aperiodic=aperiodic)
+    pts = np.stack(np.meshgrid(*[np.arange(m) for m in shape], indexing="ij"), axis=-1).reshape(-1, 3)
+    Ip, Ivp = Q.shell_integrals_at(f, R, h, 6, pts, aperiodic=aperiodic)
+    assert np.max(np.abs(Ip - I.reshape(-1))) < 1e-13
+    assert np.max(np.abs(Ivp - Iv.reshape(3, -1))) < 1e-13
