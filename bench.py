@@ -22,7 +22,9 @@ step) and cfg5 replays a Poisson request trace against resident sessions;
 each prints its own JSON line.
 """
 import argparse
+import itertools
 import json
+import math
 import os
 import sys
 import time
@@ -313,6 +315,119 @@ def bench_aperiodic(ev, steps, warmup):
     }
 
 
+def sphere_stencil_size(r, k):
+    """Integer offsets of the merged stencil of one sphere (radius r in grid
+    units, k-by-k rule): the distinct trilinear corners with nonzero weight
+    over all nodes.  Used only to count the kernel's flops."""
+    import numpy as np
+    x, _ = np.polynomial.legendre.leggauss(k)
+    seen = set()
+    for i in range(k):
+        th = 2.0 * math.pi * i / k
+        for j in range(k):
+            ph = 0.5 * math.pi * (x[j] + 1.0)
+            p = r * np.array([math.cos(th) * math.sin(ph), math.sin(th) * math.sin(ph), math.cos(ph)])
+            b = np.floor(p)
+            t = p - b
+            for c in itertools.product((0, 1), repeat=3):
+                w = np.prod([t[a] if c[a] else 1.0 - t[a] for a in range(3)])
+                if w != 0.0:
+                    seen.add(tuple(int(v) for v in b + np.array(c)))
+    return len(seen)
+
+
+def bench_sphere(ev, steps, warmup, no_cpu):
+    """Sec. 3.5 sphere quadrature (pnp_sphere_quadrature) on the benchmark's
+    256^3 densities with the three species' radii d/2 (1.5, 3 and 4 grid
+    spacings), order 8 (64 nodes per sphere), mixed and FP64.  One step = one
+    call for the three fields (scalar and vector integrals).  The kernel is
+    bound by its FMAs (four per stencil offset per output, one LDS read each):
+    roofline against the vector ALU peak.  Also: the oracle's throughput on a
+    64^3 sample, and the accuracy of the spectral delta-shell weights and of
+    the quadrature (orders 4, 8, 16) on a Gaussian bump against its exact
+    sphere integrals, both measured here on the GPU."""
+    import numpy as np
+    import torch
+    import pnp_inputs as P
+    from paper_1407_0674_amd import FLAG_ASYNC, FP64, MIXED
+    prob, rho = P.config3(n=256)
+    radii = [0.5 * sp.d for sp in prob.species]
+    k = 8
+    rd = torch.from_numpy(rho).to("cuda:0").contiguous()
+    out = torch.empty((prob.S, 4) + rho.shape[1:], dtype=torch.float64, device="cuda:0")
+    n3 = prob.n ** 3
+    entries = [sphere_stencil_size(R / prob.h, k) for R in radii]
+    flops = 8.0 * n3 * sum(entries)
+    hbm = n3 * prob.S * (8 + 4 * 8)
+    res = {}
+    for name, prec in (("mixed", MIXED), ("fp64", FP64)):
+        for _ in range(warmup):
+            ev.sphere_quadrature(rd, radii, prob.h, k, precision=prec, out=out)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            ev.sphere_quadrature(rd, radii, prob.h, k, precision=prec, flags=FLAG_ASYNC, out=out)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        res[name] = {"ms": ms, "tflops": flops / (ms / 1e3) / 1e12, "hbm_GBps": hbm / (ms / 1e3) / 1e9}
+    ev.sphere_quadrature(rd, radii, prob.h, k, precision=MIXED, out=out)   # waits: errors surface here
+    del out, rd
+    torch.cuda.empty_cache()
+
+    # accuracy on a Gaussian bump (width 0.3 nm, sphere radius 0.25 nm) at 64^3
+    import oracle
+    from oracle.sphere_quad import gaussian_bump_shell
+    n, L, s_w, R = 64, 4.8, 0.3, 0.25
+    h = L / n
+    xg = h * np.arange(n)
+    c = np.array([L / 2, L / 2 + 0.5 * h, L / 2 - 0.3 * h])
+    X, Y, Z = np.meshgrid(xg, xg, xg, indexing="ij")
+    d = np.sqrt((X - c[0]) ** 2 + (Y - c[1]) ** 2 + (Z - c[2]) ** 2)
+    f = np.exp(-d * d / (2 * s_w * s_w))
+    I_ex, _ = gaussian_bump_shell(d, R, s_w)
+    scale = float(np.max(I_ex))
+    bprob = P.Problem(n=n, h=h, species=[P.Species(d=2 * R, q=0.0, rho_bulk=1.0, mu_el_bulk=0.0)], T=300.0,
+                      terms=1, eps_r=16.6, sw_eps=None, sw_rout=None, sw_gamma=1.2, sw_prefactor=0.5,
+                      precision=FP64, name="bump")
+    fd = torch.from_numpy(f[None].copy()).to("cuda:0")
+    acc = {"spectral_weights": float(np.max(np.abs(ev.weighted_densities(bprob, fd, precision=FP64)[2].cpu().numpy()
+                                                   - I_ex)) / scale)}
+    for kk in (4, 8, 16):
+        got = ev.sphere_quadrature(fd, [R], h, kk, precision=FP64)[0, 0].cpu().numpy()
+        acc[f"quadrature_k{kk}"] = float(np.max(np.abs(got - I_ex)) / scale)
+
+    cpu = None
+    if not no_cpu:
+        from threadpoolctl import threadpool_limits
+        sub = rho[:, :64, :64, :64].copy()
+        with threadpool_limits(limits=1):
+            t0 = time.perf_counter()
+            for i, R_i in enumerate(radii):
+                oracle.shell_integrals(sub[i], R_i, prob.h, k)
+            dt = time.perf_counter() - t0
+        cpu = {"value": 64 ** 3 * prob.S / dt, "unit": "grid-pt*species/s", "cores": 1, "kind": "oracle",
+               "sample": f"the oracle's whole-grid quadrature (node by node, numpy) of the three fields on a "
+                         f"64^3 corner of the same densities, order 8, FP64, one host thread, {dt:.2f} s"}
+    ms = res["mixed"]["ms"]
+    return {
+        "metric": "sphere quadrature: grid-pts*species/s", "value": n3 * prob.S / (ms / 1e3),
+        "unit": "grid-pt*species/s", "n_gpus": 1, "steps": steps, "warmup": warmup, "ms_per_step": ms,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic (seeded)",
+        "config": {"workload": "sphere quadrature (Sec. 3.5) of the channel electrolyte's 256^3 densities, S=3, "
+                               "R = 1.5, 3, 4 h, order 8 (64 nodes), scalar + vector integrals, mixed"},
+        "stencil_offsets": entries,
+        "roofline": {"bound": "alu", "achieved": res["mixed"]["tflops"], "peak": 157.3, "unit": "TFLOP/s",
+                     "frac": res["mixed"]["tflops"] / 157.3, "traffic": None},
+        "fp64": dict(res["fp64"], frac_of_78_6=res["fp64"]["tflops"] / 78.6),
+        "hbm_GBps_effective": res["mixed"]["hbm_GBps"],
+        "accuracy_vs_exact_gaussian_bump_64": acc,
+        "cpu_baseline": cpu,
+    }
+
+
 def serve_trace(ev, reqs, precision, budget, max_active, work_cap=None, graphs=0):
     """Replay a request trace against a session pool: requests are admitted in
     arrival order when their session fits the budget (at most max_active at a
@@ -485,6 +600,10 @@ def main():
         return
     if args.workload == "aperiodic":
         print(json.dumps(bench_aperiodic(ev, args.steps, args.warmup)), flush=True)
+        ev.close()
+        return
+    if args.workload == "sphere":
+        print(json.dumps(bench_sphere(ev, args.steps, args.warmup, args.no_cpu)), flush=True)
         ev.close()
         return
     prob, rho, desc = workload(args.workload)

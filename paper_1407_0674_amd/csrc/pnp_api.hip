@@ -1001,11 +1001,12 @@ pnp_status pnp_sphere_quadrature(pnp_ctx ctx, const pnp_grid* g, int32_t F, cons
     st.push_back(build_quad_stencil(radius[i] / g->h, radius[i], order));
     H = std::max(H, st.back().reach);
   }
-  const size_t elem = precision == PNP_FP64 ? sizeof(double) : sizeof(float);
-  const int tx = quad_tx(H, elem);
-  if (tx == 0)
+  H = std::max(H, 1);
+  const int max_reach = precision == PNP_FP64 ? quad_max_reach<double>() : quad_max_reach<float>();
+  if (H > max_reach)
     return fail(ctx, PNP_E_UNSUPPORTED_SIZE, "sphere reach " + std::to_string(H) +
                                                  " grid points does not fit the LDS tile (R / h too large)");
+  const int tx = quad_tx(H, precision == PNP_FP64 ? sizeof(double) : sizeof(float));
   QuadArgs a;
   a.f = f;
   a.out = out;
@@ -1030,8 +1031,8 @@ pnp_status pnp_sphere_quadrature(pnp_ctx ctx, const pnp_grid* g, int32_t F, cons
   if (!dev) return device_check(ctx, "stencil upload");
   a.begin = (const int32_t*)dev;
   a.entries = dev + entries_at;
-  const hipError_t e = precision == PNP_FP64 ? launch_sphere_quad<double>(a, tx, F, s)
-                                             : launch_sphere_quad<float>(a, tx, F, s);
+  const hipError_t e = precision == PNP_FP64 ? launch_sphere_quad<double>(a, F, s)
+                                             : launch_sphere_quad<float>(a, F, s);
   if (e != hipSuccess) return fail(ctx, PNP_E_DEVICE, std::string("sphere quadrature launch: ") + hipGetErrorString(e));
   if (flags & PNP_FLAG_ASYNC) return PNP_OK;
   if (hipStreamSynchronize(s) != hipSuccess) return device_check(ctx, "sphere quadrature");

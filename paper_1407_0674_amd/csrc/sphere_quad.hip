@@ -36,20 +36,23 @@ constexpr int kQuadThreads = kQuadTY * kQuadTZ;
 constexpr int kQuadMaxFields = 64;
 constexpr size_t kQuadMaxLds = 65536;
 
-// One integer offset of the merged stencil: its position in the LDS tile
-// relative to the output point and the weights of the scalar and the three
+// One record of the merged stencil: an integer offset (its position in the
+// LDS tile relative to the output point) and the weights of the scalar and
+// the three vector integrals there.  A paired record also names the mirror
+// offset, whose weights are the same for the scalar and opposite for the
 // vector integrals.
 template <typename T>
 struct QuadEntry {
   int32_t lds;
-  int32_t pad;
+  int32_t lds_mirror;  // paired records only
   T c[4];
 };
 
 struct QuadArgs {
   const double* f;        // [F][N]
   double* out;            // [F][4][N]
-  const int32_t* begin;   // [F + 1] entry ranges per field, followed by the entries
+  const int32_t* begin;   // [2F + 1]: field f's pairs are [begin[2f], begin[2f+1]), its singles
+                          // [begin[2f+1], begin[2f+2])
   const void* entries;
   int32_t nx, ny, nz;
   int32_t H;              // stencil reach (max |offset| over all fields and axes)
@@ -63,10 +66,25 @@ __device__ __forceinline__ int quad_wrap(int i, int n) {
   return r < 0 ? r + n : r;
 }
 
-template <typename T, int TX>
+// Outputs per thread along x for a stencil reach H: the largest of 8, 4, 2, 1
+// whose tile fits the LDS budget; 0 if none does.
+constexpr int quad_tx(int H, size_t elem) {
+  for (int tx = 8; tx >= 1; tx /= 2) {
+    const size_t bytes = (size_t)(tx + 2 * H) * (kQuadTY + 2 * H) * (kQuadTZ + 2 * H) * elem;
+    if (bytes <= kQuadMaxLds) return tx;
+  }
+  return 0;
+}
+
+// H (the stencil reach) is a template parameter so that the tile pitches are
+// constants: the TX reads of one stencil offset then share one address and
+// differ by immediate offsets.
+template <typename T, int H>
 __global__ __launch_bounds__(kQuadThreads) void k_sphere_quad(QuadArgs a) {
-  extern __shared__ unsigned char quad_smem[];
-  T* tile = reinterpret_cast<T*>(quad_smem);
+  constexpr int TX = quad_tx(H, sizeof(T));
+  constexpr int LY = kQuadTY + 2 * H, LZ = kQuadTZ + 2 * H, LX = TX + 2 * H;
+  constexpr int PLANE = LY * LZ;
+  __shared__ T tile[LX * PLANE];
   const int field = blockIdx.y;
   int t = blockIdx.x;
   const int tz = t % a.tiles_z;
@@ -79,14 +97,12 @@ __global__ __launch_bounds__(kQuadThreads) void k_sphere_quad(QuadArgs a) {
 
   // tile element (i, j, l) holds f at grid point (x0 - H + i, y0 - H + j, z0 - H + l):
   // its periodic image, or zero outside the grid in the aperiodic mode
-  const int plane = a.ly * a.lz;
-  const int total = a.lx * plane;
-  for (int e = threadIdx.x; e < total; e += kQuadThreads) {
-    const int i = e / plane;
-    const int rem = e - i * plane;
-    const int j = rem / a.lz;
-    const int l = rem - j * a.lz;
-    int gx = x0 - a.H + i, gy = y0 - a.H + j, gz = z0 - a.H + l;
+  for (int e = threadIdx.x; e < LX * PLANE; e += kQuadThreads) {
+    const int i = e / PLANE;
+    const int rem = e - i * PLANE;
+    const int j = rem / LZ;
+    const int l = rem - j * LZ;
+    int gx = x0 - H + i, gy = y0 - H + j, gz = z0 - H + l;
     T v = T(0);
     if (a.aperiodic) {
       if (gx >= 0 && gx < a.nx && gy >= 0 && gy < a.ny && gz >= 0 && gz < a.nz)
@@ -102,7 +118,7 @@ __global__ __launch_bounds__(kQuadThreads) void k_sphere_quad(QuadArgs a) {
   __syncthreads();
 
   const int yl = threadIdx.x / kQuadTZ, zl = threadIdx.x % kQuadTZ;
-  const T* col = tile + (a.H * a.ly + (a.H + yl)) * a.lz + (a.H + zl);
+  const T* col = tile + (H * LY + (H + yl)) * LZ + (H + zl);
   T acc[TX][4];
 #pragma unroll
   for (int x = 0; x < TX; ++x)
@@ -110,14 +126,30 @@ __global__ __launch_bounds__(kQuadThreads) void k_sphere_quad(QuadArgs a) {
     for (int c = 0; c < 4; ++c) acc[x][c] = T(0);
 
   const QuadEntry<T>* E = reinterpret_cast<const QuadEntry<T>*>(a.entries);
-  const int e0 = a.begin[field], e1 = a.begin[field + 1];
+  const int e0 = a.begin[2 * field], e1 = a.begin[2 * field + 1], e2 = a.begin[2 * field + 2];
+  // mirror pairs d, -d: the scalar weight multiplies the sum of the two
+  // values and the vector weights their difference
+#pragma unroll 2
   for (int e = e0; e < e1; ++e) {
-    const int off = E[e].lds;
     const T c0 = E[e].c[0], c1 = E[e].c[1], c2 = E[e].c[2], c3 = E[e].c[3];
-    const T* p = col + off;
+    const T* p = col + E[e].lds;
+    const T* m = col + E[e].lds_mirror;
 #pragma unroll
     for (int x = 0; x < TX; ++x) {
-      const T v = p[x * plane];
+      const T vp = p[x * PLANE], vm = m[x * PLANE];
+      const T sum = vp + vm, dif = vp - vm;
+      acc[x][0] += c0 * sum;
+      acc[x][1] += c1 * dif;
+      acc[x][2] += c2 * dif;
+      acc[x][3] += c3 * dif;
+    }
+  }
+  for (int e = e1; e < e2; ++e) {
+    const T c0 = E[e].c[0], c1 = E[e].c[1], c2 = E[e].c[2], c3 = E[e].c[3];
+    const T* p = col + E[e].lds;
+#pragma unroll
+    for (int x = 0; x < TX; ++x) {
+      const T v = p[x * PLANE];
       acc[x][0] += c0 * v;
       acc[x][1] += c1 * v;
       acc[x][2] += c2 * v;
@@ -176,8 +208,10 @@ inline void gauss_legendre(int k, std::vector<double>& x, std::vector<double>& w
 }
 
 struct QuadStencil {
+  // pairs: offset (dx, dy, dz) and its mirror; singles: offset alone
   std::vector<int32_t> dx, dy, dz;
-  std::vector<double> c;  // 4 per entry
+  std::vector<double> c;  // 4 per record
+  std::vector<char> paired;
   int reach = 0;          // max |offset|
 };
 
@@ -217,38 +251,63 @@ inline QuadStencil build_quad_stencil(double r, double R, int k) {
           }
     }
   }
+  // A rule with even k holds every node together with its antipode, so the
+  // merged weights are even in the offset for the scalar integral and odd for
+  // the vector ones (in exact arithmetic; the node coordinates differ in the
+  // last bits).  Offsets whose mirror agrees to 1e-14 of the largest weight
+  // become one record with the mean weights; the rest stay single.
+  const size_t cells = (size_t)side * side * side;
+  double cmax = 0.0;
+  for (size_t cell = 0; cell < cells; ++cell)
+    if (hit[cell])
+      for (int q = 0; q < 4; ++q) cmax = std::max(cmax, std::fabs(acc[cell * 4 + q]));
+  const double tol = 1e-14 * cmax;
   QuadStencil s;
-  for (int ox = 0; ox < side; ++ox)
-    for (int oy = 0; oy < side; ++oy)
-      for (int oz = 0; oz < side; ++oz) {
-        const size_t cell = ((size_t)ox * side + oy) * side + oz;
-        if (!hit[cell]) continue;
-        s.dx.push_back(ox - Hc);
-        s.dy.push_back(oy - Hc);
-        s.dz.push_back(oz - Hc);
-        for (int q = 0; q < 4; ++q) s.c.push_back(acc[cell * 4 + q]);
-        const int m = std::max(std::abs(ox - Hc), std::max(std::abs(oy - Hc), std::abs(oz - Hc)));
-        s.reach = std::max(s.reach, m);
-      }
+  std::vector<size_t> singles;
+  auto push = [&](size_t cell, const double* c, bool paired) {
+    const int ox = (int)(cell / ((size_t)side * side)), oy = (int)(cell / side % side), oz = (int)(cell % side);
+    s.dx.push_back(ox - Hc);
+    s.dy.push_back(oy - Hc);
+    s.dz.push_back(oz - Hc);
+    for (int q = 0; q < 4; ++q) s.c.push_back(c[q]);
+    s.paired.push_back(paired ? 1 : 0);
+    const int m = std::max(std::abs(ox - Hc), std::max(std::abs(oy - Hc), std::abs(oz - Hc)));
+    s.reach = std::max(s.reach, m);
+  };
+  for (size_t cell = 0; cell < cells; ++cell) {
+    if (!hit[cell]) continue;
+    const size_t mirror = cells - 1 - cell;  // offset -d
+    if (mirror == cell || !hit[mirror]) {
+      singles.push_back(cell);
+      continue;
+    }
+    if (mirror < cell) continue;  // handled with its partner
+    const double* a = &acc[cell * 4];
+    const double* b = &acc[mirror * 4];
+    bool even = std::fabs(a[0] - b[0]) <= tol;
+    for (int q = 1; q < 4; ++q) even = even && std::fabs(a[q] + b[q]) <= tol;
+    if (!even) {
+      singles.push_back(cell);
+      singles.push_back(mirror);
+      continue;
+    }
+    const double mean[4] = {0.5 * (a[0] + b[0]), 0.5 * (a[1] - b[1]), 0.5 * (a[2] - b[2]), 0.5 * (a[3] - b[3])};
+    push(cell, mean, true);
+    const int m = std::max(std::abs((int)(mirror / ((size_t)side * side)) - Hc),
+                           std::max(std::abs((int)(mirror / side % side) - Hc), std::abs((int)(mirror % side) - Hc)));
+    s.reach = std::max(s.reach, m);
+  }
+  for (size_t cell : singles) push(cell, &acc[cell * 4], false);
   return s;
 }
 
-// Outputs per thread along x for a stencil reach H: the largest of 8, 4, 2, 1
-// whose tile fits the LDS budget; 0 if none does.
-inline int quad_tx(int H, size_t elem) {
-  for (int tx = 8; tx >= 1; tx /= 2) {
-    const size_t bytes = (size_t)(tx + 2 * H) * (kQuadTY + 2 * H) * (kQuadTZ + 2 * H) * elem;
-    if (bytes <= kQuadMaxLds) return tx;
-  }
-  return 0;
-}
-
-// The packed upload: begin[F + 1] (padded to 16 bytes), then the entries.
+// The packed upload: begin[2F + 1] (padded to 16 bytes), then per field its
+// paired records followed by its single ones.
 template <typename T>
 inline std::vector<unsigned char> pack_quad(const std::vector<QuadStencil>& st, int ly, int lz,
                                             size_t& entries_at) {
   const int F = (int)st.size();
-  size_t head = ((size_t)(F + 1) * sizeof(int32_t) + 15) / 16 * 16;
+  size_t head = ((size_t)(2 * F + 1) * sizeof(int32_t) + 15) / 16 * 16;
   size_t count = 0;
   for (const auto& s : st) count += s.dx.size();
   std::vector<unsigned char> buf(head + count * sizeof(QuadEntry<T>), 0);
@@ -256,28 +315,57 @@ inline std::vector<unsigned char> pack_quad(const std::vector<QuadStencil>& st, 
   QuadEntry<T>* E = reinterpret_cast<QuadEntry<T>*>(buf.data() + head);
   size_t e = 0;
   for (int f = 0; f < F; ++f) {
-    begin[f] = (int32_t)e;
-    for (size_t q = 0; q < st[f].dx.size(); ++q, ++e) {
-      E[e].lds = (st[f].dx[q] * ly + st[f].dy[q]) * lz + st[f].dz[q];
-      E[e].pad = 0;
-      for (int c = 0; c < 4; ++c) E[e].c[c] = (T)st[f].c[q * 4 + c];
+    const QuadStencil& q = st[f];
+    for (int pass = 0; pass < 2; ++pass) {
+      begin[2 * f + pass] = (int32_t)e;
+      for (size_t r = 0; r < q.dx.size(); ++r) {
+        if ((q.paired[r] != 0) != (pass == 0)) continue;
+        E[e].lds = (q.dx[r] * ly + q.dy[r]) * lz + q.dz[r];
+        E[e].lds_mirror = pass == 0 ? -E[e].lds : 0;
+        for (int c = 0; c < 4; ++c) E[e].c[c] = (T)q.c[r * 4 + c];
+        ++e;
+      }
     }
   }
-  begin[F] = (int32_t)e;
+  begin[2 * F] = (int32_t)e;
   entries_at = head;
   return buf;
 }
 
-template <typename T>
-inline hipError_t launch_sphere_quad(const QuadArgs& a, int tx, int F, hipStream_t s) {
-  const int tiles_x = (a.nx + tx - 1) / tx;
+template <typename T, int H>
+inline void launch_sphere_quad_h(const QuadArgs& a, int F, hipStream_t s) {
+  constexpr int TX = quad_tx(H, sizeof(T));
+  static_assert(TX > 0, "tile does not fit the LDS budget");
+  const int tiles_x = (a.nx + TX - 1) / TX;
   const dim3 grid((unsigned)(tiles_x * a.tiles_y * a.tiles_z), (unsigned)F);
-  const size_t lds = (size_t)a.lx * a.ly * a.lz * sizeof(T);
-  switch (tx) {
-    case 8: hipLaunchKernelGGL((k_sphere_quad<T, 8>), grid, dim3(kQuadThreads), lds, s, a); break;
-    case 4: hipLaunchKernelGGL((k_sphere_quad<T, 4>), grid, dim3(kQuadThreads), lds, s, a); break;
-    case 2: hipLaunchKernelGGL((k_sphere_quad<T, 2>), grid, dim3(kQuadThreads), lds, s, a); break;
-    default: hipLaunchKernelGGL((k_sphere_quad<T, 1>), grid, dim3(kQuadThreads), lds, s, a); break;
+  hipLaunchKernelGGL((k_sphere_quad<T, H>), grid, dim3(kQuadThreads), 0, s, a);
+}
+
+// The largest reach each precision's tile takes.
+template <typename T>
+constexpr int quad_max_reach() {
+  int H = 1;
+  while (quad_tx(H + 1, sizeof(T)) > 0) ++H;
+  return H;
+}
+
+// Launch for reach a.H (1 <= a.H <= quad_max_reach<T>()).
+template <typename T>
+inline hipError_t launch_sphere_quad(const QuadArgs& a, int F, hipStream_t s) {
+  switch (a.H) {
+    case 1: launch_sphere_quad_h<T, 1>(a, F, s); break;
+    case 2: launch_sphere_quad_h<T, 2>(a, F, s); break;
+    case 3: launch_sphere_quad_h<T, 3>(a, F, s); break;
+    case 4: launch_sphere_quad_h<T, 4>(a, F, s); break;
+    default:
+      if constexpr (quad_max_reach<T>() >= 7) {
+        if (a.H == 5) launch_sphere_quad_h<T, 5>(a, F, s);
+        else if (a.H == 6) launch_sphere_quad_h<T, 6>(a, F, s);
+        else if (a.H == 7) launch_sphere_quad_h<T, 7>(a, F, s);
+        else return hipErrorInvalidValue;
+      } else {
+        return hipErrorInvalidValue;
+      }
   }
   return hipGetLastError();
 }
