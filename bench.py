@@ -420,7 +420,7 @@ def bench_sphere(ev, steps, warmup, no_cpu):
                                "R = 1.5, 3, 4 h, order 8 (64 nodes), scalar + vector integrals, mixed"},
         "stencil_offsets": entries,
         "roofline": {"bound": "alu", "achieved": res["mixed"]["tflops"], "peak": 157.3, "unit": "TFLOP/s",
-                     "frac": res["mixed"]["tflops"] / 157.3, "traffic": None},
+                     "frac": res["mixed"]["tflops"] / 157.3, "traffic": traffic_from_profile("sphere_quad", 1)},
         "fp64": dict(res["fp64"], frac_of_78_6=res["fp64"]["tflops"] / 78.6),
         "hbm_GBps_effective": res["mixed"]["hbm_GBps"],
         "accuracy_vs_exact_gaussian_bump_64": acc,
