@@ -29,7 +29,9 @@
  * Around the evaluation: batches of independent requests, captured replays
  * (HIP graphs), resident sessions in a device pool, free energies, the
  * equilibrium (Picard) solve, the bulk chemical potentials, a tile-shape
- * autotuner, pass timing and a calibration copy.
+ * autotuner, pass timing and a calibration copy.  Beside it: the delta-shell
+ * integrals by the product quadrature over spheres of Sec. 3.5
+ * (pnp_sphere_quadrature), a real-space alternative to the spectral weights.
  *
  * Discrete operator: each weight / pair kernel is the inverse DFT of its
  * continuous Fourier transform sampled at the grid wave-vectors (exact bulk
