@@ -1006,7 +1006,6 @@ pnp_status pnp_sphere_quadrature(pnp_ctx ctx, const pnp_grid* g, int32_t F, cons
   if (H > max_reach)
     return fail(ctx, PNP_E_UNSUPPORTED_SIZE, "sphere reach " + std::to_string(H) +
                                                  " grid points does not fit the LDS tile (R / h too large)");
-  const int tx = quad_tx(H, precision == PNP_FP64 ? sizeof(double) : sizeof(float));
   QuadArgs a;
   a.f = f;
   a.out = out;
@@ -1014,15 +1013,13 @@ pnp_status pnp_sphere_quadrature(pnp_ctx ctx, const pnp_grid* g, int32_t F, cons
   a.ny = g->ny;
   a.nz = g->nz;
   a.H = H;
-  a.lx = tx + 2 * H;
-  a.ly = kQuadTY + 2 * H;
-  a.lz = kQuadTZ + 2 * H;
+  const int ly = kQuadTY + 2 * H, lz = kQuadTZ + 2 * H;  // the kernel's tile pitches
   a.tiles_y = (g->ny + kQuadTY - 1) / kQuadTY;
   a.tiles_z = (g->nz + kQuadTZ - 1) / kQuadTZ;
   a.aperiodic = (flags & PNP_FLAG_APERIODIC) ? 1 : 0;
   size_t entries_at = 0;
-  std::vector<unsigned char> buf = precision == PNP_FP64 ? pack_quad<double>(st, a.ly, a.lz, entries_at)
-                                                         : pack_quad<float>(st, a.ly, a.lz, entries_at);
+  std::vector<unsigned char> buf = precision == PNP_FP64 ? pack_quad<double>(st, ly, lz, entries_at)
+                                                         : pack_quad<float>(st, ly, lz, entries_at);
   if (buf.size() > ctx->arena_bytes / 2)
     return fail(ctx, PNP_E_UNSUPPORTED_SIZE, "stencils too large for one call: pass fewer fields");
   if (hipSetDevice(ctx->device) != hipSuccess) return device_check(ctx, "set device");

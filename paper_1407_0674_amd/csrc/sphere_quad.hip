@@ -25,7 +25,6 @@
 
 #include <cmath>
 #include <cstdint>
-#include <string>
 #include <vector>
 
 namespace pnp {
@@ -55,8 +54,8 @@ struct QuadArgs {
                           // [begin[2f+1], begin[2f+2])
   const void* entries;
   int32_t nx, ny, nz;
-  int32_t H;              // stencil reach (max |offset| over all fields and axes)
-  int32_t lx, ly, lz;     // LDS tile extents
+  int32_t H;              // stencil reach (max |offset| over all fields and axes); selects
+                          // the kernel, whose tile extents follow from it
   int32_t tiles_y, tiles_z;
   int32_t aperiodic;
 };
