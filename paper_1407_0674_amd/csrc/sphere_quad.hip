@@ -128,7 +128,7 @@ __global__ __launch_bounds__(kQuadThreads) void k_sphere_quad(QuadArgs a) {
   const int e0 = a.begin[2 * field], e1 = a.begin[2 * field + 1], e2 = a.begin[2 * field + 2];
   // mirror pairs d, -d: the scalar weight multiplies the sum of the two
   // values and the vector weights their difference
-#pragma unroll 2
+#pragma unroll 4
   for (int e = e0; e < e1; ++e) {
     const T c0 = E[e].c[0], c1 = E[e].c[1], c2 = E[e].c[2], c3 = E[e].c[3];
     const T* p = col + E[e].lds;
