@@ -253,8 +253,10 @@ pnp_status pnp_weighted_densities(pnp_ctx ctx, const pnp_grid* grid, int32_t S,
  *   F          number of fields, 1..64
  *   f          device, float64 [F][nx][ny][nz], z fastest; read-only
  *   radius     host, F radii [nm], 0 < R <= 16 h; the stencil reach
- *              (about R / h + 1 grid points) must fit the LDS tile: up to 7
- *              points in PNP_MIXED, 4 in PNP_FP64 (else PNP_E_UNSUPPORTED_SIZE)
+ *              (about R / h + 1 grid points) must fit the LDS tile: up to 11
+ *              points in PNP_MIXED, 8 in PNP_FP64 (else PNP_E_UNSUPPORTED_SIZE);
+ *              reaches above 4 (FP64) or 7 (mixed) run with one workgroup
+ *              per compute unit
  *   order      k in [1, 64] (k*k nodes per sphere)
  *   precision  PNP_FP64 (double arithmetic) or PNP_MIXED (float arithmetic,
  *              float weights; inputs and outputs stay double)

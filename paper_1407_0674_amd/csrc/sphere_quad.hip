@@ -33,7 +33,8 @@ constexpr int kQuadTY = 8;       // outputs per workgroup along y
 constexpr int kQuadTZ = 32;      // outputs per workgroup along z (the fastest axis)
 constexpr int kQuadThreads = kQuadTY * kQuadTZ;
 constexpr int kQuadMaxFields = 64;
-constexpr size_t kQuadMaxLds = 65536;
+constexpr size_t kQuadFastLds = 65536;   // tiles up to this size keep several workgroups per CU
+constexpr size_t kQuadMaxLds = 163840;   // the most LDS one workgroup can hold on gfx950
 
 // One record of the merged stencil: an integer offset (its position in the
 // LDS tile relative to the output point) and the weights of the scalar and
@@ -66,12 +67,17 @@ __device__ __forceinline__ int quad_wrap(int i, int n) {
 }
 
 // Outputs per thread along x for a stencil reach H: the largest of 8, 4, 2, 1
-// whose tile fits the LDS budget; 0 if none does.
+// whose tile fits 64 KB (at least two workgroups per compute unit); for
+// spheres too wide for that, the largest whose tile fits the 160 KB a
+// workgroup can hold; 0 if none does.
+constexpr size_t quad_tile_bytes(int tx, int H, size_t elem) {
+  return (size_t)(tx + 2 * H) * (kQuadTY + 2 * H) * (kQuadTZ + 2 * H) * elem;
+}
 constexpr int quad_tx(int H, size_t elem) {
-  for (int tx = 8; tx >= 1; tx /= 2) {
-    const size_t bytes = (size_t)(tx + 2 * H) * (kQuadTY + 2 * H) * (kQuadTZ + 2 * H) * elem;
-    if (bytes <= kQuadMaxLds) return tx;
-  }
+  for (int tx = 8; tx >= 1; tx /= 2)
+    if (quad_tile_bytes(tx, H, elem) <= kQuadFastLds) return tx;
+  for (int tx = 8; tx >= 1; tx /= 2)
+    if (quad_tile_bytes(tx, H, elem) <= kQuadMaxLds) return tx;
   return 0;
 }
 
@@ -348,25 +354,23 @@ constexpr int quad_max_reach() {
   return H;
 }
 
-// Launch for reach a.H (1 <= a.H <= quad_max_reach<T>()).
+// Launch for reach a.H, 1 <= a.H <= quad_max_reach<T>() (11 in FP32, 8 in FP64).
+template <typename T, int H>
+inline hipError_t launch_sphere_quad_upto(const QuadArgs& a, int F, hipStream_t s) {
+  if constexpr (H > quad_max_reach<T>()) {
+    return hipErrorInvalidValue;
+  } else {
+    if (a.H == H) {
+      launch_sphere_quad_h<T, H>(a, F, s);
+      return hipGetLastError();
+    }
+    return launch_sphere_quad_upto<T, H + 1>(a, F, s);
+  }
+}
+
 template <typename T>
 inline hipError_t launch_sphere_quad(const QuadArgs& a, int F, hipStream_t s) {
-  switch (a.H) {
-    case 1: launch_sphere_quad_h<T, 1>(a, F, s); break;
-    case 2: launch_sphere_quad_h<T, 2>(a, F, s); break;
-    case 3: launch_sphere_quad_h<T, 3>(a, F, s); break;
-    case 4: launch_sphere_quad_h<T, 4>(a, F, s); break;
-    default:
-      if constexpr (quad_max_reach<T>() >= 7) {
-        if (a.H == 5) launch_sphere_quad_h<T, 5>(a, F, s);
-        else if (a.H == 6) launch_sphere_quad_h<T, 6>(a, F, s);
-        else if (a.H == 7) launch_sphere_quad_h<T, 7>(a, F, s);
-        else return hipErrorInvalidValue;
-      } else {
-        return hipErrorInvalidValue;
-      }
-  }
-  return hipGetLastError();
+  return launch_sphere_quad_upto<T, 1>(a, F, s);
 }
 
 }  // namespace pnp

@@ -77,9 +77,10 @@ def test_parity_64_fields(ev):
     _compare(got, f, radii, h, k, False, TOL[FP64])
 
 
-@pytest.mark.parametrize("precision,ratio", [(MIXED, 6.9), (FP64, 3.9)])
+@pytest.mark.parametrize("precision,ratio", [(MIXED, 6.9), (FP64, 3.9), (MIXED, 10.9), (FP64, 7.9)])
 def test_largest_reach(ev, precision, ratio):
-    # the largest sphere each precision's LDS tile takes (reach 7 and 4 points)
+    # the largest spheres each precision's 64 KB tile takes (reach 7 and 4
+    # points) and its 160 KB tile (reach 11 and 8)
     shape, h, k = (12, 10, 36), 0.05, 8
     f = _fields(shape, 2, 15)
     radii = [ratio * h, 0.5 * h]
@@ -152,8 +153,8 @@ def test_gaussian_bump_against_closed_form(ev):
     (dict(radius=[17 * 0.05]), "radius"),
     (dict(flags=4), "flag"),
     (dict(precision=7), "precision"),
-    (dict(radius=[4.2 * 0.05], precision=FP64), "LDS"),
-    (dict(radius=[7.6 * 0.05], precision=MIXED), "LDS"),
+    (dict(radius=[8.2 * 0.05], precision=FP64), "LDS"),
+    (dict(radius=[11.6 * 0.05], precision=MIXED), "LDS"),
 ])
 def test_errors(ev, kwargs, match):
     f = to_dev(_fields((8, 8, 8), 1, 18))
