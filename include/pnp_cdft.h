@@ -266,8 +266,9 @@ pnp_status pnp_weighted_densities(pnp_ctx ctx, const pnp_grid* grid, int32_t S,
  *   out        device, float64 [F][4][nx][ny][nz]: (I, I_x, I_y, I_z) per field
  * The stencil (at most a few hundred offsets per field for R / h <= 4) is
  * built on the host in double and copied to the context's ring on `stream`
- * from host memory that the call frees before it returns, so the call must
- * not be recorded into a HIP graph (stream capture).  Errors: PNP_E_ARG,
+ * from host memory that the call frees before it returns, so the call
+ * cannot be recorded into a HIP graph: on a capturing stream it returns
+ * PNP_E_ARG and enqueues nothing.  Errors: PNP_E_ARG,
  * PNP_E_UNSUPPORTED_SIZE, PNP_E_DEVICE.
  */
 pnp_status pnp_sphere_quadrature(pnp_ctx ctx, const pnp_grid* grid, int32_t F, const double* f,

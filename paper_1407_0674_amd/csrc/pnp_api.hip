@@ -1024,6 +1024,12 @@ pnp_status pnp_sphere_quadrature(pnp_ctx ctx, const pnp_grid* g, int32_t F, cons
     return fail(ctx, PNP_E_UNSUPPORTED_SIZE, "stencils too large for one call: pass fewer fields");
   if (hipSetDevice(ctx->device) != hipSuccess) return device_check(ctx, "set device");
   hipStream_t s = (hipStream_t)stream;
+  // the stencil is copied from host memory freed on return: a captured copy
+  // would read it at every replay
+  hipStreamCaptureStatus capture = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &capture) != hipSuccess) return device_check(ctx, "capture query");
+  if (capture != hipStreamCaptureStatusNone)
+    return fail(ctx, PNP_E_ARG, "pnp_sphere_quadrature cannot be recorded into a graph");
   const char* dev = (const char*)upload(ctx, buf.data(), buf.size(), s);
   if (!dev) return device_check(ctx, "stencil upload");
   a.begin = (const int32_t*)dev;

@@ -217,3 +217,23 @@ def test_fullsize_agrees_with_spectral_weights(ev):
     assert ev2 < 2e-2, ev2
     del w, n2_q, n2v_q, rd
     torch.cuda.empty_cache()
+
+
+@pytest.mark.filterwarnings("ignore:The CUDA Graph is empty")
+def test_capture_is_refused(ev):
+    """The stencil is copied from host memory freed on return, so the call
+    refuses a capturing stream instead of recording that copy."""
+    import torch
+    f = to_dev(_fields((8, 8, 8), 1, 21))
+    out = torch.empty((1, 4, 8, 8, 8), dtype=torch.float64, device="cuda:0")
+    g = torch.cuda.CUDAGraph()
+    raised = None
+    with torch.cuda.graph(g):
+        try:
+            ev.sphere_quadrature(f, [0.1], 0.05, 8, out=out, flags=FLAG_ASYNC)
+        except PnpError as e:
+            raised = e
+    assert raised is not None and "graph" in str(raised)
+    torch.cuda.synchronize()
+    ref = ev.sphere_quadrature(f, [0.1], 0.05, 8)
+    assert torch.isfinite(ref).all()
