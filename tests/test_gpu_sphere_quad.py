@@ -88,16 +88,17 @@ def test_largest_reach(ev, precision, ratio):
     _compare(got, f, radii, h, k, False, TOL[precision])
 
 
-@pytest.mark.parametrize("precision", [MIXED, FP64])
-def test_fullsize_sampled(ev, precision):
+@pytest.mark.parametrize("precision,aperiodic", [(MIXED, False), (FP64, False), (MIXED, True)])
+def test_fullsize_sampled(ev, precision, aperiodic):
     """256^3, the benchmark's densities and radii, order 8: 384 points per field
-    (a third on the faces and edges of the box) against the oracle evaluated
-    point by point."""
+    (a third on the faces and edges of the box, where the zero extension
+    matters) against the oracle evaluated point by point."""
     import torch
     prob, rho = P.config3(n=256)
     radii = [0.5 * s.d for s in prob.species]
     rd = to_dev(rho)
-    out = ev.sphere_quadrature(rd, radii, prob.h, 8, precision=precision)
+    out = ev.sphere_quadrature(rd, radii, prob.h, 8, precision=precision,
+                               flags=FLAG_APERIODIC if aperiodic else 0)
     rng = np.random.default_rng(16)
     n = prob.n
     pts = rng.integers(0, n, size=(384, 3))
@@ -106,7 +107,7 @@ def test_fullsize_sampled(ev, precision):
     idx = torch.tensor((pts[:, 0] * n + pts[:, 1]) * n + pts[:, 2], device=rd.device)
     got = out.reshape(prob.S, 4, -1)[:, :, idx].cpu().numpy()
     for i, R in enumerate(radii):
-        I, Iv = shell_integrals_at(rho[i], R, prob.h, 8, pts)
+        I, Iv = shell_integrals_at(rho[i], R, prob.h, 8, pts, aperiodic=aperiodic)
         scale = float(np.max(np.abs(I)))
         assert np.max(np.abs(got[i, 0] - I)) / scale < TOL[precision], i
         for a in range(3):
