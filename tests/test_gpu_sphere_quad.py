@@ -238,3 +238,32 @@ def test_capture_is_refused(ev):
     torch.cuda.synchronize()
     ref = ev.sphere_quadrature(f, [0.1], 0.05, 8)
     assert torch.isfinite(ref).all()
+
+
+def test_ring_wrap_interleaved_with_evaluations(ev):
+    """Stencil records share the context's argument ring with the evaluation's
+    records.  Enough asynchronous calls to wrap the ring several times,
+    interleaved with evaluations, each output checked against its first call."""
+    import torch
+    prob, rho = P.config2()
+    rd = to_dev(rho)
+    mu_ref, _ = ev.mu_ex(prob, rd)
+    # 48 fields at order 16 with the benchmark's radii: about 150 KB of stencil
+    # records per call, so 200 calls wrap the 4 MiB ring about seven times
+    shape, h, k = (16, 16, 32), 0.05, 16
+    f = to_dev(_fields(shape, 48, 22))
+    radii = [0.075, 0.15, 0.2] * 16
+    ref = ev.sphere_quadrature(f, radii, h, k)
+    outs = [torch.empty_like(ref) for _ in range(4)]
+    mus = [torch.empty_like(mu_ref) for _ in range(4)]
+    for it in range(200):
+        ev.sphere_quadrature(f, radii, h, k, flags=FLAG_ASYNC, out=outs[it % 4])
+        if it % 10 == 0:
+            ev.mu_ex(prob, rd, out=mus[(it // 10) % 4])
+        if it % 4 == 3:
+            torch.cuda.synchronize()
+            for o in outs:
+                assert torch.equal(o, ref), it
+    torch.cuda.synchronize()
+    for m in mus:
+        assert torch.equal(m, mu_ref)
