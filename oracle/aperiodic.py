@@ -11,18 +11,23 @@ shells that leave the domain.  Here:
   * the domain Omega is the n^3 grid, placed at the corner of a (2n)^3 grid
     of the same spacing;
   * every integrand is zero outside Omega: rho for the hard-sphere weights
-    and the square well, rho - rho_bulk for the electrostatic correlation;
+    and the square well, rho - rho_bulk for the electrostatic correlation,
+    and dPhi/dn_alpha for the hard-sphere back-convolution;
   * the discrete kernels are the spectral ones of the (2n)^3 grid, and the
     result is the periodic operator of that grid applied to the extended
     fields, read back on Omega.
 
 Displacements between two points of Omega stay below n per axis, so no
-pair of domain points meets through the doubled period: for the linear
-terms this is exactly the finite sum over Omega with the kernel of the
-doubled grid (pinned against that sum written out).  The hard-sphere
-weighted densities also exist outside Omega (a sphere that sticks out of
-the domain), and their derivatives there feed the back-convolution, as in
-the continuous integrals with the extended densities.
+pair of domain points meets through the doubled period: every convolution
+is exactly the finite sum over Omega with the kernel of the doubled grid
+(pinned against those sums written out).  Sec. 2.3.1 integrates the
+hard-sphere free-energy density over Omega, F_hs = int_Omega Phi(n(r)) dr,
+and its chemical potential mu_hs(r') = sum_alpha int_Omega dPhi/dn_alpha(r)
+omega_alpha(r' - r) dr.  The weighted densities themselves are non-zero
+outside Omega (a sphere centred outside still overlaps the domain), but
+Phi is not integrated there, so the derivative fields are set to zero
+outside Omega before the back-convolution (pinned by finite differences of
+F_hs = h^3 sum_Omega Phi).
 
 The 1D construction of Sec. 3.4 (two auxiliary kernel vectors, one reflected)
 is restated in `split_convolution_1d`; its reflected vector as printed is
@@ -50,7 +55,9 @@ def mu_ex_aperiodic(problem, rho, route="fft"):
     n2 = 2 * n
     rb = np.array([s.rho_bulk for s in problem.species])
     big = problem.with_(n=n2)
-    res = mu_ex(big, extend(rho, n2), route, drho=extend(rho - rb[:, None, None, None], n2))
+    domain = np.zeros((n2, n2, n2), dtype=bool)
+    domain[:n, :n, :n] = True
+    res = mu_ex(big, extend(rho, n2), route, drho=extend(rho - rb[:, None, None, None], n2), domain=domain)
     out = {k: res[k][:, :n, :n, :n].copy() for k in ("hs", "el", "sh", "total", "slotboom")}
     out["n_ext"] = res["n"]
     return out

@@ -56,6 +56,15 @@ def _unpack_n(vals):
             "n1v": np.stack(vals[4:7]), "n2v": np.stack(vals[7:10])}
 
 
+def _restrict(d, domain):
+    """The derivative fields with every value outside `domain` set to zero
+    (nothing changes when domain is None)."""
+    if domain is None:
+        return d
+    m = np.asarray(domain, dtype=bool)
+    return {k: np.where(m, v, 0.0) for k, v in d.items()}
+
+
 def _dphi_list(d):
     return [d["d0"], d["d1"], d["d2"], d["d3"], *d["d1v"], *d["d2v"]]
 
@@ -84,11 +93,16 @@ def weighted_densities(problem, rho, route="direct", op=None, kernels=None):
     return _unpack_n(vals)
 
 
-def mu_ex(problem, rho, route="direct", drho=None):
+def mu_ex(problem, rho, route="direct", drho=None, domain=None):
     """Returns a dict with 'n' (weighted densities), 'dphi', and per-term
     arrays 'hs', 'el', 'sh', 'total', 'slotboom', each (S, n, n, n).
     drho: the density deviation the EC convolution integrates (default
-    rho - rho_bulk everywhere)."""
+    rho - rho_bulk everywhere).
+    domain: None, or a boolean (n, n, n) array marking the points where the
+    free-energy density Phi_hs is integrated (F_hs = h^3 sum over those
+    points); the derivative fields dPhi/dn_alpha are then zero elsewhere
+    before the back-convolution, which is the functional derivative of that
+    restricted sum.  None integrates over the whole periodic grid."""
     rho = np.asarray(rho, dtype=np.float64)
     S, n = rho.shape[0], rho.shape[1]
     terms = problem.terms
@@ -107,7 +121,8 @@ def mu_ex(problem, rho, route="direct", drho=None):
         fields, kers, slots = [], [], []
         if hs_fn:
             nal = weighted_densities(problem, rho, "direct", op, kernels)
-            d = hs_fn[1](nal["n0"], nal["n1"], nal["n2"], nal["n3"], nal["n1v"], nal["n2v"])
+            d = _restrict(hs_fn[1](nal["n0"], nal["n1"], nal["n2"], nal["n3"], nal["n1v"], nal["n2v"]),
+                          domain)
             res["n"], res["dphi"] = nal, d
             dl = _dphi_list(d)
             for i in range(S):
@@ -134,7 +149,8 @@ def mu_ex(problem, rho, route="direct", drho=None):
             return np.fft.irfftn(f_hat * spec, s=(n, n, n), axes=(0, 1, 2))
         if hs_fn:
             nal = weighted_densities(problem, rho, "fft", op)
-            d = hs_fn[1](nal["n0"], nal["n1"], nal["n2"], nal["n3"], nal["n1v"], nal["n2v"])
+            d = _restrict(hs_fn[1](nal["n0"], nal["n1"], nal["n2"], nal["n3"], nal["n1v"], nal["n2v"]),
+                          domain)
             res["n"], res["dphi"] = nal, d
             dh = [np.fft.rfftn(x) for x in _dphi_list(d)]
             for i in range(S):

@@ -8,6 +8,12 @@
   point (no FFT);
 * the hard-sphere term through numpy's FFT equals the oracle's direct route
   (explicit kernels and O(N^2) sums) on the doubled grid;
+* the hard-sphere term equals its sums over the domain written out point by
+  point: weighted densities at the domain points from the domain's
+  densities, then the back-convolution of the derivative fields over the
+  domain only (Sec. 2.3.1 integrates Phi_hs over Omega);
+* central differences of F_hs = h^3 sum_Omega Phi_hs against single-point
+  density changes give h^3 beta mu_hs, at faces, edges, corners and inside;
 * the mode differs from the periodic one and is mirror-covariant about the
   domain's centre (x -> n - 1 - x).
 """
@@ -93,6 +99,72 @@ def test_hard_spheres_fft_equals_direct_route():
     assert np.max(np.abs(a["hs"] - b["hs"])) < 1e-11 * np.max(np.abs(b["hs"]))
     # weighted densities reach outside the domain (spheres that stick out)
     assert np.max(np.abs(a["n_ext"]["n3"][n:, :, :])) > 1e-3
+
+
+def _hs_kernels(op, n2, h, i):
+    """Real-space kernels of species i on the doubled grid: the four scalar
+    weights, then the three components of the two vector weights
+    (-i khat V, the outward shell), in the order n0..n3, n1v, n2v."""
+    w = op.w[i]
+    ks = [real_space_kernel(w[a].astype(complex), n2, h) for a in ("w0", "w1", "w2", "w3")]
+    for v in ("v1", "v2"):
+        ks += [real_space_kernel(-1j * op.khat[c] * w[v], n2, h) for c in range(3)]
+    return ks
+
+
+def _domain_correlation(K, field, n):
+    """out[r] = sum over r' in the n^3 domain of K[(r' - r) mod 2n] field[r'], r in the domain."""
+    n2 = K.shape[0]
+    out = np.zeros((n, n, n))
+    idx = np.arange(n)
+    for (x, y, z) in itertools.product(range(n), repeat=3):
+        out[x, y, z] = np.sum(K[np.ix_((idx - x) % n2, (idx - y) % n2, (idx - z) % n2)] * field)
+    return out
+
+
+@pytest.mark.parametrize("terms", [P.TERM_HS, P.TERM_HS_WB])
+def test_hard_sphere_term_is_domain_sum(terms):
+    n = 4
+    prob, rho = _small_problem(n, 17 + terms, terms)
+    got = mu_ex_aperiodic(prob, rho, "fft")["hs"]
+    op = build_operator(prob.with_(n=2 * n), half=False)
+    h3 = prob.h ** 3
+    kers = [_hs_kernels(op, 2 * n, prob.h, i) for i in range(2)]
+    # weighted densities at the domain points (correlation over the domain)
+    nal = [sum(h3 * _domain_correlation(kers[i][a], rho[i], n) for i in range(2)) for a in range(10)]
+    dfn = oracle.dphi_hs_wb if terms == P.TERM_HS_WB else oracle.dphi_hs
+    d = dfn(nal[0], nal[1], nal[2], nal[3], np.stack(nal[4:7]), np.stack(nal[7:10]))
+    dl = [d["d0"], d["d1"], d["d2"], d["d3"], *d["d1v"], *d["d2v"]]
+    for i in range(2):
+        # back-convolution over the domain: sum_r' dPhi_a[r'] K_a[r - r']
+        ref = sum(h3 * _domain_sum(kers[i][a], dl[a], n) for a in range(10))
+        assert np.max(np.abs(got[i] - ref)) < 1e-11 * np.max(np.abs(ref)), i
+
+
+def _f_hs_domain(prob, rho, n):
+    """F_hs = h^3 sum over the domain of Phi_hs of the zero-extended densities."""
+    big = prob.with_(n=2 * n)
+    nal = oracle.weighted_densities(big, extend(rho, 2 * n), "fft")
+    phi = (oracle.phi_hs_wb if prob.terms & P.TERM_HS_WB else oracle.phi_hs)(
+        nal["n0"], nal["n1"], nal["n2"], nal["n3"], nal["n1v"], nal["n2v"])
+    return prob.h ** 3 * float(np.sum(phi[:n, :n, :n]))
+
+
+@pytest.mark.parametrize("terms", [P.TERM_HS, P.TERM_HS_WB])
+def test_hard_sphere_term_is_derivative_of_domain_free_energy(terms):
+    n = 6
+    prob, rho = _small_problem(n, 29 + terms, terms)
+    mu = mu_ex_aperiodic(prob, rho, "fft")["hs"]
+    h3 = prob.h ** 3
+    scale = float(np.max(np.abs(mu)))
+    for (i, x, y, z) in [(0, 0, 0, 0), (1, n - 1, 0, 2), (0, 2, n - 1, n - 1), (1, 3, 2, 0), (0, 2, 3, 3),
+                         (1, n - 1, n - 1, n - 1)]:
+        step = 1e-4 * rho[i, x, y, z]
+        rp, rm = rho.copy(), rho.copy()
+        rp[i, x, y, z] += step
+        rm[i, x, y, z] -= step
+        fd = (_f_hs_domain(prob, rp, n) - _f_hs_domain(prob, rm, n)) / (2.0 * step * h3)
+        assert abs(fd - mu[i, x, y, z]) < 2e-7 * scale, (i, x, y, z, fd, mu[i, x, y, z])
 
 
 def test_differs_from_periodic_and_mirror_covariant():
