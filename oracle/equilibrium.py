@@ -13,7 +13,10 @@ the relaxation of Sec. 3.2:
 
     rho <- (1 - lambda) rho + lambda rho^bulk exp(beta mu^bulk - beta mu_ex[rho] - beta V),
 
-stopped when max_i max_r |rho_new - rho| / rho_i^bulk <= tol.
+stopped when max_i max_r |rho_new - rho| / rho_i^bulk <= tol.  Stationary
+species (Species.mobile false: the fixed sites of Sec. 2.3.2) keep their
+densities; they still shape mu_ex of the others, and they are left out of
+the residual.
 """
 import numpy as np
 
@@ -32,15 +35,21 @@ def picard(problem, rho0, beta_v=None, lam=0.1, tol=1e-10, max_iter=200, mu_bulk
     """Returns (rho, iterations, residual).  beta_v: [S][n][n][n] or None."""
     rho = np.array(rho0, dtype=np.float64)
     rb = np.array([s.rho_bulk for s in problem.species])
+    mobile = [getattr(s, "mobile", True) for s in problem.species]
     mb = bulk_mu_ex(problem) if mu_bulk is None else np.asarray(mu_bulk, dtype=np.float64)
     res = np.inf
     for it in range(1, max_iter + 1):
         mu = mu_ex(problem, rho, "fft")["total"]
-        g = mb[:, None, None, None] - mu
-        if beta_v is not None:
-            g = g - beta_v
-        new = (1.0 - lam) * rho + lam * rb[:, None, None, None] * np.exp(g)
-        res = float(np.max(np.abs(new - rho) / rb[:, None, None, None]))
+        new = rho.copy()
+        res = 0.0
+        for i in range(rho.shape[0]):
+            if not mobile[i]:
+                continue
+            g = mb[i] - mu[i]
+            if beta_v is not None:
+                g = g - beta_v[i]
+            new[i] = (1.0 - lam) * rho[i] + lam * rb[i] * np.exp(g)
+            res = max(res, float(np.max(np.abs(new[i] - rho[i]) / rb[i])))
         rho = new
         if res <= tol:
             return rho, it, res

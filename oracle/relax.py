@@ -14,16 +14,23 @@ old one as the relaxation step of Sec. 3.2 mixes new and old iterates:
 
 The limit is this build's choice for the stub (the paper's PNP loop has no
 such step): it bounds every density by max(rho_i, e^clip rho_i^bulk).
+
+Stationary species (the fixed sites of Sec. 2.3.2, which are not transported)
+keep their densities.
 """
 import numpy as np
 
 
-def relax_densities(rho, mu_ex, rho_bulk, mu_bulk, lam, clip=0.0):
-    """rho, mu_ex: float64 [S][...]; rho_bulk, mu_bulk: S values; lam in [0, 1]."""
+def relax_densities(rho, mu_ex, rho_bulk, mu_bulk, lam, clip=0.0, mobile=None):
+    """rho, mu_ex: float64 [S][...]; rho_bulk, mu_bulk: S values; lam in [0, 1];
+    mobile: S flags (None: every species moves)."""
     rho = np.asarray(rho, dtype=np.float64)
     mu_ex = np.asarray(mu_ex, dtype=np.float64)
     out = np.empty_like(rho)
     for i in range(rho.shape[0]):
+        if mobile is not None and not mobile[i]:
+            out[i] = rho[i]
+            continue
         g = mu_bulk[i] - mu_ex[i]
         if clip > 0:
             g = np.clip(g, -clip, clip)

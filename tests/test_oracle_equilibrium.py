@@ -57,3 +57,50 @@ def test_converged_state_is_self_consistent():
     assert np.max(np.abs(target - out) / rb) < 1e-10
     # cations gather where their potential is low, anions where theirs is
     assert out[0].reshape(16, -1).mean(axis=1).argmax() == bv[0].reshape(16, -1).mean(axis=1).argmin()
+
+
+def sites(n, h, centres, alpha, rho0):
+    """A stationary-site density of Gaussians, rho0 (alpha/pi)^(3/2) sum_k
+    exp(-alpha |r - R_k|^2) with minimum-image distances (the site density
+    form of Sec. 2.3.2)."""
+    L = n * h
+    c = np.arange(n) * h
+    out = np.zeros((n, n, n))
+    for R in centres:
+        d = [c - R[a] - L * np.round((c - R[a]) / L) for a in range(3)]
+        r2 = d[0][:, None, None] ** 2 + d[1][None, :, None] ** 2 + d[2][None, None, :] ** 2
+        out += np.exp(-alpha * r2)
+    return rho0 * (alpha / math.pi) ** 1.5 * out
+
+
+def test_stationary_species_stay_and_mobile_ones_equilibrate():
+    """A 1:1 electrolyte next to a stationary site density that attracts the
+    cations by a square well: the sites keep their density bit for bit, the
+    ions reach the equilibrium of mu_ex computed with the sites present, and
+    the cations gather at the sites."""
+    n, h = 16, 0.1
+    prob, rho, bv = electrolyte(n, terms=P.TERMS_ALL)
+    site = P.Species(0.2, 0.0, 0.0, 0.0, mobile=False)
+    sp = list(prob.species) + [site]
+    eps = np.zeros((3, 3))
+    eps[0, 2] = eps[2, 0] = 0.05          # cation-site well [eV]
+    rout = np.zeros((3, 3))
+    prob = prob.with_(species=sp, sw_eps=eps, sw_rout=rout)
+    rs = sites(n, h, [(0.4, 0.4, 0.4), (1.2, 1.0, 0.6)], 40.0, 1.0)
+    rho = np.concatenate([rho, rs[None]])
+    bv = np.concatenate([bv, np.zeros((1, n, n, n))])
+    out, it, res = oracle.picard(prob, rho, beta_v=bv, lam=0.5, tol=1e-11, max_iter=400)
+    assert res <= 1e-11
+    assert np.array_equal(out[2], rs)
+    mu = oracle.mu_ex(prob, out, "fft")["total"]
+    mb = oracle.bulk_mu_ex(prob)
+    for i in range(2):
+        rb = prob.species[i].rho_bulk
+        target = rb * np.exp(mb[i] - mu[i] - bv[i])
+        assert np.max(np.abs(target - out[i]) / rb) < 1e-10
+    # the well draws cations to the sites: more of them at a site centre than
+    # with the well switched off
+    off, _, res0 = oracle.picard(prob.with_(sw_eps=np.zeros((3, 3))), rho, beta_v=bv, lam=0.5, tol=1e-11,
+                                 max_iter=400)
+    assert res0 <= 1e-11 and np.array_equal(off[2], rs)
+    assert out[0, 4, 4, 4] > 1.05 * off[0, 4, 4, 4]

@@ -55,3 +55,17 @@ def test_limit_bounds_the_exponent():
     # clip <= 0: no limit
     out0 = oracle.relax_densities(rho, mu, [2.0], [0.0], 1.0, clip=0.0)
     assert np.allclose(out0, 2.0 * np.exp(-mu), rtol=1e-15, atol=0)
+
+
+def test_stationary_species_keep_their_density():
+    # a stationary species (mobile = False) is left as it is, bit for bit; the
+    # mobile ones get exactly the update they get when every species moves
+    rng = np.random.default_rng(5)
+    rho = rng.uniform(0.1, 2.0, size=(3, 4, 4, 4))
+    mu = rng.normal(size=rho.shape)
+    args = (rho, mu, [1.0, 2.0, 3.0], [0.1, 0.2, 0.3], 0.4)
+    all_mobile = oracle.relax_densities(*args, clip=0.7)
+    out = oracle.relax_densities(*args, clip=0.7, mobile=[True, False, True])
+    assert np.array_equal(out[1], rho[1])
+    assert np.array_equal(out[[0, 2]], all_mobile[[0, 2]])
+    assert not np.array_equal(all_mobile[1], rho[1])
