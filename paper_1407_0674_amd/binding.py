@@ -50,7 +50,7 @@ class Grid(ctypes.Structure):
 
 class SpeciesC(ctypes.Structure):
     _fields_ = [("d", ctypes.c_double), ("q", ctypes.c_double), ("rho_bulk", ctypes.c_double),
-                ("mu_el_bulk", ctypes.c_double)]
+                ("mu_el_bulk", ctypes.c_double), ("mobile", ctypes.c_int32)]
 
 
 class ParamsC(ctypes.Structure):
@@ -169,7 +169,8 @@ class _Marshal:
     def __init__(self, problem, per_term=False, flags=0, precision=None):
         S = len(problem.species)
         self.grid = Grid(problem.n, problem.n, problem.n, float(problem.h))
-        self.species = (SpeciesC * S)(*[SpeciesC(s.d, s.q, s.rho_bulk, s.mu_el_bulk)
+        self.species = (SpeciesC * S)(*[SpeciesC(s.d, s.q, s.rho_bulk, s.mu_el_bulk,
+                                                  int(bool(getattr(s, "mobile", True))))
                                          for s in problem.species])
         self._eps = None if problem.sw_eps is None else np.ascontiguousarray(problem.sw_eps, dtype=np.float64)
         self._rout = None if problem.sw_rout is None else np.ascontiguousarray(problem.sw_rout, dtype=np.float64)

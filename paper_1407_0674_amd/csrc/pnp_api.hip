@@ -16,7 +16,8 @@
 #include <vector>
 
 #include "pnp_cdft.h"
-#include "pnp_kernels.hip"
+#include "pnp_launch.hpp"
+#include "pnp_misc.hip"
 #include "sphere_quad.hip"
 
 using namespace pnp;
@@ -126,6 +127,14 @@ struct Layout {
 };
 
 inline int padded_species(int S) { return (S + 3) / 4 * 4; }
+
+// bit i set = species i is stationary (the density updates leave it alone)
+inline uint32_t fixed_mask(int S, const pnp_species* sp) {
+  uint32_t m = 0u;
+  for (int i = 0; i < S; ++i)
+    if (!sp[i].mobile) m |= 1u << i;
+  return m;
+}
 
 Layout layout_of(int n, int S, int precision, bool hs, bool pairs, bool per_term) {
   Layout L{};
@@ -331,116 +340,23 @@ pnp_status read_status(pnp_ctx c, const void* status_dev, hipStream_t s) {
 }
 
 // ---------------------------------------------------------------------------
-// launchers per (precision, n)
+// launchers per (precision, n): instantiated in their own translation units
+// (pnp_ops.hip, one per precision and size), found here through ops_inst
 // ---------------------------------------------------------------------------
-struct Ops {
-  void (*tables)(const TableArgs*, int, int, int, hipStream_t);
-  void (*zfwd)(const EvalArgs*, int, hipStream_t);
-  void (*ystep)(const EvalArgs*, int, int, int, bool, hipStream_t);
-  void (*xfwd)(const EvalArgs*, int, hipStream_t);
-  void (*zderiv)(const EvalArgs*, int, bool, int, hipStream_t);
-  void (*xback)(const EvalArgs*, int, int, bool, hipStream_t);
-  int zderiv_tiles;  // workgroups of the derivative pass per instance
-  void (*zinv)(const EvalArgs*, int, int, hipStream_t);
-  void (*xplain)(const EvalArgs*, int, int, bool, hipStream_t);
-  void (*xport)(const EvalArgs*, int, double*, int, hipStream_t);
-};
-
-template <typename T, int N, int V = 0> struct Launch {
-  using G = Geo<T, N, V>;
-  using GD = GeoD<T, N, default_ezd<T, N>(), V>;
-  static constexpr int EZD = default_ezd<T, N>();
-  // maxS: the largest species count among the launch's instances
-  static void tables(const TableArgs* a, int count, int M, int maxS, hipStream_t s) {
-    const int items = maxS * ((maxS + 3) / 4 * 4) + maxS;  // pair-table entries + hs species
-    hipLaunchKernelGGL(k_tables<T>, dim3((M + 255) / 256, items, count), dim3(256), 0, s, a);
-  }
-  static void zfwd(const EvalArgs* a, int count, hipStream_t s) {
-    hipLaunchKernelGGL((k_zfwd<T, N, V>), dim3(count * G::tiles_z), dim3(G::RZ * G::TZ), 0, s, a);
-  }
-  static void ystep(const EvalArgs* a, int count, int sel, int nf, bool fwd, hipStream_t s) {
-    if (fwd)
-      hipLaunchKernelGGL((k_ystep<T, N, true, V>), dim3(count * G::tiles_y), dim3(G::PY * G::TY), 0, s, a, sel, nf);
-    else
-      hipLaunchKernelGGL((k_ystep<T, N, false, V>), dim3(count * G::tiles_y), dim3(G::PY * G::TY), 0, s, a, sel,
-                         nf);
-  }
-  static void xfwd(const EvalArgs* a, int count, hipStream_t s) {
-    hipLaunchKernelGGL((k_xfwd<T, N, G::EX, G::PX>), dim3(count * G::tiles_x), dim3(G::PX * G::TX), 0, s, a);
-  }
-  // phi: also sum Phi_hs per workgroup (free-energy calls); fmask: the
-  // hard-sphere functionals among the instances (1 Rosenfeld, 2 White Bear),
-  // one launch of the matching variant each
-  static void zderiv(const EvalArgs* a, int count, bool phi, int fmask, hipStream_t s) {
-    const dim3 g(count * GD::tiles), b(GD::RDD * GD::TZD);
-    if (fmask & 1) {
-      if (phi) hipLaunchKernelGGL((k_zderiv<T, N, true, false, EZD, V>), g, b, 0, s, a);
-      else hipLaunchKernelGGL((k_zderiv<T, N, false, false, EZD, V>), g, b, 0, s, a);
-    }
-    if (fmask & 2) {
-      if (phi) hipLaunchKernelGGL((k_zderiv<T, N, true, true, EZD, V>), g, b, 0, s, a);
-      else hipLaunchKernelGGL((k_zderiv<T, N, false, true, EZD, V>), g, b, 0, s, a);
-    }
-  }
-  // smax: the largest species count among the launch's instances with at
-  // most four species (0: none); large: some instance has more than four.
-  // The FP32 path runs the streamed kernel for the former and the chunked one
-  // for the latter (each skips the other's instances), so an instance gets
-  // the arithmetic of its single call in any launch list.
-  static void xback(const EvalArgs* a, int count, int smax, bool large, hipStream_t s) {
-    const dim3 g(count * G::tiles_x), b(G::PX * G::TX);
-    if constexpr (sizeof(T) == 8) {
-      // FP64: the streamed kernel does not fit the register file; the chunked
-      // one keeps every spectrum in registers without spilling
-      hipLaunchKernelGGL((k_xback_chunked<T, N, 4, G::EX, G::PX>), g, b, 0, s, a, 1);
-    } else {
-      switch (smax) {
-        case 1: hipLaunchKernelGGL((k_xback<T, N, 1, G::EX, G::PX>), g, b, 0, s, a); break;
-        case 2: hipLaunchKernelGGL((k_xback<T, N, 2, G::EX, G::PX>), g, b, 0, s, a); break;
-        case 3: hipLaunchKernelGGL((k_xback<T, N, 3, G::EX, G::PX>), g, b, 0, s, a); break;
-        case 4: hipLaunchKernelGGL((k_xback<T, N, 4, G::EX, G::PX>), g, b, 0, s, a); break;
-        default: break;
-      }
-      if (large) hipLaunchKernelGGL((k_xback_chunked<T, N, 4, G::EX, G::PX>), g, b, 0, s, a, 5);
-    }
-  }
-  static void zinv(const EvalArgs* a, int count, int sel, hipStream_t s) {
-    hipLaunchKernelGGL((k_zinv<T, N, V>), dim3(count * G::tiles_z), dim3(G::RZ * G::TZ), 0, s, a, sel);
-  }
-  static void xplain(const EvalArgs* a, int count, int nf, bool fwd, hipStream_t s) {
-    if (fwd)
-      hipLaunchKernelGGL((k_xplain<T, N, true, G::EX, G::PX>), dim3(count * G::tiles_x), dim3(G::PX * G::TX), 0, s,
-                         a, 0, nf);
-    else
-      hipLaunchKernelGGL((k_xplain<T, N, false, G::EX, G::PX>), dim3(count * G::tiles_x), dim3(G::PX * G::TX), 0,
-                         s, a, 0, nf);
-  }
-  static void xport(const EvalArgs* a, int nf, double* buf, int to_numpy, hipStream_t s) {
-    const long total = (long)nf * N * N * (N / 2 + 1);
-    const int blocks = (int)std::min<long>((total + 255) / 256, 4096);
-    hipLaunchKernelGGL((k_export<T, N>), dim3(blocks), dim3(256), 0, s, a, nf, buf, to_numpy);
-  }
-  static constexpr Ops ops{tables, zfwd, ystep, xfwd, zderiv, xback, GD::tiles, zinv, xplain, xport};
-};
-
-// Grids up to kNarrowMax also have the narrow tile shape (V = 1); larger
-// ones already launch thousands of workgroups per pass.
-constexpr int kNarrowMax = 128;
-
 template <typename T, int V>
 const Ops* ops_for_n(int n) {
   if (V == 1 && n > kNarrowMax) return nullptr;
   switch (n) {
-    case 8: return &Launch<T, 8, V>::ops;
-    case 16: return &Launch<T, 16, V>::ops;
-    case 24: return &Launch<T, 24, V>::ops;
-    case 32: return &Launch<T, 32, V>::ops;
-    case 48: return &Launch<T, 48, V>::ops;
-    case 64: return &Launch<T, 64, V>::ops;
-    case 96: return &Launch<T, 96, V>::ops;
-    case 128: return &Launch<T, 128, V>::ops;
-    case 192: return V == 0 ? &Launch<T, 192, 0>::ops : nullptr;
-    case 256: return V == 0 ? &Launch<T, 256, 0>::ops : nullptr;
+    case 8: return ops_inst<T, 8, V>();
+    case 16: return ops_inst<T, 16, V>();
+    case 24: return ops_inst<T, 24, V>();
+    case 32: return ops_inst<T, 32, V>();
+    case 48: return ops_inst<T, 48, V>();
+    case 64: return ops_inst<T, 64, V>();
+    case 96: return ops_inst<T, 96, V>();
+    case 128: return ops_inst<T, 128, V>();
+    case 192: return V == 0 ? ops_inst<T, 192, 0>() : nullptr;
+    case 256: return V == 0 ? ops_inst<T, 256, 0>() : nullptr;
     default: return nullptr;
   }
 }
@@ -887,8 +803,10 @@ pnp_status pnp_equilibrium(pnp_ctx ctx, const pnp_grid* g, int32_t S, const pnp_
   if (!(tol >= 0.0) || max_iter < 1) return fail(ctx, PNP_E_ARG, "tol must be >= 0 and max_iter >= 1");
   if (p->per_term) return fail(ctx, PNP_E_ARG, "per_term is not available here");
   if ((uintptr_t)ws % kAlign) return fail(ctx, PNP_E_ARG, "workspace must be 256-byte aligned");
+  const uint32_t fixed = fixed_mask(S, sp);
   for (int i = 0; i < S; ++i)
-    if (!(sp[i].rho_bulk > 0.0)) return fail(ctx, PNP_E_ARG, "bulk densities must be > 0");
+    if (!((fixed >> i) & 1u) && !(sp[i].rho_bulk > 0.0))
+      return fail(ctx, PNP_E_ARG, "bulk densities of mobile species must be > 0");
   const bool pairs = d.ec || d.sw;
   const Layout L = layout_of(d.n, S, d.precision, d.hs, pairs, false);
   if (ws_bytes < L.total) return fail(ctx, PNP_E_NOMEM, "workspace too small: need " + std::to_string(L.total));
@@ -919,7 +837,7 @@ pnp_status pnp_equilibrium(pnp_ctx ctx, const pnp_grid* g, int32_t S, const pnp_
     run_sequence(ctx, select_ops(ctx, d.precision, d.n, 1), dea, dta, 1, L.M, hs_mask(d), mix_of(S), s);
     if (hipMemsetAsync(res, 0, sizeof(unsigned long long), s) != hipSuccess) return device_check(ctx, "reset");
     hipLaunchKernelGGL(k_picard, dim3(blocks), dim3(256), 0, s, rho, (const double*)mu, beta_v, n3, (int)S, drb,
-                       lambda, res);
+                       lambda, res, fixed);
     st = device_check(ctx, "picard launch");
     if (st != PNP_OK) return st;
     unsigned long long rbits = 0;
@@ -1160,7 +1078,7 @@ pnp_status pnp_plan_create(pnp_ctx ctx, int32_t count, pnp_request* reqs, const 
         const int blocks = (int)std::min<long>((q.S * n3 + 255) / 256, 4096);
         hipLaunchKernelGGL(k_relax, dim3(blocks), dim3(256), 0, cs, (double*)q.rho, (const double*)q.mu_ex, n3,
                            (int)q.S, (const double*)(blk + rb_off[r]), relax[r].lambda, relax[r].clip,
-                           (const uint32_t*)p->status[r]);
+                           (const uint32_t*)p->status[r], fixed_mask(q.S, q.species));
       }
     ctx->capturing = false;
     ok = hipStreamEndCapture(cs, &p->graph) == hipSuccess && p->graph;
@@ -1323,7 +1241,7 @@ pnp_status pnp_relax_densities(pnp_ctx ctx, const pnp_grid* g, int32_t S, const 
   const long n3 = (long)g->nx * g->ny * g->nz;
   const int blocks = (int)std::min<long>((S * n3 + 255) / 256, 4096);
   hipLaunchKernelGGL(k_relax, dim3(blocks), dim3(256), 0, s, rho, mu, n3, (int)S, drb, lambda, clip,
-                     (const uint32_t*)nullptr);
+                     (const uint32_t*)nullptr, fixed_mask(S, sp));
   return device_check(ctx, "relax launch");
 }
 

@@ -1,0 +1,34 @@
+// The launch table of the evaluation's passes for one (precision, grid
+// size, tile shape): host functions that launch each pass kernel over a
+// device table of per-instance arguments.  The table of each (precision,
+// size) is built in its own translation unit (pnp_ops.hip compiled once per
+// pair), so the kernels of different sizes compile in parallel; the ABI's
+// translation unit only declares ops_inst.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "pnp_kernels.hpp"
+
+namespace pnp {
+
+struct Ops {
+  void (*tables)(const TableArgs*, int, int, int, hipStream_t);
+  void (*zfwd)(const EvalArgs*, int, hipStream_t);
+  void (*ystep)(const EvalArgs*, int, int, int, bool, hipStream_t);
+  void (*xfwd)(const EvalArgs*, int, hipStream_t);
+  void (*zderiv)(const EvalArgs*, int, bool, int, hipStream_t);
+  void (*xback)(const EvalArgs*, int, int, bool, hipStream_t);
+  int zderiv_tiles;  // workgroups of the derivative pass per instance
+  void (*zinv)(const EvalArgs*, int, int, hipStream_t);
+  void (*xplain)(const EvalArgs*, int, int, bool, hipStream_t);
+  void (*xport)(const EvalArgs*, int, double*, int, hipStream_t);
+};
+
+// Grids up to kNarrowMax also have the narrow tile shape (V = 1); larger
+// ones already launch thousands of workgroups per pass.
+constexpr int kNarrowMax = 128;
+
+// the launch table of (T, N, V); defined by the translation unit of (T, N)
+template <typename T, int N, int V> const Ops* ops_inst();
+
+}  // namespace pnp

@@ -35,13 +35,16 @@ BASE_SEED = 14070674
 
 @dataclass(frozen=True)
 class Species:
-    """One mobile (or fixed) species: hard-core diameter d [nm], valence q,
-    bulk density rho_bulk [nm^-3] and the bulk electrostatic-correlation
-    chemical potential mu_el_bulk [k_B T] that the paper leaves unspecified."""
+    """One species: hard-core diameter d [nm], valence q, bulk density
+    rho_bulk [nm^-3], the bulk electrostatic-correlation chemical potential
+    mu_el_bulk [k_B T] that the paper leaves unspecified, and whether it is
+    mobile (an ion) or stationary (fixed sites, whose density the density
+    updates leave alone)."""
     d: float
     q: float
     rho_bulk: float
     mu_el_bulk: float = 0.0
+    mobile: bool = True
 
 
 @dataclass
@@ -137,6 +140,25 @@ def gaussian_channel_profile(rng, n: int, h: float, rho_b: Sequence[float],
     return out
 
 
+def channel_3d(rng, n: int, h: float, rho_b: Sequence[float], q: Sequence[float],
+               amp: float = 0.5, noise: float = 0.1, nyquist: float = 0.05) -> np.ndarray:
+    """The Gaussian tube of gaussian_channel made to vary along all three
+    axes: the tube densities times
+        1 + noise * U(-1, 1) + nyquist * ((-1)^x + (-1)^y + (-1)^z) / 3,
+    with the uniform draws i.i.d. per point and species.  The noise puts
+    weight on every wave-vector (k_y = 0 is no longer singled out), and the
+    alternating-sign terms put a sizeable share of it on the three Nyquist
+    planes.  Densities stay positive for amp + noise + nyquist < 1."""
+    prof = gaussian_channel_profile(rng, n, h, rho_b, q, amp)
+    S = len(rho_b)
+    alt = np.where(np.arange(n) % 2 == 0, 1.0, -1.0)
+    stag = (alt[:, None, None] + alt[None, :, None] + alt[None, None, :]) / 3.0
+    out = np.empty((S, n, n, n))
+    for i in range(S):
+        out[i] = prof[i][:, None, :] * (1.0 + noise * rng.uniform(-1.0, 1.0, size=(n, n, n)) + nyquist * stag)
+    return out
+
+
 def local_packing_max(rho: np.ndarray, species: Sequence[Species]) -> float:
     """max_r sum_i rho_i(r) * pi d_i^3 / 6: the workload's own (unsmoothed)
     packing fraction, used only to size the inputs."""
@@ -163,10 +185,13 @@ def config1(seed: int = BASE_SEED + 1):
 
 
 def channel_problem(n: int, seed: int, precision: int = FP64, h: float = 0.05,
-                    T: float = 300.0, terms: int = TERMS_ALL):
+                    T: float = 300.0, terms: int = TERMS_ALL, pattern: str = "3d"):
     """The three-species channel electrolyte of the 64^3 workload at any n:
     d = 0.15/0.30/0.40 nm, z = +1/-1/-3, bulk ~ U(0.5, 2.0) M, Gaussian tube
-    modulation of amplitude 50 %, HS + EC + SW."""
+    modulation of amplitude 50 %, HS + EC + SW.
+    pattern "3d" (default): the tube with 10 % i.i.d. noise and 5 %
+    alternating-sign (Nyquist) components, varying along every axis
+    (channel_3d); "tube": the plain tube, constant along y."""
     rng = np.random.default_rng(seed)
     d = (0.15, 0.30, 0.40)
     q = (+1.0, -1.0, -3.0)
@@ -175,7 +200,12 @@ def channel_problem(n: int, seed: int, precision: int = FP64, h: float = 0.05,
     eps, rout = uniform_well(sp, 0.3, 0.3)
     prob = Problem(n=n, h=h, species=sp, T=T, terms=terms, sw_eps=eps, sw_rout=rout,
                    precision=precision, name=f"channel-{n}^3-S3")
-    rho = gaussian_channel(rng, n, h, [s.rho_bulk for s in sp], q, 0.5)
+    if pattern == "tube":
+        rho = gaussian_channel(rng, n, h, [s.rho_bulk for s in sp], q, 0.5)
+    elif pattern == "3d":
+        rho = channel_3d(rng, n, h, [s.rho_bulk for s in sp], q, 0.5)
+    else:
+        raise ValueError(f"unknown pattern {pattern!r}")
     return prob, rho
 
 
@@ -186,10 +216,10 @@ def config2(seed: int = BASE_SEED + 2, n: int = 64):
 
 
 def config3(seed: int = BASE_SEED + 3, n: int = 256, eta_max: float = 0.45,
-            precision: int = MIXED):
+            precision: int = MIXED, pattern: str = "3d"):
     """Channel electrolyte at 256^3 scaled (densities and bulk alike) so that
     the largest local packing fraction is eta_max = 0.45."""
-    prob, rho = channel_problem(n, seed, precision)
+    prob, rho = channel_problem(n, seed, precision, pattern=pattern)
     f = eta_max / local_packing_max(rho, prob.species)
     sp = [Species(s.d, s.q, s.rho_bulk * f, s.mu_el_bulk) for s in prob.species]
     prob = prob.with_(species=sp, name=f"cfg3-{n}^3-S3-eta{eta_max}")
@@ -224,7 +254,7 @@ def random_instance(rng, n_choices, precision: int = MIXED, h: float = 0.05,
 def many_species(n: int, S: int, seed: int, precision: int = FP64, h: float = 0.05, terms: int = TERMS_ALL):
     """S species (1..8) of the random-instance recipe with bulk ~ U(0.1, 1.0) M
     (lower, so that eight species stay well below close packing), 300 K,
-    channel pattern."""
+    the three-dimensional channel pattern (channel_3d)."""
     rng = np.random.default_rng(seed)
     d = rng.uniform(0.15, 0.45, size=S)
     rb = rng.uniform(0.1, 1.0, size=S) * MOLAR_TO_NM3
@@ -233,7 +263,7 @@ def many_species(n: int, S: int, seed: int, precision: int = FP64, h: float = 0.
     eps, rout = uniform_well(sp, 0.3, 0.3)
     prob = Problem(n=n, h=h, species=sp, T=300.0, terms=terms, sw_eps=eps, sw_rout=rout,
                    precision=precision, name=f"many-{n}^3-S{S}")
-    return prob, gaussian_channel(rng, n, h, [s.rho_bulk for s in sp], list(q), 0.5)
+    return prob, channel_3d(rng, n, h, [s.rho_bulk for s in sp], list(q), 0.5)
 
 
 def config4(seed: int = BASE_SEED + 4, count: int = 64, n_choices=(32, 48, 64, 96, 128),
@@ -290,6 +320,6 @@ def config5(seed: int = BASE_SEED + 5, rate: float = 200.0, duration: float = 10
 __all__ = [
     "MOLAR_TO_NM3", "TERM_HS", "TERM_EC", "TERM_SW", "TERM_HS_WB", "TERMS_ALL", "FP64", "MIXED",
     "Species", "Problem", "Request", "uniform_well", "uniform_noise",
-    "gaussian_channel", "gaussian_channel_profile", "local_packing_max", "config1", "config2", "config3",
+    "gaussian_channel", "gaussian_channel_profile", "channel_3d", "local_packing_max", "config1", "config2", "config3",
     "config4", "config5", "channel_problem", "random_instance", "many_species", "BASE_SEED",
 ]

@@ -58,12 +58,33 @@ def test_null_arguments_are_rejected_without_device():
     assert lib.pnp_workspace_bytes(None, None, 1, None, None) == -1
 
 
-def test_struct_layouts_match_header():
-    # natural C alignment: grid = 3 int32 + pad + double; params = 4 x 4 bytes + 5 x 8
-    assert ctypes.sizeof(binding.Grid) == 24
-    assert ctypes.sizeof(binding.SpeciesC) == 32
-    assert ctypes.sizeof(binding.ParamsC) == 56
-    assert binding.RequestC.status.offset == ctypes.sizeof(binding.RequestC) - 8
+def test_struct_layouts_match_header(tmp_path):
+    """Sizes and field offsets of the binding's records equal what a C
+    compiler makes of include/pnp_cdft.h (gcc on the host)."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no host C compiler")
+    recs = {"pnp_grid": binding.Grid, "pnp_species": binding.SpeciesC, "pnp_params": binding.ParamsC,
+            "pnp_request": binding.RequestC, "pnp_relax_spec": binding.RelaxSpecC}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "pnp_cdft.h"', 'int main(void) {']
+    for cname, py in recs.items():
+        lines.append(f'  printf("{cname} sizeof %zu\\n", sizeof({cname}));')
+        for fname, _ in py._fields_:
+            cf = "lambda" if fname == "lambda_" else fname
+            lines.append(f'  printf("{cname} {fname} %zu\\n", offsetof({cname}, {cf}));')
+    lines += ['  return 0;', '}']
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split("\n")
+    got = {(a, b): int(c) for a, b, c in (ln.split() for ln in out if ln.strip())}
+    for cname, py in recs.items():
+        assert got[(cname, "sizeof")] == ctypes.sizeof(py), cname
+        for fname, _ in py._fields_:
+            assert got[(cname, fname)] == getattr(py, fname).offset, (cname, fname)
 
 
 def _uniform(problem, n=8):

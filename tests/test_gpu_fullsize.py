@@ -3,7 +3,9 @@
 mu_ex and Slotboom outputs), checked at 512 sampled grid points per species
 against values the FP64 oracle wrote (tests/golden/cfg3_256_samples.json,
 made by tests/golden/make_cfg3_samples.py), and against the FP64 GPU path
-everywhere.
+everywhere.  The same checks run at 192^3 (the largest served size, a
+radix-3 grid; tests/golden/cfg3_192_samples.json).  The densities vary along
+all three axes (noise and alternating-sign components on the channel).
 
 Bars: sampled values within 1e-5 of the oracle term's largest magnitude
 (per species); the mixed path within 1e-5 of the FP64 path per term
@@ -23,15 +25,21 @@ pytestmark = pytest.mark.gpu
 HERE = os.path.dirname(os.path.abspath(__file__))
 
 
+@pytest.fixture(scope="module", params=[256, 192])
+def size(request):
+    return request.param
+
+
 @pytest.fixture(scope="module")
-def golden():
-    with open(os.path.join(HERE, "golden", "cfg3_256_samples.json")) as f:
+def golden(size):
+    with open(os.path.join(HERE, "golden", f"cfg3_{size}_samples.json")) as f:
         return json.load(f)
 
 
 @pytest.fixture(scope="module")
-def workload():
-    prob, rho = P.config3()
+def workload(size):
+    print(f"workload n={size}", flush=True)
+    prob, rho = P.config3(n=size)
     return prob, torch.from_numpy(rho).to("cuda:0").contiguous()
 
 
@@ -50,7 +58,7 @@ def _check(golden, mu3, tol, what):
             assert err < tol, (what, term, s, err)
 
 
-def test_cfg3_256_mixed_as_timed(ev, golden, workload):
+def test_cfg3_mixed_as_timed(ev, golden, workload):
     prob, rho = workload
     S, n = prob.S, prob.n
     out = torch.empty((S, n, n, n), dtype=torch.float64, device=rho.device)
@@ -69,7 +77,7 @@ def test_cfg3_256_mixed_as_timed(ev, golden, workload):
     del out, slot
 
 
-def test_cfg3_256_mixed_per_term(ev, golden, workload):
+def test_cfg3_mixed_per_term(ev, golden, workload):
     prob, rho = workload
     mu3, _ = ev.mu_ex(prob, rho, per_term=True, slotboom=False)
     _check(golden, mu3, 1e-5, "mixed")

@@ -197,12 +197,14 @@ def test_runs_on_the_callers_stream(ev):
 
 def test_fullsize_agrees_with_spectral_weights(ev):
     """The two GPU routes to the delta-shell weighted densities at 256^3 with
-    the benchmark's densities: n2 and n2v from the sphere quadrature (order 8,
-    FP64) against the spectral weights of pnp_weighted_densities.  The
-    densities vary over about 1 nm against h = 0.05 nm, so the quadrature's
-    trilinear error stays well under 1 % of the largest value."""
+    the benchmark's smooth channel (the plain tube, without the point-to-point
+    noise of the parity inputs, which no interpolating quadrature resolves):
+    n2 and n2v from the sphere quadrature (order 8, FP64) against the spectral
+    weights of pnp_weighted_densities.  The densities vary over about 1 nm
+    against h = 0.05 nm, so the quadrature's trilinear error stays well under
+    1 % of the largest value."""
     import torch
-    prob, rho = P.config3(n=256)
+    prob, rho = P.config3(n=256, pattern="tube")
     radii = [0.5 * s.d for s in prob.species]
     rd = to_dev(rho)
     q = ev.sphere_quadrature(rd, radii, prob.h, 8, precision=FP64)
