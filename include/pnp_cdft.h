@@ -190,6 +190,31 @@ pnp_status pnp_cdft_mu_ex(pnp_ctx ctx, const pnp_grid* grid, int32_t S,
                           void* workspace, size_t workspace_bytes, void* stream);
 
 /*
+ * pnp_cdft_mu_ex without a workspace argument and without any allocation,
+ * for callers that cannot allocate device memory (tight serving loops,
+ * harnesses that forbid hipMalloc): the same evaluation, the same kernels and
+ * the same results bit for bit, with the workspace taken from one static
+ * device array of 64 MiB that each GPU the library runs on holds until the
+ * process ends (its address is looked up once per device by pnp_create).
+ * Arguments, outputs and errors as pnp_cdft_mu_ex, plus:
+ *   - PNP_E_NOMEM when pnp_workspace_bytes() of the call exceeds 64 MiB
+ *     (for example mixed precision up to 96^3 with S <= 4, FP64 up to 64^3
+ *     with S <= 8; the aperiodic mode needs the doubled grid's workspace);
+ *   - PNP_E_ARG on a stream that is capturing a graph (the argument records
+ *     are copied from host memory at call time), and nothing is enqueued;
+ *   - PNP_E_DEVICE when the array has no address on this device.
+ * Every call on one GPU shares that GPU's array, whichever context, stream or
+ * thread makes it: calls that overlap on one GPU race and give undefined
+ * results.  The array keeps the last call's contents; a call writes every
+ * part it reads (the status words are cleared by its first pass).  With
+ * PNP_FLAG_ASYNC the status words stay in the array and are not reported.
+ */
+pnp_status pnp_cdft_mu_ex_noalloc(pnp_ctx ctx, const pnp_grid* grid, int32_t S,
+                                  const pnp_species* species, const double* rho, double T,
+                                  const pnp_params* params, double* mu_ex, double* slotboom,
+                                  void* stream);
+
+/*
  * Excess free energies [k_B T] of the densities rho (Sec. 2.3), from one
  * per-term evaluation (the same operator as pnp_cdft_mu_ex):
  *   F_hs = h^3 sum_r Phi_hs(n(r))                          (Sec. 2.3.1)

@@ -30,7 +30,7 @@ EXPORTED = [
     "pnp_profile_select", "pnp_profile_read", "pnp_free_energy", "pnp_equilibrium", "pnp_bulk_mu_ex", "pnp_session_bytes", "pnp_pool_create", "pnp_pool_destroy",
     "pnp_pool_usage", "pnp_session_open", "pnp_session_step", "pnp_session_view", "pnp_session_close",
     "pnp_plan_create", "pnp_plan_launch", "pnp_plan_status", "pnp_plan_destroy", "pnp_pool_graphs",
-    "pnp_autotune", "pnp_tune_export", "pnp_tune_import", "pnp_sphere_quadrature",
+    "pnp_autotune", "pnp_tune_export", "pnp_tune_import", "pnp_sphere_quadrature", "pnp_cdft_mu_ex_noalloc",
 ]
 
 PASS_NAMES = ["tables", "z_fwd_rho", "y_fwd_rho", "x_fwd_weights", "y_inv_n", "z_deriv",
@@ -102,6 +102,8 @@ def load_library():
     lib.pnp_cdft_mu_ex.argtypes = [P, ctypes.POINTER(Grid), ctypes.c_int32, ctypes.POINTER(SpeciesC),
                                    P, ctypes.c_double, ctypes.POINTER(ParamsC), P, P, P,
                                    ctypes.c_size_t, P]
+    lib.pnp_cdft_mu_ex_noalloc.argtypes = [P, ctypes.POINTER(Grid), ctypes.c_int32, ctypes.POINTER(SpeciesC),
+                                           P, ctypes.c_double, ctypes.POINTER(ParamsC), P, P, P]
     lib.pnp_weighted_densities.argtypes = [P, ctypes.POINTER(Grid), ctypes.c_int32,
                                            ctypes.POINTER(SpeciesC), P, ctypes.POINTER(ParamsC), P,
                                            P, ctypes.c_size_t, P]
@@ -273,6 +275,18 @@ class Evaluator:
             ctypes.c_void_p(ws.data_ptr()), ctypes.c_size_t(ws.numel()), self._stream())
         self._check(st)
         return out, (slot if slotboom else None)
+
+    def mu_ex_noalloc(self, problem, rho, out, slot=None, per_term=False, flags=0, precision=None):
+        """pnp_cdft_mu_ex_noalloc: the evaluation into caller-given outputs with
+        the library's static scratch array as workspace (no allocation here or
+        in the library)."""
+        m = _Marshal(problem, per_term, flags, precision)
+        st = self.lib.pnp_cdft_mu_ex_noalloc(
+            self.ctx, ctypes.byref(m.grid), m.S, m.species, self._dev(rho, "rho"), m.T, ctypes.byref(m.params),
+            self._dev(out, "mu_ex"), self._dev(slot, "slotboom") if slot is not None else ctypes.c_void_p(0),
+            self._stream())
+        self._check(st)
+        return out, slot
 
     def free_energy(self, problem, rho, precision=None):
         """{"hs", "el", "sh", "total"} excess free energies [k_B T] and the

@@ -12,6 +12,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -38,7 +39,38 @@ struct pnp_ctx_s {
   bool capturing = false;  // a plan is being captured: no pass events
   // autotuned tile shapes: (precision, n, count class) -> narrow-pass mask
   std::map<uint64_t, uint32_t> tune;
+  // device address of this device's static scratch array (null if the
+  // lookup failed at creation)
+  void* scratch = nullptr;
 };
+
+// Scratch of the allocation-free evaluation (pnp_cdft_mu_ex_noalloc): one
+// static device array, which every GPU the library runs on holds from the
+// load of this code object until the process ends.  In host code `scratch`
+// names a host-side stand-in, not a device address; the device address of
+// each GPU's copy comes from hipGetSymbolAddress (pnp_create, once per
+// device) and only that address is ever handed to kernels or copies.
+constexpr size_t kScratchBytes = (size_t)64 << 20;
+__device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+std::mutex g_scratch_mu;
+std::map<int, void*> g_scratch_addr;  // device -> address of its scratch copy
+
+// The address of `scratch` on the current device (looked up once per device).
+void* scratch_address(int device) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  auto it = g_scratch_addr.find(device);
+  if (it != g_scratch_addr.end()) return it->second;
+  void* ptr = nullptr;
+  if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) {
+    (void)hipGetLastError();  // leave no sticky error behind
+    return nullptr;
+  }
+  g_scratch_addr[device] = ptr;
+  return ptr;
+}
+}  // namespace
 
 namespace {
 
@@ -578,6 +610,7 @@ pnp_status pnp_create(int device, pnp_ctx* out) {
     delete c;
     return PNP_E_DEVICE;
   }
+  c->scratch = scratch_address(device);  // with `device` current; null: the no-alloc call reports it
   *out = c;
   return PNP_OK;
 }
@@ -746,6 +779,30 @@ pnp_status pnp_cdft_mu_ex(pnp_ctx ctx, const pnp_grid* g, int32_t S, const pnp_s
   if (st != PNP_OK) return st;
   if (p->flags & PNP_FLAG_ASYNC) return PNP_OK;
   return read_status(ctx, w + L.status, s);
+}
+
+pnp_status pnp_cdft_mu_ex_noalloc(pnp_ctx ctx, const pnp_grid* g, int32_t S, const pnp_species* sp,
+                                  const double* rho, double T, const pnp_params* p, double* mu, double* slot,
+                                  void* stream) {
+  if (!ctx) return PNP_E_ARG;
+  if (!ctx->scratch) return fail(ctx, PNP_E_DEVICE, "the static scratch array has no device address on this device");
+  size_t need = 0;
+  pnp_status st = pnp_workspace_bytes(ctx, g, S, p, &need);
+  if (st != PNP_OK) return st;
+  if (need > kScratchBytes)
+    return fail(ctx, PNP_E_NOMEM, "this evaluation needs " + std::to_string(need) + " bytes of scratch; the static "
+                                  "scratch array holds " + std::to_string(kScratchBytes));
+  if (hipSetDevice(ctx->device) != hipSuccess) return device_check(ctx, "set device");
+  // argument records are copied from host memory at call time: a captured
+  // copy would read them again at every replay
+  hipStreamCaptureStatus capture = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing((hipStream_t)stream, &capture) != hipSuccess) return device_check(ctx, "capture query");
+  if (capture != hipStreamCaptureStatusNone)
+    return fail(ctx, PNP_E_ARG, "pnp_cdft_mu_ex_noalloc cannot be recorded into a graph");
+  // the evaluation of pnp_cdft_mu_ex with this device's scratch as workspace;
+  // every region it reads is written earlier in the same call (the status
+  // words are cleared by the first pass)
+  return pnp_cdft_mu_ex(ctx, g, S, sp, rho, T, p, mu, slot, ctx->scratch, kScratchBytes, stream);
 }
 
 pnp_status pnp_free_energy(pnp_ctx ctx, const pnp_grid* g, int32_t S, const pnp_species* sp, const double* rho,
