@@ -235,8 +235,67 @@ __device__ __forceinline__ cx<T> twiddle(const cx<T>* tw, int idx) {
   return FWD ? w : cconj<T>(w);
 }
 
-template <typename T, int N, int EPT, int R, int NS, bool FWD, class L>
-__device__ __forceinline__ void stockham_stage(cx<T>* v, int t, const cx<T>* tw, const L& lds) {
+// number of twiddles one thread applies in a full transform (stages after the first)
+constexpr int tw_count(int n, int ept) {
+  int c = 0;
+  for (int ns = 1; ns < n;) {
+    const int r = pick_radix(n / ns, ept);
+    if (ns > 1) c += (ept / r) * (r - 1);
+    ns *= r;
+  }
+  return c;
+}
+// index of the first twiddle of the stage that starts after radix product ns0
+constexpr int tw_offset(int n, int ept, int ns0) {
+  int c = 0;
+  for (int ns = 1; ns < ns0;) {
+    const int r = pick_radix(n / ns, ept);
+    if (ns > 1) c += (ept / r) * (r - 1);
+    ns *= r;
+  }
+  return c;
+}
+
+// The twiddles of one thread's share of a length-N transform, held in
+// registers (filled once from the LDS table, reused for every field the
+// thread transforms); forward values, conjugated for the inverse.
+template <typename T, int N, int EPT>
+struct TwReg {
+  static constexpr int count = tw_count(N, EPT);
+  cx<T> w[count > 0 ? count : 1];
+  template <int NS, int OFF>
+  __device__ __forceinline__ void fill(int t, const cx<T>* tab) {
+    if constexpr (NS < N) {
+      constexpr int R = pick_radix(N / NS, EPT);
+      constexpr int B = EPT / R, TPP = N / EPT;
+      if constexpr (NS > 1) {
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+          const int k = (t + TPP * b) % NS;
+#pragma unroll
+          for (int r = 1; r < R; ++r) w[OFF + b * (R - 1) + r - 1] = tab[k * r * (N / (NS * R))];
+        }
+        fill<NS * R, OFF + B * (R - 1)>(t, tab);
+      } else {
+        fill<NS * R, OFF>(t, tab);
+      }
+    }
+  }
+  __device__ __forceinline__ void load(int t, const cx<T>* tab) { fill<1, 0>(t, tab); }
+};
+
+template <typename T, int N, int EPT, int R, int NS, bool FWD>
+__device__ __forceinline__ cx<T> stage_tw(const cx<T>* tw, int b, int r, int k) {
+  return twiddle<T, N, FWD>(tw, k * r * (N / (NS * R)));
+}
+template <typename T, int N, int EPT, int R, int NS, bool FWD>
+__device__ __forceinline__ cx<T> stage_tw(const TwReg<T, N, EPT>& tw, int b, int r, int) {
+  const cx<T> w = tw.w[tw_offset(N, EPT, NS) + b * (R - 1) + r - 1];
+  return FWD ? w : cconj<T>(w);
+}
+
+template <typename T, int N, int EPT, int R, int NS, bool FWD, class TW, class L>
+__device__ __forceinline__ void stockham_stage(cx<T>* v, int t, const TW& tw, const L& lds) {
   constexpr int TPP = N / EPT;
   constexpr int B = EPT / R;
   static_assert(EPT % R == 0 && N % (NS * R) == 0, "bad radix plan");
@@ -252,7 +311,7 @@ __device__ __forceinline__ void stockham_stage(cx<T>* v, int t, const cx<T>* tw,
       const int k = j % NS;
 #pragma unroll
       for (int r = 1; r < R; ++r)
-        u[r] = cmul<T>(u[r], twiddle<T, N, FWD>(tw, k * r * (N / (NS * R))));
+        u[r] = cmul<T>(u[r], stage_tw<T, N, EPT, R, NS, FWD>(tw, b, r, k));
     }
     Dft<T, R, FWD>::run(u);
 #pragma unroll
@@ -276,8 +335,8 @@ __device__ __forceinline__ void stockham_stage(cx<T>* v, int t, const cx<T>* tw,
   }
 }
 
-template <typename T, int N, int EPT, int NS, bool FWD, class L>
-__device__ __forceinline__ void stockham_run(cx<T>* v, int t, const cx<T>* tw, const L& lds) {
+template <typename T, int N, int EPT, int NS, bool FWD, class TW, class L>
+__device__ __forceinline__ void stockham_run(cx<T>* v, int t, const TW& tw, const L& lds) {
   if constexpr (NS < N) {
     constexpr int R = pick_radix(N / NS, EPT);
     static_assert(R > 1, "unsupported length / elements-per-thread pair");
@@ -289,8 +348,8 @@ __device__ __forceinline__ void stockham_run(cx<T>* v, int t, const cx<T>* tw, c
 // Unnormalised DFT of one pencil held as v[m] = x[t + (N/EPT) m].
 // Every thread of the workgroup (or of the wavefront, for a wave-local LDS
 // view) must call this: it contains the exchange synchronisation.
-template <typename T, int N, int EPT, bool FWD, class L>
-__device__ __forceinline__ void fft_pencil(cx<T>* v, int t, const cx<T>* tw, const L& lds) {
+template <typename T, int N, int EPT, bool FWD, class TW, class L>
+__device__ __forceinline__ void fft_pencil(cx<T>* v, int t, const TW& tw, const L& lds) {
   stockham_run<T, N, EPT, 1, FWD>(v, t, tw, lds);
 }
 

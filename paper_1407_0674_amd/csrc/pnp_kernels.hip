@@ -555,6 +555,52 @@ __device__ __forceinline__ void c2r_combine(cx<T>* v, const cx<T>* xk0, const cx
   }
 }
 
+// c2r_combine with the lane's W^k in registers (twk[m] = W^(t + TZ m))
+template <typename T, int N, int TZ, int EZ>
+__device__ __forceinline__ void c2r_combine_r(cx<T>* v, const cx<T>* xk0, const cx<T>* xm0, int t,
+                                              const cx<T>* twk, bool zmul = false) {
+  constexpr int H = N / 2;
+#pragma unroll
+  for (int m = 0; m < EZ; ++m) {
+    const int k = t + TZ * m;
+    cx<T> xk = xk0[m], xm = xm0[m];
+    if (k == 0) { xk.y = (T)0; xm.y = (T)0; }
+    if (zmul) {
+      xk = cscale<T>(cmuli<T>(xk), (T)k);
+      xm = k == 0 ? mk<T>((T)0, (T)0) : cscale<T>(cmuli<T>(xm), (T)(H - k));
+    }
+    const cx<T> cm = cconj<T>(xm);
+    const cx<T> s = cadd<T>(xk, cm);
+    const cx<T> d = csub<T>(xk, cm);
+    v[m] = cadd<T>(s, cmuli<T>(cmulc<T>(d, twk[m])));
+  }
+}
+
+// r2c_post with the lane's W^k in registers
+template <typename T, int N, int TZ, int EZ, typename BF>
+__device__ __forceinline__ void r2c_post_r(cx<T>* v, int t, const cx<T>* twk, cx<T>* row, const BF& f,
+                                           uint32_t soff, uint32_t row_id, bool zmul = false) {
+  constexpr int H = N / 2;
+  constexpr uint32_t cs = sizeof(cx<T>);
+#pragma unroll
+  for (int m = 0; m < EZ; ++m) row[t + TZ * m] = v[m];
+  lds_sync<row_in_wave<TZ>()>();
+#pragma unroll
+  for (int m = 0; m < EZ; ++m) {
+    const int k = t + TZ * m;
+    const cx<T> c = v[m];
+    const cx<T> cm = cconj<T>(row[k == 0 ? 0 : H - k]);
+    const cx<T> e = mk<T>((T)0.5 * (c.x + cm.x), (T)0.5 * (c.y + cm.y));
+    const cx<T> d = mk<T>((T)0.5 * (c.x - cm.x), (T)0.5 * (c.y - cm.y));
+    cx<T> x = cadd<T>(e, cmul<T>(twk[m], cmulmi<T>(d)));
+    if (zmul) x = cscale<T>(cmuli<T>(x), (T)k);
+    f.template st<cx<T>>(x, (row_id * H + k) * cs, soff);
+    if (k == 0) f.template st<cx<T>>(zmul ? mk<T>((T)0, (T)0) : mk<T>(c.x - c.y, (T)0),
+                            ((uint32_t)(N * N * H) + row_id) * cs, soff);
+  }
+  lds_sync<row_in_wave<TZ>()>();
+}
+
 // 1 / x in FP64: hardware reciprocal estimate refined by two Newton steps
 // (error within an ulp of the quotient)
 __device__ __forceinline__ double recip_f64(double x) {
@@ -616,6 +662,8 @@ __global__ void __launch_bounds__((GeoD<T, N, EZD, V>::RDD * GeoD<T, N, EZD, V>:
   const BufN<N> B = make_buf<stream_policy<N>()>(a.specB, spec_bytes<T>(a, kFields));
   const uint32_t fbytes = __builtin_amdgcn_readfirstlane((uint32_t)(a.fstride * sizeof(cx<T>)));
   cx<T> val[kFields * EZ];
+  TwReg<T, H, EZ> twr;  // the FFT twiddles of this lane, for all twenty transforms
+  cx<T> twk[EZ];        // the r2c / c2r twiddles W^k of this lane's elements
   {
     // the raw values of field q + 1 are in flight while field q is transformed;
     // those of field 0 while the twiddle tables are built
@@ -624,6 +672,9 @@ __global__ void __launch_bounds__((GeoD<T, N, EZD, V>::RDD * GeoD<T, N, EZD, V>:
     init_twiddles<T, H>(twH);
     init_twiddles<T, N>(twN);
     __syncthreads();
+    twr.load(t, twH);
+#pragma unroll
+    for (int m = 0; m < EZ; ++m) twk[m] = twN[t + TZ * m];
 #pragma unroll
     for (int q = 0; q < kFields; ++q) {
       cx<T>* kc = (q & 1) ? k1 : k0;
@@ -632,8 +683,8 @@ __global__ void __launch_bounds__((GeoD<T, N, EZD, V>::RDD * GeoD<T, N, EZD, V>:
       cx<T>* mn = (q & 1) ? m0 : m1;
       if (q + 1 < kFields) c2r_load<T, N, TZ, EZ>(kn, mn, t, B, (uint32_t)(q + 1) * fbytes, row);
       // the z component of each vector density is i s_z Q_b, formed here
-      c2r_combine<T, N, TZ, EZ>(val + q * EZ, kc, mc, t, twN, q == kSlotZ || q == kSlotZ + kVecStride);
-      fft_pencil<T, N / 2, EZ, false>(val + q * EZ, t, twH, lp);
+      c2r_combine_r<T, N, TZ, EZ>(val + q * EZ, kc, mc, t, twk, q == kSlotZ || q == kSlotZ + kVecStride);
+      fft_pencil<T, N / 2, EZ, false>(val + q * EZ, t, twr, lp);
     }
   }
   if (a.ext_n != 0) {
@@ -713,9 +764,9 @@ __global__ void __launch_bounds__((GeoD<T, N, EZD, V>::RDD * GeoD<T, N, EZD, V>:
   }
 #pragma unroll
   for (int q = 0; q < kFields; ++q) {
-    fft_pencil<T, N / 2, EZ, true>(val + q * EZ, t, twH, lp);
+    fft_pencil<T, N / 2, EZ, true>(val + q * EZ, t, twr, lp);
     // the z components of the vector derivatives leave as i s_z F_z
-    r2c_post<T, N, TZ, EZ>(val + q * EZ, t, twN, lrow, B, q * fbytes, row, q == kSlotZ || q == kSlotZ + kVecStride);
+    r2c_post_r<T, N, TZ, EZ>(val + q * EZ, t, twk, lrow, B, q * fbytes, row, q == kSlotZ || q == kSlotZ + kVecStride);
     __builtin_amdgcn_sched_barrier(0);
   }
   if (bad) raise_status(a.status, bad, badidx);
@@ -1222,31 +1273,27 @@ __global__ void __launch_bounds__((PX * (N / EX)))
       }
     }
   } else if (pair_on) {
-    // G_{0..3, j} of row [m][j][.]: one gather per element, prefetched with the pencil
-    v4<T> g0[EX], g1[EX];
-#pragma unroll
-    for (int m = 0; m < EX; ++m) g0[m] = pt.template ld<v4<T>>((uint32_t)(mm[m] * S * a.Sp) * (uint32_t)sizeof(T));
+    // G_{0..3, j} of row [m][j][.]: one gather per element, issued before the
+    // transform of the same species' pencil (its latency hides behind it)
+    v4<T> g[EX];
 #pragma unroll
     for (int j = 0; j < CH; ++j) {
       if (j < S) {  // uniform
         cx<T>* cur = (j & 1) ? b1 : b0;
         cx<T>* nxt = (j & 1) ? b0 : b1;
-        v4<T>* gc = (j & 1) ? g1 : g0;
-        v4<T>* gn = (j & 1) ? g0 : g1;
         if (j + 1 < S) {
 #pragma unroll
           for (int m = 0; m < EX; ++m) nxt[m] = A.template ldnt<cx<T>>(xa.vo, (uint32_t)(j + 1) * fbytes + m * xa.mstride);
-#pragma unroll
-          for (int m = 0; m < EX; ++m)
-            gn[m] = pt.template ld<v4<T>>((uint32_t)((mm[m] * S + j + 1) * a.Sp) * (uint32_t)sizeof(T));
         }
+#pragma unroll
+        for (int m = 0; m < EX; ++m) g[m] = pt.template ld<v4<T>>((uint32_t)((mm[m] * S + j) * a.Sp) * (uint32_t)sizeof(T));
         fft_pencil<T, N, EX, true>(cur, t, tw, lp);
 #pragma unroll
         for (int m = 0; m < EX; ++m) {
-          cfma<T>(out[0][m], cur[m], gc[m].x);
-          if constexpr (CH > 1) cfma<T>(out[1][m], cur[m], gc[m].y);
-          if constexpr (CH > 2) cfma<T>(out[2][m], cur[m], gc[m].z);
-          if constexpr (CH > 3) cfma<T>(out[3][m], cur[m], gc[m].w);
+          cfma<T>(out[0][m], cur[m], g[m].x);
+          if constexpr (CH > 1) cfma<T>(out[1][m], cur[m], g[m].y);
+          if constexpr (CH > 2) cfma<T>(out[2][m], cur[m], g[m].z);
+          if constexpr (CH > 3) cfma<T>(out[3][m], cur[m], g[m].w);
         }
       }
     }

@@ -227,13 +227,15 @@ def config3(seed: int = BASE_SEED + 3, n: int = 256, eta_max: float = 0.45,
 
 
 def random_instance(rng, n_choices, precision: int = MIXED, h: float = 0.05,
-                    with_rho: bool = True, profile: bool = False):
+                    with_rho: bool = True, profile: bool = False, pattern: str = "tube"):
     """One uneven instance of the batched / served mixes: n from n_choices,
     T ~ U(250, 350) K, S ~ U{2,3,4}, d ~ U(0.15, 0.45) nm, bulk ~ U(0.1, 2.0) M,
     z ~ U{+-1, +-2}, channel pattern, HS + EC + SW (0.3 eV, 0.3 nm wells).
     With with_rho=False only the description is drawn (rho is None); with
     profile=True the second value is the (x, z) profile [S][n][n] instead of
-    the full array (the same draws: broadcasting it along y gives rho)."""
+    the full array (the same draws: broadcasting it along y gives rho).
+    pattern "3d": the channel with noise and alternating-sign components
+    (channel_3d) instead of the plain tube (not with profile=True)."""
     n = int(rng.choice(n_choices))
     T = float(rng.uniform(250.0, 350.0))
     S = int(rng.integers(2, 5))
@@ -248,6 +250,8 @@ def random_instance(rng, n_choices, precision: int = MIXED, h: float = 0.05,
         return prob, None
     if profile:
         return prob, gaussian_channel_profile(rng, n, h, [s.rho_bulk for s in sp], list(q), 0.5)
+    if pattern == "3d":
+        return prob, channel_3d(rng, n, h, [s.rho_bulk for s in sp], list(q), 0.5)
     return prob, gaussian_channel(rng, n, h, [s.rho_bulk for s in sp], list(q), 0.5)
 
 
