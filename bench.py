@@ -187,6 +187,49 @@ def cpu_all_cores(n=96):
                                        f"mean per evaluation {sum(per) / len(per):.2f} s"}
 
 
+def _cpu_direct_worker(n):
+    """One direct O(N^2) oracle evaluation at n^3 in a fresh process; wall time."""
+    import sys as _sys
+    if ROOT not in _sys.path:
+        _sys.path.insert(0, ROOT)
+    import oracle
+    import pnp_inputs as P
+    prob, rho = P.config3(n=n, precision=0)
+    t0 = time.perf_counter()
+    oracle.mu_ex(prob, rho, "direct")
+    return time.perf_counter() - t0
+
+
+def bench_cpu():
+    """The CPU baselines of the method's scope on the host (one JSON line):
+    the direct O(N^2) oracle at 16^3, 24^3, 32^3 and the numpy-FFT route at
+    64^3 and 256^3, each on one thread and on every core (one process per
+    core, independent evaluations: the oracle's numpy kernels run on one
+    thread per process).  The benchmark recipe (three-species channel,
+    packing 0.45, all terms) throughout."""
+    import multiprocessing as mp
+    import pnp_inputs as P
+    cores = min(len(os.sched_getaffinity(0)), 32)
+    out = {"host": host_info(), "results": []}
+    ctx = mp.get_context("spawn")
+    with ctx.Pool(cores) as pool:
+        pool.map(_cpu_worker, [16] * cores)  # start-up, not timed
+        for route, n, conc in (("direct", 16, cores), ("direct", 24, cores), ("direct", 32, 1),
+                               ("fft", 64, cores), ("fft", 256, 1), ("fft", 256, min(cores, 8))):
+            work = _cpu_direct_worker if route == "direct" else _cpu_worker
+            t0 = time.perf_counter()
+            if conc == 1:
+                per = [work(n)]
+            else:
+                per = pool.map(work, [n] * conc)
+            wall = time.perf_counter() - t0
+            out["results"].append({"route": route, "n": n, "processes": conc, "wall_s": wall,
+                                   "mean_eval_s": sum(per) / len(per),
+                                   "grid_pt_species_per_s": conc * n ** 3 * 3 / wall})
+            print(json.dumps({"progress": "cpu", **out["results"][-1]}), file=sys.stderr, flush=True)
+    return {"metric": "CPU oracle grid-pts*species/s (baselines)", "unit": "grid-pt*species/s", "cpu": out}
+
+
 def cpu_direct(n=16):
     """The direct O(N^2) oracle on the benchmark recipe at n^3, one thread."""
     import pnp_inputs as P
@@ -632,6 +675,10 @@ def main():
         print(json.dumps(bench_serve(ev, args.duration, args.rate)), flush=True)
         ev.close()
         return
+    if args.workload == "cpu":
+        print(json.dumps(bench_cpu()), flush=True)
+        ev.close()
+        return
     if args.workload == "aperiodic":
         print(json.dumps(bench_aperiodic(ev, args.steps, args.warmup)), flush=True)
         ev.close()
@@ -732,7 +779,7 @@ def main():
         cpu["host"] = host_info()
         if n > 16:
             cpu["direct_route_16"] = cpu_direct(16)
-            cpu["all_cores"] = cpu_all_cores(96)
+            cpu["all_cores"] = cpu_all_cores(128)
         print(json.dumps({"progress": "cpu baseline done"}), file=sys.stderr, flush=True)
 
     value = n3 * S / (ms / 1e3)

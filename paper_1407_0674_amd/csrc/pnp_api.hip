@@ -42,6 +42,11 @@ struct pnp_ctx_s {
   // device address of this device's static scratch array (null if the
   // lookup failed at creation)
   void* scratch = nullptr;
+  // side stream (default priority) for the Nyquist-plane tiles of the y and
+  // x passes, with its fork and join events; created on first use
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  bool side_failed = false;
 };
 
 // Scratch of the allocation-free evaluation (pnp_cdft_mu_ex_noalloc): one
@@ -429,23 +434,81 @@ inline SpeciesMix mix_of(int S) {
   return m;
 }
 
+// Between two z passes the y and x passes of the Nyquist plane (kz = n/2)
+// touch only that plane, so for large grids its tiles run as separate
+// launches on the context's side stream: forked from the caller's stream
+// after a z pass and joined back before the next one.  On large grids the
+// main-array tiles of a y or x pass are whole rounds of the 256 compute
+// units (2048 workgroups); launched together, the 16 Nyquist tiles would
+// add a last, nearly empty round (measured at 256^3: the y and x passes
+// 6-10 % longer), while on the side stream they run in the idle slots of
+// the main launches.  The split is not used while a plan is being captured
+// (every tile then runs on the capturing stream).
+constexpr int kSplitMinN = 192;
+
+struct Split {
+  pnp_ctx c;
+  hipStream_t s;
+  bool on = false;
+  Split(pnp_ctx ctx, hipStream_t stream, int n) : c(ctx), s(stream) {
+    if (n < kSplitMinN || !c || c->capturing || c->side_failed) return;
+    if (!c->side) {
+      if (hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess ||
+          hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
+          hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess) {
+        (void)hipGetLastError();
+        c->side_failed = true;  // every tile stays on the caller's stream
+        return;
+      }
+    }
+    on = true;
+  }
+  // the side stream waits for all work enqueued on the caller's stream so far
+  void fork() {
+    if (!on) return;
+    (void)hipEventRecord(c->ev_fork, s);
+    (void)hipStreamWaitEvent(c->side, c->ev_fork, 0);
+  }
+  // the caller's stream waits for all work enqueued on the side stream so far
+  void join() {
+    if (!on) return;
+    (void)hipEventRecord(c->ev_join, c->side);
+    (void)hipStreamWaitEvent(s, c->ev_join, 0);
+  }
+  // stream of the Nyquist tiles, and the parts of the main launch
+  int main_part() const { return on ? kPartMain : kPartAll; }
+  hipStream_t nyq() const { return c->side; }
+};
+
 // ea: device arg tables; fmask: the hard-sphere functionals among the
 // instances (1 Rosenfeld, 2 White Bear, 0 no HS term); sm: their species
-// counts.
+// counts; n: the grid size of the launch list.
 void run_sequence(pnp_ctx c, const OpsSel& op, const EvalArgs* ea, const TableArgs* ta, int count, int M,
-                  int fmask, const SpeciesMix& sm, hipStream_t s) {
+                  int fmask, const SpeciesMix& sm, hipStream_t s, int n) {
   PassTimer pt{c, s};
+  Split sp(c, s, n);
+  const int mp = sp.main_part();
   pt.begin(0); op.at(0)->tables(ta, count, M, sm.maxS, s); pt.end();
   pt.begin(1); op.at(1)->zfwd(ea, count, s); pt.end();
-  pt.begin(2); op.at(2)->ystep(ea, count, 0, -1, true, s); pt.end();
+  sp.fork();
+  pt.begin(2); op.at(2)->ystep(ea, count, 0, -1, true, mp, s); pt.end();
+  if (sp.on) op.at(2)->ystep(ea, count, 0, -1, true, kPartNyquist, sp.nyq());
   if (fmask) {
-    pt.begin(3); op.at(3)->xfwd(ea, count, s); pt.end();
-    pt.begin(4); op.at(4)->ystep(ea, count, 1, kVecMode, false, s); pt.end();
+    pt.begin(3); op.at(3)->xfwd(ea, count, mp, s); pt.end();
+    if (sp.on) op.at(3)->xfwd(ea, count, kPartNyquist, sp.nyq());
+    pt.begin(4); op.at(4)->ystep(ea, count, 1, kVecMode, false, mp, s); pt.end();
+    if (sp.on) op.at(4)->ystep(ea, count, 1, kVecMode, false, kPartNyquist, sp.nyq());
+    sp.join();
     pt.begin(5); op.at(5)->zderiv(ea, count, false, fmask, s); pt.end();
-    pt.begin(6); op.at(6)->ystep(ea, count, 1, kVecMode, true, s); pt.end();
+    sp.fork();
+    pt.begin(6); op.at(6)->ystep(ea, count, 1, kVecMode, true, mp, s); pt.end();
+    if (sp.on) op.at(6)->ystep(ea, count, 1, kVecMode, true, kPartNyquist, sp.nyq());
   }
-  pt.begin(7); op.at(7)->xback(ea, count, sm.small, sm.maxS > 4, s); pt.end();
-  pt.begin(8); op.at(8)->ystep(ea, count, 2, -1, false, s); pt.end();
+  pt.begin(7); op.at(7)->xback(ea, count, sm.small, sm.maxS > 4, mp, s); pt.end();
+  if (sp.on) op.at(7)->xback(ea, count, sm.small, sm.maxS > 4, kPartNyquist, sp.nyq());
+  pt.begin(8); op.at(8)->ystep(ea, count, 2, -1, false, mp, s); pt.end();
+  if (sp.on) op.at(8)->ystep(ea, count, 2, -1, false, kPartNyquist, sp.nyq());
+  sp.join();
   pt.begin(9); op.at(9)->zinv(ea, count, 2, s); pt.end();
 }
 
@@ -576,18 +639,31 @@ static pnp_status enqueue_per_term(pnp_ctx ctx, const Derived& d, const pnp_grid
   op->tables(dta, 1, L.M, S, s);
   if (d.sw) op->tables(dta + 1, 1, L.M, S, s);
   pt.end();
+  Split sq(ctx, s, d.n);
+  const int mp = sq.main_part();
   pt.begin(1); op->zfwd(dea, 1, s); pt.end();
-  pt.begin(2); op->ystep(dea, 1, 0, -1, true, s); pt.end();
+  sq.fork();
+  pt.begin(2); op->ystep(dea, 1, 0, -1, true, mp, s); pt.end();
+  if (sq.on) op->ystep(dea, 1, 0, -1, true, kPartNyquist, sq.nyq());
   if (d.hs) {
-    pt.begin(3); op->xfwd(dea, 1, s); pt.end();
-    pt.begin(4); op->ystep(dea, 1, 1, kVecMode, false, s); pt.end();
+    pt.begin(3); op->xfwd(dea, 1, mp, s); pt.end();
+    if (sq.on) op->xfwd(dea, 1, kPartNyquist, sq.nyq());
+    pt.begin(4); op->ystep(dea, 1, 1, kVecMode, false, mp, s); pt.end();
+    if (sq.on) op->ystep(dea, 1, 1, kVecMode, false, kPartNyquist, sq.nyq());
+    sq.join();
     pt.begin(5); op->zderiv(dea, 1, phi_part != nullptr, hs_mask(d), s); pt.end();
-    pt.begin(6); op->ystep(dea, 1, 1, kVecMode, true, s); pt.end();
+    sq.fork();
+    pt.begin(6); op->ystep(dea, 1, 1, kVecMode, true, mp, s); pt.end();
+    if (sq.on) op->ystep(dea, 1, 1, kVecMode, true, kPartNyquist, sq.nyq());
   }
   for (int k = 1; k < 4; ++k) {
-    pt.begin(7); op->xback(dea + k, 1, S <= 4 ? S : 0, S > 4, s); pt.end();
-    pt.begin(8); op->ystep(dea + k, 1, 2, -1, false, s); pt.end();
+    pt.begin(7); op->xback(dea + k, 1, S <= 4 ? S : 0, S > 4, mp, s); pt.end();
+    if (sq.on) op->xback(dea + k, 1, S <= 4 ? S : 0, S > 4, kPartNyquist, sq.nyq());
+    pt.begin(8); op->ystep(dea + k, 1, 2, -1, false, mp, s); pt.end();
+    if (sq.on) op->ystep(dea + k, 1, 2, -1, false, kPartNyquist, sq.nyq());
+    sq.join();
     pt.begin(9); op->zinv(dea + k, 1, 2, s); pt.end();
+    if (k < 3) sq.fork();  // the next term's Nyquist tiles rewrite what this z pass read
   }
   const long sn3 = (long)S * n3;
   const int blocks = (int)std::min<long>((sn3 + 255) / 256, 4096);
@@ -622,6 +698,9 @@ void pnp_destroy(pnp_ctx c) {
     hipDeviceSynchronize();
     hipFree(c->arena);
   }
+  if (c->side) (void)hipStreamDestroy(c->side);
+  if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
+  if (c->ev_join) (void)hipEventDestroy(c->ev_join);
   for (auto& o : c->ev_open) { hipEventDestroy(o.second.first); hipEventDestroy(o.second.second); }
   for (hipEvent_t e : c->ev_pool) hipEventDestroy(e);
   delete c;
@@ -710,7 +789,7 @@ static pnp_status enqueue_aperiodic(pnp_ctx ctx, const Derived& d, const pnp_gri
     const TableArgs* dta = (const TableArgs*)upload(ctx, &ta, sizeof(ta), s);
     const EvalArgs* dea = (const EvalArgs*)upload(ctx, &ea, sizeof(ea), s);
     if (!dta || !dea) return device_check(ctx, "argument upload");
-    run_sequence(ctx, ops, dea, dta, 1, L.M, 0, mix_of(S), s);
+    run_sequence(ctx, ops, dea, dta, 1, L.M, 0, mix_of(S), s, d.n);
   }
   // the extended densities (their status word starts clean here)
   if (!p->per_term) {
@@ -723,7 +802,7 @@ static pnp_status enqueue_aperiodic(pnp_ctx ctx, const Derived& d, const pnp_gri
     const TableArgs* dta = (const TableArgs*)upload(ctx, &ta, sizeof(ta), s);
     const EvalArgs* dea = (const EvalArgs*)upload(ctx, &ea, sizeof(ea), s);
     if (!dta || !dea) return device_check(ctx, "argument upload");
-    run_sequence(ctx, ops, dea, dta, 1, L.M, hs_mask(d), mix_of(S), s);
+    run_sequence(ctx, ops, dea, dta, 1, L.M, hs_mask(d), mix_of(S), s, d.n);
   } else {
     const pnp_status st = enqueue_per_term(ctx, d, g, sp, rho, p, L, w, muA, nullptr, nullptr, s);
     if (st != PNP_OK) return st;
@@ -770,7 +849,7 @@ pnp_status pnp_cdft_mu_ex(pnp_ctx ctx, const pnp_grid* g, int32_t S, const pnp_s
     const TableArgs* dta = (const TableArgs*)upload(ctx, &ta, sizeof(ta), s);
     const EvalArgs* dea = (const EvalArgs*)upload(ctx, &ea, sizeof(ea), s);
     if (!dta || !dea) return device_check(ctx, "argument upload");
-    run_sequence(ctx, select_ops(ctx, d.precision, d.n, 1), dea, dta, 1, L.M, hs_mask(d), mix_of(S), s);
+    run_sequence(ctx, select_ops(ctx, d.precision, d.n, 1), dea, dta, 1, L.M, hs_mask(d), mix_of(S), s, d.n);
   } else {
     st = enqueue_per_term(ctx, d, g, sp, rho, p, L, w, mu, slot, nullptr, s);
     if (st != PNP_OK) return st;
@@ -891,7 +970,7 @@ pnp_status pnp_equilibrium(pnp_ctx ctx, const pnp_grid* g, int32_t S, const pnp_
   *iters = 0;
   *residual = INFINITY;
   for (int it = 1; it <= max_iter; ++it) {
-    run_sequence(ctx, select_ops(ctx, d.precision, d.n, 1), dea, dta, 1, L.M, hs_mask(d), mix_of(S), s);
+    run_sequence(ctx, select_ops(ctx, d.precision, d.n, 1), dea, dta, 1, L.M, hs_mask(d), mix_of(S), s, d.n);
     if (hipMemsetAsync(res, 0, sizeof(unsigned long long), s) != hipSuccess) return device_check(ctx, "reset");
     hipLaunchKernelGGL(k_picard, dim3(blocks), dim3(256), 0, s, rho, (const double*)mu, beta_v, n3, (int)S, drb,
                        lambda, res, fixed);
@@ -944,9 +1023,9 @@ pnp_status pnp_weighted_densities(pnp_ctx ctx, const pnp_grid* g, int32_t S, con
   if (!dta || !dea) return device_check(ctx, "argument upload");
   op->tables(dta, 1, L.M, S, s);
   op->zfwd(dea, 1, s);
-  op->ystep(dea, 1, 0, -1, true, s);
-  op->xfwd(dea, 1, s);
-  op->ystep(dea, 1, 1, kVecMode, false, s);
+  op->ystep(dea, 1, 0, -1, true, kPartAll, s);
+  op->xfwd(dea, 1, kPartAll, s);
+  op->ystep(dea, 1, 1, kVecMode, false, kPartAll, s);
   op->zinv(dea, 1, 1, s);
   st = device_check(ctx, "launch");
   if (st != PNP_OK) return st;
@@ -1030,7 +1109,7 @@ pnp_status pnp_batch_mu_ex(pnp_ctx ctx, int32_t count, pnp_request* reqs, void* 
     const TableArgs* dta = (const TableArgs*)upload(ctx, g.ta.data(), sizeof(TableArgs) * cnt, s);
     const EvalArgs* dea = (const EvalArgs*)upload(ctx, g.ea.data(), sizeof(EvalArgs) * cnt, s);
     if (!dta || !dea) return device_check(ctx, "argument upload");
-    run_sequence(ctx, select_ops(ctx, g.precision, g.n, cnt), dea, dta, cnt, g.M, g.fmask, g.mix, s);
+    run_sequence(ctx, select_ops(ctx, g.precision, g.n, cnt), dea, dta, cnt, g.M, g.fmask, g.mix, s, g.n);
   }
   pnp_status st = device_check(ctx, "batch launch");
   if (st != PNP_OK) return st;
@@ -1125,7 +1204,7 @@ pnp_status pnp_plan_create(pnp_ctx ctx, int32_t count, pnp_request* reqs, const 
     for (size_t k = 0; k < groups.size(); ++k) {
       const Group& g = groups[k];
       run_sequence(ctx, select_ops(ctx, g.precision, g.n, (int)g.ids.size()), (const EvalArgs*)(blk + ea_off[k]),
-                   (const TableArgs*)(blk + ta_off[k]), (int)g.ids.size(), g.M, g.fmask, g.mix, cs);
+                   (const TableArgs*)(blk + ta_off[k]), (int)g.ids.size(), g.M, g.fmask, g.mix, cs, g.n);
     }
     if (relax)
       for (int r = 0; r < count; ++r) {
@@ -1216,7 +1295,7 @@ pnp_status pnp_autotune(pnp_ctx ctx, int32_t count, pnp_request* reqs, int32_t r
       for (int r = 0; r <= reps && st == PNP_OK; ++r)  // the first round warms up and is not counted
         for (int v = 0; v < 2 && st == PNP_OK; ++v) {
           sel.mask = v ? ~0u : 0u;
-          run_sequence(ctx, sel, dea, dta, cnt, g.M, g.fmask, g.mix, s);
+          run_sequence(ctx, sel, dea, dta, cnt, g.M, g.fmask, g.mix, s, g.n);
           double ms[PNP_NUM_PASSES];
           st = pnp_profile_read(ctx, ms, nullptr, PNP_NUM_PASSES, 1);
           if (r > 0)
@@ -1324,13 +1403,13 @@ pnp_status pnp_debug_rfft3(pnp_ctx ctx, const pnp_grid* g, int32_t precision, in
   if (!dea) return device_check(ctx, "argument upload");
   if (!inverse) {
     op->zfwd(dea, 1, s);
-    op->ystep(dea, 1, 0, -1, true, s);
+    op->ystep(dea, 1, 0, -1, true, kPartAll, s);
     op->xplain(dea, 1, count, true, s);
     op->xport(dea, count, out, 1, s);
   } else {
     op->xport(dea, count, (double*)in, 0, s);
     op->xplain(dea, 1, count, false, s);
-    op->ystep(dea, 1, 0, -1, false, s);
+    op->ystep(dea, 1, 0, -1, false, kPartAll, s);
     op->zinv(dea, 1, 0, s);
   }
   pnp_status st = device_check(ctx, "launch");

@@ -182,6 +182,20 @@ __device__ __forceinline__ int inst_of(int tiles, int& tile) {
   return b / tiles;
 }
 
+// Launch parts of the y and x passes: the tiles of the main array
+// (kz < n/2) and those of the Nyquist plane (kz = n/2) are independent
+// between two z passes, so they may run as separate launches.
+enum : int { kPartAll = 0, kPartMain = 1, kPartNyquist = 2 };
+
+// instance and tile of this block for a launch of `part` over instances with
+// `main` main-array tiles and `nyq` Nyquist-plane tiles each
+__device__ __forceinline__ int inst_of_part(int main, int nyq, int part, int& tile) {
+  const int per = part == kPartAll ? main + nyq : part == kPartMain ? main : nyq;
+  const int b = blockIdx.x;
+  tile = b % per + (part == kPartNyquist ? main : 0);
+  return b / per;
+}
+
 // Sum of one double per thread over the workgroup, in a fixed order (the
 // result is the same on every run); valid in thread 0.  red: LDS scratch of
 // one double per wavefront.
@@ -799,13 +813,13 @@ __device__ __forceinline__ void mul_isy(cx<T>* v, int t) {
 
 template <typename T, int N, bool FWD, int V = 0>
 __global__ void __launch_bounds__((Geo<T, N, V>::PY * Geo<T, N, V>::TY))
-    k_ystep(const EvalArgs* __restrict__ args, int sel, int nf_code) {
+    k_ystep(const EvalArgs* __restrict__ args, int sel, int nf_code, int part) {
   using G = Geo<T, N, V>;
   constexpr int H = G::H, TY = G::TY, EY = G::EY, PY = G::PY;
   __shared__ cx<T> tw[N];
   __shared__ cx<T> xch[PY * N];
   int tile;
-  const EvalArgs& a = args[inst_of(G::tiles_y, tile)];
+  const EvalArgs& a = args[inst_of_part((N * H) / PY, N / PY, part, tile)];
   if (sel == 1 && !a.hs_on) return;  // uniform per block
   init_twiddles<T, N>(tw);
   __syncthreads();
@@ -1039,12 +1053,12 @@ struct XAddr {
 // species i + 1 are in flight while species i is transformed.
 template <typename T, int N, int EX = Geo<T, N>::EX, int PX = Geo<T, N>::PX>
 __global__ void __launch_bounds__((PX * (N / EX)))
-    k_xfwd(const EvalArgs* __restrict__ args) {
+    k_xfwd(const EvalArgs* __restrict__ args, int part) {
   constexpr int TX = N / EX;
   __shared__ cx<T> tw[N];
   __shared__ cx<T> xch[PX * N];
   int tile;
-  const EvalArgs& a = args[inst_of(x_tiles<N, PX>(), tile)];
+  const EvalArgs& a = args[inst_of_part((N * (N / 2)) / PX, N / PX, part, tile)];
   if (!a.hs_on) return;  // uniform per block
   const int p = threadIdx.x % PX, t = threadIdx.x / PX;
   const XPencil<N, PX> pc(tile, p);
@@ -1149,13 +1163,13 @@ __global__ void __launch_bounds__((PX * (N / EX)))
 // same launch list and are skipped here.
 template <typename T, int N, int CH, int EX = Geo<T, N>::EX, int PX = Geo<T, N>::PX>
 __global__ void __launch_bounds__((PX * (N / EX)))
-    k_xback(const EvalArgs* __restrict__ args) {
+    k_xback(const EvalArgs* __restrict__ args, int part) {
   static_assert(CH >= 1 && CH <= 4, "output chunk");
   constexpr int TX = N / EX;
   __shared__ cx<T> tw[N];
   __shared__ cx<T> xch[PX * N];
   int tile;
-  const EvalArgs& a = args[inst_of(x_tiles<N, PX>(), tile)];
+  const EvalArgs& a = args[inst_of_part((N * (N / 2)) / PX, N / PX, part, tile)];
   if (a.S > CH) return;  // uniform per block
   const int p = threadIdx.x % PX, t = threadIdx.x / PX;
   const XPencil<N, PX> pc(tile, p);
@@ -1202,6 +1216,10 @@ __global__ void __launch_bounds__((PX * (N / EX)))
         const int f1 = back_field(q + 1);
 #pragma unroll
         for (int m = 0; m < EX; ++m) nxt[m] = B.template ldnt<cx<T>>(xa.vo, (uint32_t)f1 * fbytes + m * xa.mstride);
+      } else if (pair_on) {
+        // the first density pencil is in flight during the last transform and the fold
+#pragma unroll
+        for (int m = 0; m < EX; ++m) nxt[m] = A.template ldnt<cx<T>>(xa.vo, m * xa.mstride);
       }
       fft_pencil<T, N, EX, true>(cur, t, tw, lp);
       const int f = back_field(q);
@@ -1245,10 +1263,10 @@ __global__ void __launch_bounds__((PX * (N / EX)))
 #pragma unroll
       for (int m = 0; m < EX; ++m) out[c][m] = mk<T>((T)0, (T)0);
   }
-  if (pair_on && hs_on) {  // the density stream starts in b0 (already there without HS)
-#pragma unroll
-    for (int m = 0; m < EX; ++m) b0[m] = A.template ldnt<cx<T>>(xa.vo, m * xa.mstride);
-  }
+  // the density stream starts in b0: without HS it was loaded at the start;
+  // with HS after the last of the (even number of) derivative fields, into
+  // the buffer that field left free
+  static_assert(kBackFields % 2 == 0, "the density stream continues in b0");
   if (pair_on && sizeof(T) == 8) {
     // FP64: pair-table rows gathered after each transform (two buffers of
     // double rows would not fit the register budget)
@@ -1319,13 +1337,13 @@ __global__ void __launch_bounds__((PX * (N / EX)))
 // launch list and are skipped here (1: every instance runs here).
 template <typename T, int N, int CH, int EX = Geo<T, N>::EX, int PX = Geo<T, N>::PX>
 __global__ void __launch_bounds__((PX * (N / EX)))
-    k_xback_chunked(const EvalArgs* __restrict__ args, int min_s) {
+    k_xback_chunked(const EvalArgs* __restrict__ args, int min_s, int part) {
   static_assert(CH >= 1 && CH <= 4, "output chunk");
   constexpr int TX = N / EX;
   __shared__ cx<T> tw[N];
   __shared__ cx<T> xch[PX * N];
   int tile;
-  const EvalArgs& a = args[inst_of(x_tiles<N, PX>(), tile)];
+  const EvalArgs& a = args[inst_of_part((N * (N / 2)) / PX, N / PX, part, tile)];
   if (a.S < min_s) return;  // uniform per block
   init_twiddles<T, N>(tw);
   __syncthreads();

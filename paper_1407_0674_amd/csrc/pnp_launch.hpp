@@ -14,10 +14,10 @@ namespace pnp {
 struct Ops {
   void (*tables)(const TableArgs*, int, int, int, hipStream_t);
   void (*zfwd)(const EvalArgs*, int, hipStream_t);
-  void (*ystep)(const EvalArgs*, int, int, int, bool, hipStream_t);
-  void (*xfwd)(const EvalArgs*, int, hipStream_t);
+  void (*ystep)(const EvalArgs*, int, int, int, bool, int, hipStream_t);  // count, sel, nf, fwd, part
+  void (*xfwd)(const EvalArgs*, int, int, hipStream_t);                   // count, part
   void (*zderiv)(const EvalArgs*, int, bool, int, hipStream_t);
-  void (*xback)(const EvalArgs*, int, int, bool, hipStream_t);
+  void (*xback)(const EvalArgs*, int, int, bool, int, hipStream_t);  // count, smax, large, part
   int zderiv_tiles;  // workgroups of the derivative pass per instance
   void (*zinv)(const EvalArgs*, int, int, hipStream_t);
   void (*xplain)(const EvalArgs*, int, int, bool, hipStream_t);

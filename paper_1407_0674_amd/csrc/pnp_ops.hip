@@ -30,15 +30,19 @@ template <typename T, int N, int V = 0> struct Launch {
   static void zfwd(const EvalArgs* a, int count, hipStream_t s) {
     hipLaunchKernelGGL((k_zfwd<T, N, V>), dim3(count * G::tiles_z), dim3(G::RZ * G::TZ), 0, s, a);
   }
-  static void ystep(const EvalArgs* a, int count, int sel, int nf, bool fwd, hipStream_t s) {
+  // part: kPartAll, kPartMain (main-array tiles) or kPartNyquist (Nyquist-plane tiles)
+  static int tiles_y(int part) { return part == kPartAll ? G::tiles_y : part == kPartMain ? (N * G::H) / G::PY : N / G::PY; }
+  static int tiles_x(int part) { return part == kPartAll ? G::tiles_x : part == kPartMain ? (N * G::H) / G::PX : N / G::PX; }
+  static void ystep(const EvalArgs* a, int count, int sel, int nf, bool fwd, int part, hipStream_t s) {
+    const dim3 g(count * tiles_y(part)), b(G::PY * G::TY);
     if (fwd)
-      hipLaunchKernelGGL((k_ystep<T, N, true, V>), dim3(count * G::tiles_y), dim3(G::PY * G::TY), 0, s, a, sel, nf);
+      hipLaunchKernelGGL((k_ystep<T, N, true, V>), g, b, 0, s, a, sel, nf, part);
     else
-      hipLaunchKernelGGL((k_ystep<T, N, false, V>), dim3(count * G::tiles_y), dim3(G::PY * G::TY), 0, s, a, sel,
-                         nf);
+      hipLaunchKernelGGL((k_ystep<T, N, false, V>), g, b, 0, s, a, sel, nf, part);
   }
-  static void xfwd(const EvalArgs* a, int count, hipStream_t s) {
-    hipLaunchKernelGGL((k_xfwd<T, N, G::EX, G::PX>), dim3(count * G::tiles_x), dim3(G::PX * G::TX), 0, s, a);
+  static void xfwd(const EvalArgs* a, int count, int part, hipStream_t s) {
+    hipLaunchKernelGGL((k_xfwd<T, N, G::EX, G::PX>), dim3(count * tiles_x(part)), dim3(G::PX * G::TX), 0, s, a,
+                       part);
   }
   // phi: also sum Phi_hs per workgroup (free-energy calls); fmask: the
   // hard-sphere functionals among the instances (1 Rosenfeld, 2 White Bear),
@@ -59,21 +63,21 @@ template <typename T, int N, int V = 0> struct Launch {
   // The FP32 path runs the streamed kernel for the former and the chunked one
   // for the latter (each skips the other's instances), so an instance gets
   // the arithmetic of its single call in any launch list.
-  static void xback(const EvalArgs* a, int count, int smax, bool large, hipStream_t s) {
-    const dim3 g(count * G::tiles_x), b(G::PX * G::TX);
+  static void xback(const EvalArgs* a, int count, int smax, bool large, int part, hipStream_t s) {
+    const dim3 g(count * tiles_x(part)), b(G::PX * G::TX);
     if constexpr (sizeof(T) == 8) {
       // FP64: the streamed kernel does not fit the register file; the chunked
       // one keeps every spectrum in registers without spilling
-      hipLaunchKernelGGL((k_xback_chunked<T, N, 4, G::EX, G::PX>), g, b, 0, s, a, 1);
+      hipLaunchKernelGGL((k_xback_chunked<T, N, 4, G::EX, G::PX>), g, b, 0, s, a, 1, part);
     } else {
       switch (smax) {
-        case 1: hipLaunchKernelGGL((k_xback<T, N, 1, G::EX, G::PX>), g, b, 0, s, a); break;
-        case 2: hipLaunchKernelGGL((k_xback<T, N, 2, G::EX, G::PX>), g, b, 0, s, a); break;
-        case 3: hipLaunchKernelGGL((k_xback<T, N, 3, G::EX, G::PX>), g, b, 0, s, a); break;
-        case 4: hipLaunchKernelGGL((k_xback<T, N, 4, G::EX, G::PX>), g, b, 0, s, a); break;
+        case 1: hipLaunchKernelGGL((k_xback<T, N, 1, G::EX, G::PX>), g, b, 0, s, a, part); break;
+        case 2: hipLaunchKernelGGL((k_xback<T, N, 2, G::EX, G::PX>), g, b, 0, s, a, part); break;
+        case 3: hipLaunchKernelGGL((k_xback<T, N, 3, G::EX, G::PX>), g, b, 0, s, a, part); break;
+        case 4: hipLaunchKernelGGL((k_xback<T, N, 4, G::EX, G::PX>), g, b, 0, s, a, part); break;
         default: break;
       }
-      if (large) hipLaunchKernelGGL((k_xback_chunked<T, N, 4, G::EX, G::PX>), g, b, 0, s, a, 5);
+      if (large) hipLaunchKernelGGL((k_xback_chunked<T, N, 4, G::EX, G::PX>), g, b, 0, s, a, 5, part);
     }
   }
   static void zinv(const EvalArgs* a, int count, int sel, hipStream_t s) {

@@ -88,3 +88,25 @@ def test_cfg3_mixed_per_term(ev, golden, workload):
         assert float(e.max()) < 1e-5, (k, e)
     del mu3, ref3
     torch.cuda.empty_cache()
+
+
+def test_on_a_callers_stream_equals_default_stream(ev, workload):
+    """From 192^3 on, the Nyquist-plane tiles of the y and x passes run on the
+    context's side stream, forked from and joined back into the caller's
+    stream: on a non-default caller stream, with the output consumed by work
+    queued after the call on that stream, the result equals the
+    default-stream call bit for bit (per term and in total)."""
+    prob, rho = workload
+    ref, ref_slot = ev.mu_ex(prob, rho)
+    ref3, _ = ev.mu_ex(prob, rho, per_term=True, slotboom=False)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        from paper_1407_0674_amd import FLAG_ASYNC
+        mu, slot = ev.mu_ex(prob, rho, flags=FLAG_ASYNC, workspace=ev.workspace(ev.workspace_bytes(prob), "alt"))
+        mu_c = mu.clone()   # consumed on the caller's stream right after the call
+        mu3, _ = ev.mu_ex(prob, rho, per_term=True, slotboom=False)
+    s.synchronize()
+    assert torch.equal(mu_c, ref) and torch.equal(slot, ref_slot)
+    assert torch.equal(mu3, ref3)
+    del mu, slot, mu_c, mu3, ref, ref_slot, ref3
+    torch.cuda.empty_cache()
