@@ -312,8 +312,9 @@ def bench_batch(ev, steps, warmup):
     torch.cuda.synchronize()
     ms_call = (time.perf_counter() - t0) * 1e3 / steps
     # the same evaluation captured once and replayed as one HIP graph per step,
-    # first in the default tile shapes, then after the autotuner has chosen
-    # per pass and size (results are bit-identical either way)
+    # first in the default tile shapes and FFT schedules, then after the
+    # autotuner has chosen both per pass and size (tile shapes keep the bits;
+    # a different schedule agrees to rounding)
     def time_plan():
         plan = ev.plan(probs, rhos, outs=outs, slots=slots, workspaces=wss)
         for _ in range(warmup):
@@ -369,7 +370,7 @@ def bench_batch(ev, steps, warmup):
                 "pct_peak": 100.0 * bytes_model / 1e9 / (ms / 1e3) / HBM_PEAK_GBS,
                 "note": "instances up to 128^3 partly stay in the 256 MB Infinity Cache between passes"},
         "timing": "one captured HIP graph (pnp_plan) replayed per step, statuses read after the last; "
-                  "tile shapes from the autotuner",
+                  "tile shapes and FFT schedules from the autotuner",
         "graph_replay_default_tiles_ms": ms_default_tiles, "autotune_s": tune_s,
         "tuning": ev.tune_export().strip().splitlines(),
         "graph_replay_with_status_each_ms": ms_graph_sync, "batch_call_ms": ms_call,

@@ -383,30 +383,50 @@ pnp_status pnp_plan_status(pnp_plan plan, void* stream, int32_t* status);
 void pnp_plan_destroy(pnp_plan plan);
 
 /*
- * Autotuner of tile shapes.  Every pass of the evaluation has a default tile
- * shape (workgroups carrying 16 pencils or rows, for full-width HBM bursts
- * on large grids) and, for grids up to 128^3, a narrow one with a quarter of
- * the pencils per workgroup and four times the workgroups (small grids
- * otherwise leave most of the 256 compute units idle).  pnp_autotune
- * evaluates the requests (validated and grouped as pnp_batch_mu_ex; their
- * outputs receive real results) `reps` times in each shape after one
- * warm-up round, times every pass with HIP events, and keeps per pass the
- * narrow shape only where it is faster by more than 3 %.  The choice is
- * stored in the context under (precision, n, instance-count class of the
- * launch: 1, 2-3, 4-15, >= 16) and used by every later evaluation with that
- * key (single calls, batches, plans, sessions, the equilibrium solve).
- * Tile shapes do not change the arithmetic: results are bit-identical under
- * any choice.  The call waits for its work.  Accumulated pass timings
- * (pnp_profile_read) are left as they were.
+ * Autotuner of FFT schedules and tile shapes.  Each pass of the evaluation
+ * has two FFT schedules: the primary one (16 elements per thread for the z
+ * and y transforms, 12 on sizes with a factor 3; 8 for the x transforms in
+ * mixed precision, 4 in FP64, 6 with a factor 3; 4, 2 or 6 for the
+ * derivative pass) and a secondary one with half as many elements per
+ * thread, twice the threads per pencil and smaller radices, where such a
+ * radix plan exists (else the two are the same).  Every pass also has a
+ * default tile shape (workgroups carrying 16 pencils or rows, for
+ * full-width HBM bursts on large grids) and, for grids up to 128^3, a
+ * narrow one with a quarter of the pencils per workgroup and four times the
+ * workgroups (small grids otherwise leave most of the 256 compute units
+ * idle).  pnp_autotune evaluates the requests (validated and grouped as
+ * pnp_batch_mu_ex; their outputs receive real results) `reps` times in each
+ * (schedule, shape) combination after one warm-up round, times every pass
+ * with HIP events, and keeps per pass the narrow shape where it is faster
+ * by more than 3 % under a schedule, and the secondary schedule where its
+ * best shape is faster than the primary's by more than 3 %.
+ *
+ * The schedule is stored in the context under (precision, n): the last
+ * autotune or import for that pair sets it for every later evaluation of
+ * that size (single calls, batches of any composition, plans, sessions, the
+ * equilibrium solve, free energies, weighted densities), so an instance gets
+ * the same arithmetic alone and in any batch.  Before any tuning the
+ * schedule is a built-in table of choices measured on an MI355X (the
+ * secondary schedule for the z passes of 256^3 in mixed precision, the
+ * primary one elsewhere).  The two schedules order the floating-point
+ * operations differently: results agree to rounding, not bit for bit.  The
+ * tile shape is stored under (precision, n, instance-count class of the
+ * launch: 1, 2-3, 4-15, >= 16); it does not change the arithmetic.  The
+ * call waits for its work.  Accumulated pass timings (pnp_profile_read) are
+ * left as they were.
  */
 pnp_status pnp_autotune(pnp_ctx ctx, int32_t count, pnp_request* reqs, int32_t reps, void* stream);
 
-/* The stored tuning as text, one line "precision n class mask" per key
- * (mask: bit p set = pass p of pnp_profile_read's order runs narrow).
- * pnp_tune_export writes it into buf (NUL-terminated; *len = its length
- * without the NUL; with buf NULL only *len is set; PNP_E_ARG if cap is too
- * small).  pnp_tune_import merges such text into the context (PNP_E_ARG on
- * malformed or out-of-range lines, and then nothing is merged). */
+/* The stored tuning as text, one line per key: "precision n s mask" for an
+ * FFT schedule (bit p set = pass p of pnp_profile_read's order runs the
+ * secondary schedule) and "precision n class mask" for a tile shape (class
+ * 0-3; bit p set = pass p runs narrow).  Bit 0 (the table pass) is never
+ * set.  pnp_tune_export writes it into buf (NUL-terminated; *len = its
+ * length without the NUL; with buf NULL only *len is set; PNP_E_ARG if cap
+ * is too small).  pnp_tune_import merges such text into the context
+ * (PNP_E_ARG on malformed or out-of-range lines, and then nothing is
+ * merged); a schedule bit of a pass whose two schedules are the same has no
+ * effect. */
 pnp_status pnp_tune_export(pnp_ctx ctx, char* buf, size_t cap, size_t* len);
 pnp_status pnp_tune_import(pnp_ctx ctx, const char* text);
 

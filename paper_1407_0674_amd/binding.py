@@ -399,9 +399,11 @@ class Evaluator:
         return mus, sls, [int(reqs[r].status) for r in range(count)]
 
     def autotune(self, problems: Sequence, rhos: Sequence, reps: int = 3):
-        """Time both tile shapes of every pass on these problems (evaluated as
-        one batch) and keep the faster per pass in this context; returns the
-        statuses.  Saved to $PNP_TUNE_CACHE when that is set."""
+        """Time both FFT schedules and both tile shapes of every pass on these
+        problems (evaluated as one batch) and keep the faster per pass in
+        this context (schedule per precision and size, tile shape also per
+        instance-count class); returns the statuses.  Saved to
+        $PNP_TUNE_CACHE when that is set."""
         count = len(problems)
         reqs, keep, _, _ = self._requests(problems, rhos, True, None, None, None)
         self._check(self.lib.pnp_autotune(self.ctx, count, reqs, int(reps), self._stream()))

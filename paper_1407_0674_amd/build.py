@@ -5,9 +5,9 @@
 Sources (csrc/):
   * pnp_api.hip   the C ABI (host driver) with the kernels outside the FFT
                   passes and the sphere quadrature;
-  * pnp_ops.hip   the pass kernels and their launch table, compiled once per
-                  (precision, grid size) with -DPNP_OPS_T / -DPNP_OPS_N, so
-                  the sizes compile in parallel;
+  * pnp_ops.hip   the pass kernels and their launch tables, compiled once
+                  per (precision, grid size, FFT schedule) with -DPNP_OPS_T /
+                  -DPNP_OPS_N / -DPNP_OPS_SCHED, so they compile in parallel;
   * pnp_serve.cpp the host-only serving layer over the ABI.
 Objects go to paper_1407_0674_amd/_build/ and are linked into the library.
 Packed-FP32 instructions are disabled for every device pass.
@@ -46,8 +46,10 @@ def _units():
              (os.path.join(OBJ, "pnp_serve.o"), [], os.path.join(CSRC, "pnp_serve.cpp"))]
     for t in PRECISIONS:
         for n in SIZES:
-            units.append((os.path.join(OBJ, f"pnp_ops_{t}_{n}.o"), [f"-DPNP_OPS_T={t}", f"-DPNP_OPS_N={n}"],
-                          os.path.join(CSRC, "pnp_ops.hip")))
+            for sched in (0, 1):
+                units.append((os.path.join(OBJ, f"pnp_ops_{t}_{n}_s{sched}.o"),
+                              [f"-DPNP_OPS_T={t}", f"-DPNP_OPS_N={n}", f"-DPNP_OPS_SCHED={sched}"],
+                              os.path.join(CSRC, "pnp_ops.hip")))
     return units
 
 

@@ -39,6 +39,8 @@ struct pnp_ctx_s {
   bool capturing = false;  // a plan is being captured: no pass events
   // autotuned tile shapes: (precision, n, count class) -> narrow-pass mask
   std::map<uint64_t, uint32_t> tune;
+  // autotuned or imported FFT schedules: (precision, n) -> secondary-pass mask
+  std::map<uint64_t, uint32_t> sched;
   // device address of this device's static scratch array (null if the
   // lookup failed at creation)
   void* scratch = nullptr;
@@ -382,7 +384,7 @@ pnp_status read_status(pnp_ctx c, const void* status_dev, hipStream_t s) {
 // ---------------------------------------------------------------------------
 template <typename T, int V>
 const Ops* ops_for_n(int n) {
-  if (V == 1 && n > kNarrowMax) return nullptr;
+  if ((V & 1) && n > kNarrowMax) return nullptr;
   switch (n) {
     case 8: return ops_inst<T, 8, V>();
     case 16: return ops_inst<T, 16, V>();
@@ -392,29 +394,51 @@ const Ops* ops_for_n(int n) {
     case 64: return ops_inst<T, 64, V>();
     case 96: return ops_inst<T, 96, V>();
     case 128: return ops_inst<T, 128, V>();
-    case 192: return V == 0 ? ops_inst<T, 192, 0>() : nullptr;
-    case 256: return V == 0 ? ops_inst<T, 256, 0>() : nullptr;
+    case 192: return (V & 1) ? nullptr : ops_inst<T, 192, V & 2>();
+    case 256: return (V & 1) ? nullptr : ops_inst<T, 256, V & 2>();
     default: return nullptr;
   }
 }
 
+// variant: bit 0 narrow tile shape, bit 1 secondary FFT schedule
 const Ops* ops_for(int precision, int n, int variant = 0) {
-  if (variant == 1) return precision == PNP_MIXED ? ops_for_n<float, 1>(n) : ops_for_n<double, 1>(n);
-  return precision == PNP_MIXED ? ops_for_n<float, 0>(n) : ops_for_n<double, 0>(n);
+  const bool f = precision == PNP_MIXED;
+  switch (variant & 3) {
+    case 1: return f ? ops_for_n<float, 1>(n) : ops_for_n<double, 1>(n);
+    case 2: return f ? ops_for_n<float, 2>(n) : ops_for_n<double, 2>(n);
+    case 3: return f ? ops_for_n<float, 3>(n) : ops_for_n<double, 3>(n);
+    default: return f ? ops_for_n<float, 0>(n) : ops_for_n<double, 0>(n);
+  }
 }
 
-// The tile shape of each pass of one launch sequence: pass p runs the narrow
-// launcher when bit p of mask is set and one exists.
+// The launch variant of each pass of one launch sequence: pass p runs the
+// secondary FFT schedule when bit p of smask is set, and the narrow tile
+// shape when bit p of mask is set and that shape exists.
 struct OpsSel {
-  const Ops* v[2] = {nullptr, nullptr};
-  uint32_t mask = 0;
-  const Ops* at(int pass) const { return ((mask >> pass) & 1u) && v[1] ? v[1] : v[0]; }
+  const Ops* v[4] = {nullptr, nullptr, nullptr, nullptr};
+  uint32_t mask = 0, smask = 0;
+  const Ops* at(int pass) const {
+    const int sch = ((smask >> pass) & 1u) ? 2 : 0;
+    const Ops* o = ((mask >> pass) & 1u) ? v[sch | 1] : nullptr;
+    return o ? o : v[sch];
+  }
 };
 
-// instance-count class of a launch, part of the tuning key
+// instance-count class of a launch, part of the tile-shape key
 int count_class(int count) { return count <= 1 ? 0 : count <= 3 ? 1 : count <= 15 ? 2 : 3; }
 
 uint64_t tune_key(int precision, int n, int cls) { return ((uint64_t)precision << 40) | ((uint64_t)n << 8) | cls; }
+uint64_t sched_key(int precision, int n) { return ((uint64_t)precision << 40) | (uint64_t)n; }
+
+// The FFT schedule of (precision, n) before any tuning: the choice of the
+// autotuner on an MI355X (one instance, three species, all terms) where it
+// measured the secondary schedule faster by more than 3 %; the primary one
+// elsewhere.  At 256^3 in mixed precision the z passes run 8 elements per
+// thread (16 threads per pencil) instead of 16.
+uint32_t default_sched(int precision, int n) {
+  if (precision == PNP_MIXED && n == 256) return (1u << 1) | (1u << 9);
+  return 0u;
+}
 
 // The full launch sequence for `count` instances of one size and precision.
 // Species counts of a launch list: the largest, and the largest among the
@@ -512,13 +536,15 @@ void run_sequence(pnp_ctx c, const OpsSel& op, const EvalArgs* ea, const TableAr
   pt.begin(9); op.at(9)->zinv(ea, count, 2, s); pt.end();
 }
 
-// the tuned tile shapes for a launch of `count` instances of (precision, n)
+// the FFT schedule of (precision, n) and the tuned tile shapes for a launch
+// of `count` instances of it
 OpsSel select_ops(pnp_ctx c, int precision, int n, int count) {
   OpsSel o;
-  o.v[0] = ops_for(precision, n, 0);
-  o.v[1] = ops_for(precision, n, 1);
+  for (int v = 0; v < 4; ++v) o.v[v] = ops_for(precision, n, v);
   auto it = c->tune.find(tune_key(precision, n, count_class(count)));
   if (it != c->tune.end()) o.mask = it->second;
+  auto is = c->sched.find(sched_key(precision, n));
+  o.smask = is != c->sched.end() ? is->second : default_sched(precision, n);
   return o;
 }
 
@@ -608,7 +634,7 @@ static pnp_status enqueue_per_term(pnp_ctx ctx, const Derived& d, const pnp_grid
                           double* slot, double* phi_part, hipStream_t s) {
   const int S = d.S;
   const bool pairs = d.ec || d.sw;
-  const Ops* op = ops_for(d.precision, d.n);
+  const OpsSel os = select_ops(ctx, d.precision, d.n, 1);
   const double sw_c = p->sw_prefactor;
   const long n3 = (long)d.n * d.n * d.n;
   // tables: HS (+ EC pairs into pair), SW pairs into pair2
@@ -636,33 +662,33 @@ static pnp_status enqueue_per_term(pnp_ctx ctx, const Derived& d, const pnp_grid
   if (!dta || !dea) return device_check(ctx, "argument upload");
   PassTimer pt{ctx, s};
   pt.begin(0);
-  op->tables(dta, 1, L.M, S, s);
-  if (d.sw) op->tables(dta + 1, 1, L.M, S, s);
+  os.at(0)->tables(dta, 1, L.M, S, s);
+  if (d.sw) os.at(0)->tables(dta + 1, 1, L.M, S, s);
   pt.end();
   Split sq(ctx, s, d.n);
   const int mp = sq.main_part();
-  pt.begin(1); op->zfwd(dea, 1, s); pt.end();
+  pt.begin(1); os.at(1)->zfwd(dea, 1, s); pt.end();
   sq.fork();
-  pt.begin(2); op->ystep(dea, 1, 0, -1, true, mp, s); pt.end();
-  if (sq.on) op->ystep(dea, 1, 0, -1, true, kPartNyquist, sq.nyq());
+  pt.begin(2); os.at(2)->ystep(dea, 1, 0, -1, true, mp, s); pt.end();
+  if (sq.on) os.at(2)->ystep(dea, 1, 0, -1, true, kPartNyquist, sq.nyq());
   if (d.hs) {
-    pt.begin(3); op->xfwd(dea, 1, mp, s); pt.end();
-    if (sq.on) op->xfwd(dea, 1, kPartNyquist, sq.nyq());
-    pt.begin(4); op->ystep(dea, 1, 1, kVecMode, false, mp, s); pt.end();
-    if (sq.on) op->ystep(dea, 1, 1, kVecMode, false, kPartNyquist, sq.nyq());
+    pt.begin(3); os.at(3)->xfwd(dea, 1, mp, s); pt.end();
+    if (sq.on) os.at(3)->xfwd(dea, 1, kPartNyquist, sq.nyq());
+    pt.begin(4); os.at(4)->ystep(dea, 1, 1, kVecMode, false, mp, s); pt.end();
+    if (sq.on) os.at(4)->ystep(dea, 1, 1, kVecMode, false, kPartNyquist, sq.nyq());
     sq.join();
-    pt.begin(5); op->zderiv(dea, 1, phi_part != nullptr, hs_mask(d), s); pt.end();
+    pt.begin(5); os.at(5)->zderiv(dea, 1, phi_part != nullptr, hs_mask(d), s); pt.end();
     sq.fork();
-    pt.begin(6); op->ystep(dea, 1, 1, kVecMode, true, mp, s); pt.end();
-    if (sq.on) op->ystep(dea, 1, 1, kVecMode, true, kPartNyquist, sq.nyq());
+    pt.begin(6); os.at(6)->ystep(dea, 1, 1, kVecMode, true, mp, s); pt.end();
+    if (sq.on) os.at(6)->ystep(dea, 1, 1, kVecMode, true, kPartNyquist, sq.nyq());
   }
   for (int k = 1; k < 4; ++k) {
-    pt.begin(7); op->xback(dea + k, 1, S <= 4 ? S : 0, S > 4, mp, s); pt.end();
-    if (sq.on) op->xback(dea + k, 1, S <= 4 ? S : 0, S > 4, kPartNyquist, sq.nyq());
-    pt.begin(8); op->ystep(dea + k, 1, 2, -1, false, mp, s); pt.end();
-    if (sq.on) op->ystep(dea + k, 1, 2, -1, false, kPartNyquist, sq.nyq());
+    pt.begin(7); os.at(7)->xback(dea + k, 1, S <= 4 ? S : 0, S > 4, mp, s); pt.end();
+    if (sq.on) os.at(7)->xback(dea + k, 1, S <= 4 ? S : 0, S > 4, kPartNyquist, sq.nyq());
+    pt.begin(8); os.at(8)->ystep(dea + k, 1, 2, -1, false, mp, s); pt.end();
+    if (sq.on) os.at(8)->ystep(dea + k, 1, 2, -1, false, kPartNyquist, sq.nyq());
     sq.join();
-    pt.begin(9); op->zinv(dea + k, 1, 2, s); pt.end();
+    pt.begin(9); os.at(9)->zinv(dea + k, 1, 2, s); pt.end();
     if (k < 3) sq.fork();  // the next term's Nyquist tiles rewrite what this z pass read
   }
   const long sn3 = (long)S * n3;
@@ -917,7 +943,7 @@ pnp_status pnp_free_energy(pnp_ctx ctx, const pnp_grid* g, int32_t S, const pnp_
   // F_el = h^3/2 sum drho (mu_el + mu_el[bulk]); F_sh = h^3 / (2 c_sw) sum rho mu_sh (Sec. 2.3.2, 2.3.4)
   const double el_scale = d.ec ? 0.5 * h3 : 0.0;
   const double sh_scale = (d.sw && p->sw_prefactor != 0.0) ? h3 / (2.0 * p->sw_prefactor) : 0.0;
-  const Ops* op = ops_for(d.precision, d.n);
+  const Ops* op = select_ops(ctx, d.precision, d.n, 1).at(5);  // the derivative pass's launch
   hipLaunchKernelGGL(k_energy_final, dim3(1), dim3(256), 0, s, (const double*)phi_part,
                      d.hs ? op->zderiv_tiles : 0, (const double*)part, kEnergyBlocks, h3, el_scale, sh_scale, res);
   st = device_check(ctx, "energy launch");
@@ -1007,7 +1033,7 @@ pnp_status pnp_weighted_densities(pnp_ctx ctx, const pnp_grid* g, int32_t S, con
   if (ws_bytes < L.total) return fail(ctx, PNP_E_NOMEM, "workspace too small: need " + std::to_string(L.total));
   if (hipSetDevice(ctx->device) != hipSuccess) return device_check(ctx, "set device");
   hipStream_t s = (hipStream_t)stream;
-  const Ops* op = ops_for(d.precision, d.n);
+  const OpsSel os = select_ops(ctx, d.precision, d.n, 1);
   char* w = (char*)ws;
   TableArgs ta;
   fill_table_args(ta, d, sp, g->h, 0.0, false, false, w + L.hs, nullptr, L.M);
@@ -1021,12 +1047,12 @@ pnp_status pnp_weighted_densities(pnp_ctx ctx, const pnp_grid* g, int32_t S, con
   const TableArgs* dta = (const TableArgs*)upload(ctx, &ta, sizeof(ta), s);
   const EvalArgs* dea = (const EvalArgs*)upload(ctx, &ea, sizeof(ea), s);
   if (!dta || !dea) return device_check(ctx, "argument upload");
-  op->tables(dta, 1, L.M, S, s);
-  op->zfwd(dea, 1, s);
-  op->ystep(dea, 1, 0, -1, true, kPartAll, s);
-  op->xfwd(dea, 1, kPartAll, s);
-  op->ystep(dea, 1, 1, kVecMode, false, kPartAll, s);
-  op->zinv(dea, 1, 1, s);
+  os.at(0)->tables(dta, 1, L.M, S, s);
+  os.at(1)->zfwd(dea, 1, s);
+  os.at(2)->ystep(dea, 1, 0, -1, true, kPartAll, s);
+  os.at(3)->xfwd(dea, 1, kPartAll, s);
+  os.at(4)->ystep(dea, 1, 1, kVecMode, false, kPartAll, s);
+  os.at(9)->zinv(dea, 1, 1, s);
   st = device_check(ctx, "launch");
   if (st != PNP_OK) return st;
   if (p->flags & PNP_FLAG_ASYNC) return PNP_OK;
@@ -1287,26 +1313,44 @@ pnp_status pnp_autotune(pnp_ctx ctx, int32_t count, pnp_request* reqs, int32_t r
     const EvalArgs* dea = (const EvalArgs*)upload(ctx, g.ea.data(), sizeof(EvalArgs) * cnt, s);
     if (!dta || !dea) { st = device_check(ctx, "argument upload"); break; }
     OpsSel sel;
-    sel.v[0] = ops_for(g.precision, g.n, 0);
-    sel.v[1] = ops_for(g.precision, g.n, 1);
-    uint32_t best = 0;
-    if (sel.v[1]) {
-      double t[2][PNP_NUM_PASSES] = {};
-      for (int r = 0; r <= reps && st == PNP_OK; ++r)  // the first round warms up and is not counted
-        for (int v = 0; v < 2 && st == PNP_OK; ++v) {
-          sel.mask = v ? ~0u : 0u;
-          run_sequence(ctx, sel, dea, dta, cnt, g.M, g.fmask, g.mix, s, g.n);
-          double ms[PNP_NUM_PASSES];
-          st = pnp_profile_read(ctx, ms, nullptr, PNP_NUM_PASSES, 1);
-          if (r > 0)
-            for (int p = 0; p < PNP_NUM_PASSES; ++p) t[v][p] += ms[p];
-        }
-      // narrow only where it wins clearly
-      for (int p = 1; p < PNP_NUM_PASSES; ++p)
-        if (t[1][p] < 0.97 * t[0][p]) best |= 1u << p;
-    }
+    for (int v = 0; v < 4; ++v) sel.v[v] = ops_for(g.precision, g.n, v);
+    const uint32_t alt = sel.v[0]->sched_alt;       // passes with a secondary schedule
+    const uint32_t all = (1u << PNP_NUM_PASSES) - 2u;  // every pass but the tables
+    // configurations: (schedule mask, tile mask); the narrow ones only where that shape exists
+    const uint32_t cfg[4][2] = {{0u, 0u}, {alt, 0u}, {0u, all}, {alt, all}};
+    const int ncfg = sel.v[1] ? 4 : 2;
+    double t[4][PNP_NUM_PASSES] = {};
+    for (int r = 0; r <= reps && st == PNP_OK; ++r)  // the first round warms up and is not counted
+      for (int c = 0; c < ncfg && st == PNP_OK; ++c) {
+        if (c == 1 && !alt) continue;
+        if (c == 3 && !alt) continue;
+        sel.smask = cfg[c][0];
+        sel.mask = cfg[c][1];
+        run_sequence(ctx, sel, dea, dta, cnt, g.M, g.fmask, g.mix, s, g.n);
+        double ms[PNP_NUM_PASSES];
+        st = pnp_profile_read(ctx, ms, nullptr, PNP_NUM_PASSES, 1);
+        if (r > 0)
+          for (int p = 0; p < PNP_NUM_PASSES; ++p) t[c][p] += ms[p];
+      }
     if (st != PNP_OK) break;
-    ctx->tune[tune_key(g.precision, g.n, count_class(cnt))] = best;
+    // per pass: under each schedule the tile shape (narrow only where it wins
+    // by more than 3 %), then the secondary schedule only where its best
+    // shape wins by more than 3 %
+    uint32_t smask = 0, tmask = 0;
+    for (int p = 1; p < PNP_NUM_PASSES; ++p) {
+      bool nar[2];
+      double best[2];
+      for (int sc = 0; sc < 2; ++sc) {
+        const double wide = t[sc][p], nw = t[2 + sc][p];
+        nar[sc] = ncfg == 4 && nw < 0.97 * wide;
+        best[sc] = nar[sc] ? nw : wide;
+      }
+      const int sc = ((alt >> p) & 1u) && best[1] < 0.97 * best[0] ? 1 : 0;
+      if (sc) smask |= 1u << p;
+      if (nar[sc]) tmask |= 1u << p;
+    }
+    ctx->sched[sched_key(g.precision, g.n)] = smask;
+    ctx->tune[tune_key(g.precision, g.n, count_class(cnt))] = tmask;
   }
   ctx->prof = prof0;
   ctx->prof_mask = mask0;
@@ -1319,6 +1363,10 @@ pnp_status pnp_autotune(pnp_ctx ctx, int32_t count, pnp_request* reqs, int32_t r
 pnp_status pnp_tune_export(pnp_ctx ctx, char* buf, size_t cap, size_t* len) {
   if (!ctx || !len) return PNP_E_ARG;
   std::string out;
+  for (const auto& kv : ctx->sched) {
+    const int precision = (int)(kv.first >> 40), n = (int)(kv.first & 0xffffffffu);
+    out += std::to_string(precision) + " " + std::to_string(n) + " s " + std::to_string(kv.second) + "\n";
+  }
   for (const auto& kv : ctx->tune) {
     const int precision = (int)(kv.first >> 40), n = (int)((kv.first >> 8) & 0xffffffffu),
               cls = (int)(kv.first & 0xff);
@@ -1333,23 +1381,28 @@ pnp_status pnp_tune_export(pnp_ctx ctx, char* buf, size_t cap, size_t* len) {
 
 pnp_status pnp_tune_import(pnp_ctx ctx, const char* text) {
   if (!ctx || !text) return PNP_E_ARG;
-  std::map<uint64_t, uint32_t> parsed;
+  std::map<uint64_t, uint32_t> tiles, scheds;
   const char* p = text;
   while (*p) {
-    int precision, n, cls, used = 0;
+    int precision, n, used = 0;
+    char cls[8];
     unsigned mask;
-    if (std::sscanf(p, " %d %d %d %u%n", &precision, &n, &cls, &mask, &used) != 4) {
+    if (std::sscanf(p, " %d %d %7s %u%n", &precision, &n, cls, &mask, &used) != 4) {
       while (*p == ' ' || *p == '\n' || *p == '\t' || *p == '\r') ++p;
       if (!*p) break;
-      return fail(ctx, PNP_E_ARG, "tuning text: expected lines 'precision n class mask'");
+      return fail(ctx, PNP_E_ARG, "tuning text: expected lines 'precision n class mask' or 'precision n s mask'");
     }
-    if ((precision != PNP_FP64 && precision != PNP_MIXED) || !size_ok(n) || cls < 0 || cls > 3 ||
+    const bool is_sched = std::strcmp(cls, "s") == 0;
+    const bool is_tile = std::strlen(cls) == 1 && cls[0] >= '0' && cls[0] <= '3';
+    if ((precision != PNP_FP64 && precision != PNP_MIXED) || !size_ok(n) || !(is_sched || is_tile) ||
         (mask & 1u) || (mask >> PNP_NUM_PASSES))
       return fail(ctx, PNP_E_ARG, "tuning text: entry out of range");
-    parsed[tune_key(precision, n, cls)] = mask;
+    if (is_sched) scheds[sched_key(precision, n)] = mask;
+    else tiles[tune_key(precision, n, cls[0] - '0')] = mask;
     p += used;
   }
-  for (const auto& kv : parsed) ctx->tune[kv.first] = kv.second;
+  for (const auto& kv : tiles) ctx->tune[kv.first] = kv.second;
+  for (const auto& kv : scheds) ctx->sched[kv.first] = kv.second;
   return PNP_OK;
 }
 

@@ -43,27 +43,57 @@ constexpr int pow2_divisor_le(long v, int cap) {
   return r;
 }
 
-// V selects the tile shape: 0 the default (wide rows for full HBM bursts),
-// 1 narrow (a quarter of the rows or pencils per workgroup: four times the
-// workgroups, for grids too small to fill the chip).  The shape only changes
-// how many pencils a workgroup carries; every pencil's arithmetic is the same.
-constexpr int narrow(int v, int V) { return V == 0 ? v : (v / 4 > 1 ? v / 4 : 1); }
+// V selects the launch variant of a pass.  Bit 0, the tile shape: clear,
+// the default (wide rows for full HBM bursts); set, narrow (a quarter of the
+// rows or pencils per workgroup: four times the workgroups, for grids too
+// small to fill the chip).  The shape only changes how many pencils a
+// workgroup carries; every pencil's arithmetic is the same.  Bit 1, the FFT
+// schedule: clear, the primary elements per thread of each pass family;
+// set, the secondary one (half as many elements per thread, twice the
+// threads per pencil, and a radix plan with smaller radices).  The schedule
+// changes the order of the floating-point operations, so results of the two
+// schedules agree to rounding, not bit for bit.
+constexpr int narrow(int v, int V) { return (V & 1) == 0 ? v : (v / 4 > 1 ? v / 4 : 1); }
+
+// whether a length-len pencil with ept elements per thread has a radix plan
+// (every stage a radix dividing both what is left of len and ept)
+constexpr bool plan_ok(int len, int ept) {
+  if (ept < 2 || len % ept != 0) return false;
+  for (int ns = 1; ns < len;) {
+    const int r = pick_radix(len / ns, ept);
+    if (r <= 1) return false;
+    ns *= r;
+  }
+  return true;
+}
+
+// the secondary schedule of a pass family: half the primary elements per
+// thread where that has a radix plan and stays within 1024 threads per
+// workgroup (`per` pencils per workgroup in the wide tile shape, the larger
+// one, so both shapes get the same schedule), else the primary one
+constexpr int alt_ept(int len, int prim, int per) {
+  return (plan_ok(len, prim / 2) && per * (len / (prim / 2)) <= 1024) ? prim / 2 : prim;
+}
 
 template <typename T, int N, int V = 0> struct Geo {
   static constexpr int H = N / 2;
   static constexpr bool R3 = (N % 3 == 0);
+  static constexpr bool SEC = (V & 2) != 0;
   // z passes (P1, P9): complex FFT of length H, EZ elements per thread
-  static constexpr int EZ = R3 ? 12 : (H >= 16 ? 16 : H);
+  static constexpr int EZ0 = R3 ? 12 : (H >= 16 ? 16 : H);
+  static constexpr int EZ = SEC ? alt_ept(H, EZ0, 1) : EZ0;  // RZ * TZ <= 256 for any EZ
   static constexpr int TZ = H / EZ;
   static constexpr int RZ = narrow(pow2_divisor_le((long)N * N, 256 / TZ), V);  // rows per block
   // y passes
-  static constexpr int EY = R3 ? 12 : (N >= 16 ? 16 : N);
-  static constexpr int TY = N / EY;
   static constexpr int PY = narrow(pow2_divisor_le(N, sizeof(T) == 4 ? 16 : 8), V);
+  static constexpr int EY0 = R3 ? 12 : (N >= 16 ? 16 : N);
+  static constexpr int EY = SEC ? alt_ept(N, EY0, pow2_divisor_le(N, sizeof(T) == 4 ? 16 : 8)) : EY0;
+  static constexpr int TY = N / EY;
   // x passes
-  static constexpr int EX = R3 ? 6 : (sizeof(T) == 4 ? (N >= 8 ? 8 : N) : (N >= 4 ? 4 : N));
-  static constexpr int TX = N / EX;
   static constexpr int PX = narrow(pow2_divisor_le(N, sizeof(T) == 4 ? 16 : 8), V);
+  static constexpr int EX0 = R3 ? 6 : (sizeof(T) == 4 ? (N >= 8 ? 8 : N) : (N >= 4 ? 4 : N));
+  static constexpr int EX = SEC ? alt_ept(N, EX0, pow2_divisor_le(N, sizeof(T) == 4 ? 16 : 8)) : EX0;
+  static constexpr int TX = N / EX;
   // tiles per instance
   static constexpr int tiles_z = (N * N) / RZ;
   static constexpr int tiles_y = (N * H) / PY + N / PY;
@@ -523,6 +553,12 @@ __global__ void __launch_bounds__((Geo<T, N, V>::RZ * Geo<T, N, V>::TZ))
 template <typename T, int N>
 constexpr int default_ezd() {
   return ((N / 2) % 3 == 0) ? 6 : ((N / 2) >= (sizeof(T) == 4 ? 4 : 2) ? (sizeof(T) == 4 ? 4 : 2) : N / 2);
+}
+// elements per thread of the derivative pass under launch variant V (bit 1:
+// secondary schedule; RDD * TZD <= 256 for any choice)
+template <typename T, int N, int V>
+constexpr int ezd_of() {
+  return (V & 2) ? alt_ept(N / 2, default_ezd<T, N>(), 1) : default_ezd<T, N>();
 }
 
 template <typename T, int N, int EZ = default_ezd<T, N>(), int V = 0> struct GeoD {

@@ -1,7 +1,7 @@
 // One translation unit of launch tables: the pass kernels of one precision
-// (PNP_OPS_T: float or double) and grid size (PNP_OPS_N), in both tile
-// shapes where the narrow one exists.  The build compiles this file once per
-// (precision, size) pair.
+// (PNP_OPS_T: float or double), grid size (PNP_OPS_N) and FFT schedule
+// (PNP_OPS_SCHED), in both tile shapes where the narrow one exists.  The
+// build compiles this file once per (precision, size, schedule).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -15,13 +15,16 @@
 #ifndef PNP_OPS_N
 #error "PNP_OPS_N (grid size) must be defined"
 #endif
+#ifndef PNP_OPS_SCHED
+#error "PNP_OPS_SCHED (0 primary or 1 secondary FFT schedule) must be defined"
+#endif
 
 namespace pnp {
 
 template <typename T, int N, int V = 0> struct Launch {
   using G = Geo<T, N, V>;
-  using GD = GeoD<T, N, default_ezd<T, N>(), V>;
-  static constexpr int EZD = default_ezd<T, N>();
+  static constexpr int EZD = ezd_of<T, N, V>();
+  using GD = GeoD<T, N, EZD, V>;
   // maxS: the largest species count among the launch's instances
   static void tables(const TableArgs* a, int count, int M, int maxS, hipStream_t s) {
     const int items = maxS * ((maxS + 3) / 4 * 4) + maxS;  // pair-table entries + hs species
@@ -96,14 +99,22 @@ template <typename T, int N, int V = 0> struct Launch {
     const int blocks = (int)std::min<long>((total + 255) / 256, 4096);
     hipLaunchKernelGGL((k_export<T, N>), dim3(blocks), dim3(256), 0, s, a, nf, buf, to_numpy);
   }
-  static constexpr Ops ops{tables, zfwd, ystep, xfwd, zderiv, xback, GD::tiles, zinv, xplain, xport};
+  // passes whose secondary schedule differs from the primary one
+  using G0 = Geo<T, N, 0>;
+  using G2 = Geo<T, N, 2>;
+  static constexpr uint32_t sched_alt =
+      (G0::EZ != G2::EZ ? (1u << 1) | (1u << 9) : 0u) |
+      (G0::EY != G2::EY ? (1u << 2) | (1u << 4) | (1u << 6) | (1u << 8) : 0u) |
+      (G0::EX != G2::EX ? (1u << 3) | (1u << 7) : 0u) | (ezd_of<T, N, 0>() != ezd_of<T, N, 2>() ? 1u << 5 : 0u);
+  static constexpr Ops ops{tables, zfwd, ystep, xfwd, zderiv, xback, GD::tiles, zinv, xplain, xport, sched_alt};
 };
 
 template <typename T, int N, int V> const Ops* ops_inst() { return &Launch<T, N, V>::ops; }
 
-template const Ops* ops_inst<PNP_OPS_T, PNP_OPS_N, 0>();
+// PNP_OPS_SCHED (0 or 1): the FFT schedule of this translation unit
+template const Ops* ops_inst<PNP_OPS_T, PNP_OPS_N, 2 * PNP_OPS_SCHED>();
 #if PNP_OPS_N <= 128
-template const Ops* ops_inst<PNP_OPS_T, PNP_OPS_N, 1>();
+template const Ops* ops_inst<PNP_OPS_T, PNP_OPS_N, 2 * PNP_OPS_SCHED + 1>();
 #endif
 
 }  // namespace pnp
