@@ -406,9 +406,10 @@ void pnp_plan_destroy(pnp_plan plan);
  * that size (single calls, batches of any composition, plans, sessions, the
  * equilibrium solve, free energies, weighted densities), so an instance gets
  * the same arithmetic alone and in any batch.  Before any tuning the
- * schedule is a built-in table of choices measured on an MI355X (the
- * secondary schedule for the z passes of 256^3 in mixed precision, the
- * primary one elsewhere).  The two schedules order the floating-point
+ * schedule is a built-in table of the autotuner's choices measured on an
+ * MI355X for each supported size and precision (at 256^3 in mixed
+ * precision: the secondary schedule for the two z passes and the first y
+ * pass).  The two schedules order the floating-point
  * operations differently: results agree to rounding, not bit for bit.  The
  * tile shape is stored under (precision, n, instance-count class of the
  * launch: 1, 2-3, 4-15, >= 16); it does not change the arithmetic.  The

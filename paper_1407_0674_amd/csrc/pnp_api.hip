@@ -11,6 +11,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <initializer_list>
 #include <map>
 #include <mutex>
 #include <string>
@@ -430,13 +431,37 @@ int count_class(int count) { return count <= 1 ? 0 : count <= 3 ? 1 : count <= 1
 uint64_t tune_key(int precision, int n, int cls) { return ((uint64_t)precision << 40) | ((uint64_t)n << 8) | cls; }
 uint64_t sched_key(int precision, int n) { return ((uint64_t)precision << 40) | (uint64_t)n; }
 
-// The FFT schedule of (precision, n) before any tuning: the choice of the
-// autotuner on an MI355X (one instance, three species, all terms) where it
-// measured the secondary schedule faster by more than 3 %; the primary one
-// elsewhere.  At 256^3 in mixed precision the z passes run 8 elements per
-// thread (16 threads per pencil) instead of 16.
+// The FFT schedule of (precision, n) before any tuning: the passes (numbered
+// as pnp_profile_read orders them) on which the autotuner, run twice on an
+// MI355X for one three-species instance with every term, chose the
+// secondary schedule both times.
+constexpr uint32_t passes(std::initializer_list<int> l) {
+  uint32_t m = 0;
+  for (int p : l) m |= 1u << p;
+  return m;
+}
+
+struct SchedDefault {
+  int n;
+  uint32_t mixed, fp64;
+};
+
+constexpr SchedDefault kSchedDefault[] = {
+    {8, passes({3, 5, 7, 9}), passes({3, 7, 9})},
+    {16, passes({1, 3, 5, 6, 7, 9}), passes({1, 3, 4, 6, 7, 9})},
+    {24, passes({1, 2, 4, 6, 8, 9}), passes({1, 2, 4, 6, 8, 9})},
+    {32, passes({1, 2, 3, 4, 5, 6, 7, 8, 9}), passes({1, 2, 3, 4, 6, 8, 9})},
+    {48, passes({1, 9}), passes({1, 2, 6, 8, 9})},
+    {64, passes({1, 2, 3, 4, 5, 6, 7, 8, 9}), passes({1, 2, 4, 6, 8, 9})},
+    {96, passes({1, 9}), passes({1, 9})},
+    {128, passes({1, 2, 3, 4, 6, 9}), passes({1, 2, 4, 6, 9})},
+    {192, passes({1, 9}), passes({9})},
+    {256, passes({1, 2, 9}), passes({1})},
+};
+
 uint32_t default_sched(int precision, int n) {
-  if (precision == PNP_MIXED && n == 256) return (1u << 1) | (1u << 9);
+  for (const SchedDefault& d : kSchedDefault)
+    if (d.n == n) return precision == PNP_MIXED ? d.mixed : d.fp64;
   return 0u;
 }
 
