@@ -661,6 +661,55 @@ __device__ __forceinline__ double recip_f64(double x) {
   return __builtin_fma(y, e, y);
 }
 
+// Natural logarithm in FP64 by table reduction.  Write u = m 2^e with m in
+// [1/2, 1).  The top eight fraction bits of m select entry j, for the
+// interval centred on c_j = 1/2 + (j + 1/2) / 512: ic_j is a double close to
+// 1 / c_j and nl_j = -ln(ic_j) (both made once per workgroup by
+// log_table_init).  Then r = m ic_j - 1 (one fma, so r is the correctly
+// rounded value; |r| <= 2^-9) and ln u = e ln 2 + nl_j + log1p(r), with
+// log1p(r) = r - r^2/2 + ... + r^7/7 (truncation below 2^-66 relative) and
+// ln 2 split into a head whose products with e are exact and a tail.
+// Within 2^-9 of 1 the series runs on r = u - 1 (exact) with no table, so
+// ln u keeps full relative accuracy there; elsewhere the error is within a
+// few units in the last place of the result (the rounding of nl_j and of
+// the final sum), and a few units of 1e-16 in absolute terms where e = 1 and
+// u is just above 1 + 2^-9.  Any u maps to an entry in [0, 255] (the index
+// is masked), so non-positive or non-finite inputs give a meaningless value
+// without touching memory outside the table.
+struct LogEntry {
+  double ic, nl;
+};
+constexpr int kLogTable = 256;
+
+__device__ __forceinline__ void log_table_init(LogEntry* tab) {
+  for (int j = threadIdx.x; j < kLogTable; j += blockDim.x) {
+    const double ic = 1.0 / (0.5 + ((double)j + 0.5) / 512.0);
+    tab[j] = LogEntry{ic, -log(ic)};
+  }
+}
+
+__device__ __forceinline__ double log_f64(double u, const LogEntry* tab) {
+  constexpr double ln2_hi = 6.93147180369123816490e-01;  // 32 significant bits
+  constexpr double ln2_lo = 1.90821492927058770002e-10;
+  const double m = __builtin_amdgcn_frexp_mant(u);
+  const int e = __builtin_amdgcn_frexp_exp(u);
+  const uint32_t hi = (uint32_t)(__builtin_bit_cast(uint64_t, m) >> 32);
+  const LogEntry t = tab[(hi >> 12) & (kLogTable - 1)];
+  const bool near1 = fabs(u - 1.0) < 0x1p-9;
+  const double r = near1 ? u - 1.0 : __builtin_fma(m, t.ic, -1.0);
+  double q = 1.0 / 7.0;
+  q = __builtin_fma(q, r, -1.0 / 6.0);
+  q = __builtin_fma(q, r, 1.0 / 5.0);
+  q = __builtin_fma(q, r, -0.25);
+  q = __builtin_fma(q, r, 1.0 / 3.0);
+  q = __builtin_fma(q, r, -0.5);
+  const double lp = __builtin_fma(q, r * r, r);  // log1p(r)
+  const double ed = (double)e;
+  const double head = __builtin_fma(ed, ln2_hi, t.nl);
+  const double tail = __builtin_fma(ed, ln2_lo, lp);
+  return near1 ? lp : head + tail;
+}
+
 // Coefficient of the n2^3 term of the modified (White Bear) functional,
 // phi3(x) = [x + (1 - x)^2 ln(1 - x)] / (36 pi x^2 (1 - x)^2), as
 // g = 36 pi phi3 and its derivative g'.  With u = 1 - x:
@@ -702,6 +751,7 @@ __global__ void __launch_bounds__((GeoD<T, N, EZD, V>::RDD * GeoD<T, N, EZD, V>:
   __shared__ cx<T> twH[H];
   __shared__ cx<T> twN[N];
   __shared__ cx<T> xch[RD * H];
+  __shared__ LogEntry logt[kLogTable];
   int tile;
   const EvalArgs& a = args[inst_of(D::tiles, tile)];
   if (!a.hs_on || (a.hs_wb != 0) != WB) return;  // uniform per block
@@ -721,6 +771,7 @@ __global__ void __launch_bounds__((GeoD<T, N, EZD, V>::RDD * GeoD<T, N, EZD, V>:
     c2r_load<T, N, TZ, EZ>(k0, m0, t, B, 0, row);
     init_twiddles<T, H>(twH);
     init_twiddles<T, N>(twN);
+    log_table_init(logt);
     __syncthreads();
     twr.load(t, twH);
 #pragma unroll
@@ -777,7 +828,7 @@ __global__ void __launch_bounds__((GeoD<T, N, EZD, V>::RDD * GeoD<T, N, EZD, V>:
       double d[kFields];
       // -ln(1 - n3): log of the rounded u plus the first-order correction for
       // the rounding of u, which equals log1p(-n3) to working precision
-      d[0] = -(log(u) - ((u - 1.0) + n3) * inv);
+      d[0] = -(log_f64(u, logt) - ((u - 1.0) + n3) * inv);
       // Phi_hs (Sec. 2.3.1): -n0 ln(1 - n3) + (n1 n2 - n1v.n2v) / (1 - n3)
       //                      + (n2^3 - 3 n2 n2v.n2v) phi3(n3)
       // with phi3 = 1 / (24 pi (1 - n3)^2) (Rosenfeld) or the modified form

@@ -4,6 +4,8 @@ element by element on the same seeded inputs.
 Tolerances (infinity-norm relative error per species and term):
 FP64 path 1e-10, mixed FP32/FP64 path 1e-5.
 """
+import math
+
 import numpy as np
 import pytest
 import torch
@@ -103,3 +105,22 @@ def test_high_packing_mixed_64(ev):
     ref = oracle.mu_ex(prob, rho, "fft")
     mu3, slot = ev.mu_ex(prob, to_dev(rho), per_term=True)
     _check_terms(mu3.cpu().numpy(), ref, prob.S, MIXED_TOL, prob.terms)
+
+
+def _py_single(eta):
+    """beta mu_ex of a one-component hard-sphere fluid in the Percus-Yevick
+    compressibility route, which the Rosenfeld functional reproduces in bulk."""
+    return -math.log1p(-eta) + (14 * eta - 13 * eta ** 2 + 5 * eta ** 3) / (2 * (1 - eta) ** 3)
+
+
+@pytest.mark.parametrize("eta", [1e-9, 1e-4, 0.0025, 0.2, 0.45, 0.6, 0.72])
+def test_uniform_fluid_fp64_is_percus_yevick(ev, eta):
+    # the packing fractions put 1 - n3 in every branch of the derivative
+    # pass's logarithm: within 2^-9 of 1, just outside, and below 1/2
+    d = 0.3
+    rho_b = eta / (math.pi / 6 * d ** 3)
+    prob = P.Problem(n=8, h=0.1, species=[P.Species(d, 0.0, rho_b)], T=300.0, terms=P.TERM_HS)
+    rho = np.full(prob.shape, rho_b)
+    mu, _ = ev.mu_ex(prob, to_dev(rho))
+    got = mu.cpu().numpy()
+    assert np.max(np.abs(got / _py_single(eta) - 1.0)) < 1e-12, eta
