@@ -259,30 +259,30 @@ template <typename T> using v4 = typename vec4<T>::type;
 // ---------------------------------------------------------------------------
 constexpr double kPi = 3.14159265358979323846;
 
-// j1(x)/x = (sin x - x cos x) / x^3, series below 0.5
-__device__ inline double d_j1x(double x) {
-  if (fabs(x) < 0.5) {
-    const double x2 = x * x;
+// Radial profiles of the step-like kernels at y = k a, from one sin/cos pair
+// of y (the caller evaluates it only where the closed forms are used):
+//   j1x(y) = j1(y) / y = (sin y - y cos y) / y^3        (series below 0.5)
+//   rb(y)  = (2 y sin y + (2 - y^2) cos y - 2) / y^4    (series below 1)
+//   irb(y) = (1 - cos y) / y^2                          (series below 1)
+// with the ball transform 4 pi a^3 j1x, the transform of r theta(a - r)
+// 4 pi a^4 rb and that of theta(a - r) / r 4 pi a^2 irb.  The series are the
+// Taylor expansions of the same expressions (the closed forms cancel as
+// y -> 0), summed to below 1e-17 relative on their ranges.
+__device__ inline double d_j1x(double y, double sn, double cs) {
+  if (fabs(y) < 0.5) {
+    const double y2 = y * y;
     double p = 1.0, s = 0.0, f = 1.0;  // f = (2m+1)!
     for (int m = 0; m < 8; ++m) {
       if (m > 0) f *= (double)(2 * m) * (double)(2 * m + 1);
       s += ((m & 1) ? -p : p) / (f * (double)(2 * m + 3));
-      p *= x2;
+      p *= y2;
     }
     return s;
   }
-  double sn, cs;
-  sincos(x, &sn, &cs);
-  return (sn - x * cs) / (x * x * x);
+  return (sn - y * cs) / (y * y * y);
 }
 
-// transform of the unit ball of radius a
-__device__ inline double d_ball(double k, double a) { return 4.0 * kPi * a * a * a * d_j1x(k * a); }
-
-// transform of r * theta(a - r)
-__device__ inline double d_rball(double k, double a) {
-  const double y = k * a;
-  double f;
+__device__ inline double d_rb(double y, double sn, double cs) {
   if (fabs(y) < 1.0) {
     const double y2 = y * y;
     double p = 1.0, s = 0.0, fa = 1.0;
@@ -291,31 +291,39 @@ __device__ inline double d_rball(double k, double a) {
       s += ((m & 1) ? -p : p) / (fa * (double)(2 * m + 4));
       p *= y2;
     }
-    f = s;
-  } else {
-    double sn, cs;
-    sincos(y, &sn, &cs);
-    f = (2.0 * y * sn + (2.0 - y * y) * cs - 2.0) / (y * y * y * y);
+    return s;
   }
-  return 4.0 * kPi * a * a * a * a * f;
+  return (2.0 * y * sn + (2.0 - y * y) * cs - 2.0) / (y * y * y * y);
 }
 
-// transform of theta(a - r) / r
-__device__ inline double d_invrball(double k, double a) {
-  const double y = k * a;
-  double f = 0.5;
-  if (y != 0.0) {
-    const double s = sin(0.5 * y);
-    f = 2.0 * s * s / (y * y);
+__device__ inline double d_irb(double y, double cs) {
+  if (fabs(y) < 1.0) {
+    // (1 - cos y) / y^2 = sum_m (-1)^m y^(2m) / (2m + 2)!
+    const double y2 = y * y;
+    double p = 1.0, s = 0.0, fa = 2.0;  // fa = (2m+2)!
+    for (int m = 0; m < 10; ++m) {
+      if (m > 0) fa *= (double)(2 * m + 1) * (double)(2 * m + 2);
+      s += ((m & 1) ? -p : p) / fa;
+      p *= y2;
+    }
+    return s;
   }
-  return 4.0 * kPi * a * a * f;
+  return (1.0 - cs) / (y * y);
+}
+
+// j1(x)/x from x alone
+__device__ inline double d_j1x(double x) {
+  double sn = 0.0, cs = 1.0;
+  if (fabs(x) >= 0.5) sincos(x, &sn, &cs);
+  return d_j1x(x, sn, cs);
 }
 
 // hs table [m][S][4] = (j0(kR), 4 pi R^3 j1(kR)/(kR), 4 pi R^2 j1(kR), 0)
 // (FP64 path only); pair table [m][j][i] (row length Sp) = G_ij, the combined
 // pair kernel, zero for i >= S.  One thread per (m, table entry): blockIdx.y
 // picks the entry (pair-table entries first, then the hs species), blockIdx.z
-// the instance.
+// the instance.  G is symmetric, so the thread of entry (j, i) with i <= j
+// writes both (j, i) and (i, j), and those with i > j have nothing to do.
 template <typename T>
 __global__ void __launch_bounds__(256) k_tables(const TableArgs* __restrict__ targs) {
   const TableArgs& a = targs[blockIdx.z];
@@ -327,24 +335,41 @@ __global__ void __launch_bounds__(256) k_tables(const TableArgs* __restrict__ ta
   if (item < npair) {
     if (!a.pair_tab) return;
     const int j = item / a.Sp, i = item % a.Sp;
-    double v = 0.0;
-    if (i < a.S) {
-      const int p = a.pidx[i][j];
-      const double s = a.sigma[p];
-      if (a.ec_pref[p] != 0.0) {
-        const double b = a.Bsig[p];
-        v += a.ec_pref[p] * (2.0 * b * d_ball(k, s) - b * b * d_rball(k, s) - d_invrball(k, s));
-      }
-      if (a.sw_pref[p] != 0.0) v += a.sw_pref[p] * (d_ball(k, a.rout[p]) - d_ball(k, s));
-    }
     const Buf pr = make_buf(a.pair_tab, (uint64_t)a.M * a.S * a.Sp * sizeof(T));
+    if (i >= a.S) {
+      pr.template st<T>((T)0, (uint32_t)(((m * a.S + j) * a.Sp + i) * sizeof(T)));
+      return;
+    }
+    if (i > j) return;  // written by the thread of (i, j)
+    const int p = a.pidx[i][j];
+    const double s = a.sigma[p];
+    const double y = k * s;
+    double sn = 0.0, cs = 1.0;
+    if (fabs(y) >= 0.5) sincos(y, &sn, &cs);
+    const double ball = 4.0 * kPi * s * s * s * d_j1x(y, sn, cs);
+    double v = 0.0;
+    if (a.ec_pref[p] != 0.0) {
+      // MSA correlation (Sec. 2.3.4): 2 B ball - B^2 (r-ball) - (1/r-ball)
+      const double b = a.Bsig[p];
+      const double rball = 4.0 * kPi * s * s * s * s * d_rb(y, sn, cs);
+      const double irball = 4.0 * kPi * s * s * d_irb(y, cs);
+      v += a.ec_pref[p] * (2.0 * b * ball - b * b * rball - irball);
+    }
+    if (a.sw_pref[p] != 0.0) {
+      // square well (Sec. 2.3.2): the shell between sigma and r_out
+      const double ro = a.rout[p];
+      v += a.sw_pref[p] * (4.0 * kPi * ro * ro * ro * d_j1x(k * ro) - ball);
+    }
     pr.template st<T>((T)v, (uint32_t)(((m * a.S + j) * a.Sp + i) * sizeof(T)));
+    if (i != j) pr.template st<T>((T)v, (uint32_t)(((m * a.S + i) * a.Sp + j) * sizeof(T)));
   } else if (sizeof(T) == 8 && item < npair + a.S) {  // the FP32 path evaluates these in registers
     const int i = item - npair;
     const double R = a.R[i];
     const double x = k * R;
-    const double j1x = d_j1x(x);
-    const double j0 = (x == 0.0) ? 1.0 : sin(x) / x;
+    double sn, cs;
+    sincos(x, &sn, &cs);
+    const double j1x = d_j1x(x, sn, cs);
+    const double j0 = (x == 0.0) ? 1.0 : sn / x;
     v4<T> w;
     w.x = (T)j0;
     w.y = (T)(4.0 * kPi * R * R * R * j1x);
