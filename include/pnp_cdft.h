@@ -96,10 +96,13 @@ enum {
   PNP_FP64 = 0,  /* FFTs, weights and pointwise work in double */
   PNP_MIXED = 1  /* FFTs, weight multiplies and the sum of the three terms
                     (taken in k-space, before the last inverse transform) in
-                    float; the FMT derivatives (log(1 - n3), 1/(1 - n3)^k),
-                    the bulk constants, the output and exp(-beta mu) in
-                    double.  Error against the FP64 path: about 1e-6 of each
-                    term's largest magnitude at packing 0.45 */
+                    float; the singular factors of the FMT derivatives
+                    (log(1 - n3), 1/(1 - n3)^k, the White Bear coefficient)
+                    in double, their products with the weighted densities in
+                    float (in double for free energies); the bulk constants,
+                    the output and exp(-beta mu) in double.  Error against
+                    the FP64 path: about 1e-6 of each term's largest
+                    magnitude at packing 0.45 */
 };
 
 /* flags */

@@ -29,6 +29,8 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 
+#include <type_traits>
+
 #include "fft_core.hpp"
 #include "pnp_kernels.hpp"
 
@@ -571,8 +573,11 @@ __global__ void __launch_bounds__((Geo<T, N, V>::RZ * Geo<T, N, V>::TZ))
   if (bad) raise_status(a.status, bad, badidx);
 }
 
-// P5: z c2r of the 10 weighted densities, the FMT derivatives in float64
-// (Sec. 2.3.1), z r2c of the 10 derivative fields; in place on specB.
+// P5: z c2r of the 10 weighted densities, the FMT derivatives (Sec. 2.3.1),
+// z r2c of the 10 derivative fields; in place on specB.  ln(1 - n3) and the
+// powers of 1 / (1 - n3) (and the White Bear coefficient) are evaluated in
+// float64; their products with the weighted densities in the FFT type (in
+// float64 for free-energy calls).
 // Every thread keeps its EZD elements of all ten fields in registers, so the
 // ten values at a grid point meet in one thread without an LDS round trip.
 template <typename T, int N>
@@ -833,53 +838,60 @@ __global__ void __launch_bounds__((GeoD<T, N, EZD, V>::RDD * GeoD<T, N, EZD, V>:
   const double inv8pi = 1.0 / (8.0 * kPi), inv12pi = 1.0 / (12.0 * kPi), inv4pi = 1.0 / (4.0 * kPi);
   const double inv24pi = 1.0 / (24.0 * kPi), inv36pi = 1.0 / (36.0 * kPi);
   double phi = 0.0;  // Phi_hs summed over this thread's grid points
+  // type of the products of the weighted densities with those factors: the
+  // FFT type, except for free-energy calls (double throughout, Phi summed in
+  // double)
+  using P = typename std::conditional<PHI, double, T>::type;
 #pragma unroll
   for (int m = 0; m < EZ; ++m) {
 #pragma unroll
     for (int h = 0; h < 2; ++h) {  // the two real points z = 2j, 2j+1 of element j
-      double f[kFields];
+      P f[kFields];
 #pragma unroll
-      for (int q = 0; q < kFields; ++q) f[q] = h ? (double)val[q * EZ + m].y : (double)val[q * EZ + m].x;
-      const double n0 = f[0], n1 = f[1], n2 = f[2], n3 = f[3];
-      const double a1x = f[4], a1y = f[5], a1z = f[6], a2x = f[7], a2y = f[8], a2z = f[9];
-      if (!(n3 < 1.0)) {
+      for (int q = 0; q < kFields; ++q) f[q] = h ? (P)val[q * EZ + m].y : (P)val[q * EZ + m].x;
+      const P n0 = f[0], n1 = f[1], n2 = f[2], n3 = f[3];
+      const P a1x = f[4], a1y = f[5], a1z = f[6], a2x = f[7], a2y = f[8], a2z = f[9];
+      if (!(n3 < (P)1)) {
         bad |= isfinite(n3) ? kStPacking : kStNonFinite;
         badidx = min(badidx, row * N + 2 * (t + TZ * m) + h);
       }
-      const double u = 1.0 - n3;
+      // the logarithm and the powers of 1 / (1 - n3) in double
+      const double n3d = (double)n3, u = 1.0 - n3d;
       const double inv = recip_f64(u), inv2 = inv * inv, inv3 = inv2 * inv;
-      const double v12 = a1x * a2x + a1y * a2y + a1z * a2z;
-      const double v22 = a2x * a2x + a2y * a2y + a2z * a2z;
-      double d[kFields];
       // -ln(1 - n3): log of the rounded u plus the first-order correction for
       // the rounding of u, which equals log1p(-n3) to working precision
-      d[0] = -(log_f64(u, logt) - ((u - 1.0) + n3) * inv);
+      const double d0 = -(log_f64(u, logt) - ((u - 1.0) + n3d) * inv);
+      const P i1 = (P)inv, i2 = (P)inv2;
+      const P v12 = a1x * a2x + a1y * a2y + a1z * a2z;
+      const P v22 = a2x * a2x + a2y * a2y + a2z * a2z;
+      P d[kFields];
+      d[0] = (P)d0;
       // Phi_hs (Sec. 2.3.1): -n0 ln(1 - n3) + (n1 n2 - n1v.n2v) / (1 - n3)
       //                      + (n2^3 - 3 n2 n2v.n2v) phi3(n3)
       // with phi3 = 1 / (24 pi (1 - n3)^2) (Rosenfeld) or the modified form
-      double c2;  // 6 n2 phi3: the n2v coefficient of d[7..9]
-      d[1] = n2 * inv;
+      P c2;  // 6 n2 phi3: the n2v coefficient of d[7..9]
+      d[1] = n2 * i1;
       if constexpr (WB) {
         double g, dg;
-        wb_coeff(n3, inv, -d[0], g, dg);
-        const double p3 = g * inv36pi, dp3 = dg * inv36pi;  // phi3 and its derivative
-        c2 = 6.0 * n2 * p3;
-        if constexpr (PHI) phi += n0 * d[0] + (n1 * n2 - v12) * inv + (n2 * n2 * n2 - 3.0 * n2 * v22) * p3;
-        d[2] = n1 * inv + 3.0 * (n2 * n2 - v22) * p3;
-        d[3] = n0 * inv + (n1 * n2 - v12) * inv2 + (n2 * n2 * n2 - 3.0 * n2 * v22) * dp3;
+        wb_coeff(n3d, inv, -d0, g, dg);
+        const P p3 = (P)(g * inv36pi), dp3 = (P)(dg * inv36pi);  // phi3 and its derivative
+        c2 = (P)6 * n2 * p3;
+        if constexpr (PHI) phi += n0 * d0 + (n1 * n2 - v12) * inv + (n2 * n2 * n2 - 3.0 * n2 * v22) * p3;
+        d[2] = n1 * i1 + (P)3 * (n2 * n2 - v22) * p3;
+        d[3] = n0 * i1 + (n1 * n2 - v12) * i2 + (n2 * n2 * n2 - (P)3 * n2 * v22) * dp3;
       } else {
         // Rosenfeld: 3 phi3 = 1 / (8 pi u^2), phi3' = 1 / (12 pi u^3), 6 n2 phi3 = n2 / (4 pi u^2)
-        c2 = n2 * inv2 * inv4pi;
-        if constexpr (PHI) phi += n0 * d[0] + (n1 * n2 - v12) * inv + (n2 * n2 * n2 - 3.0 * n2 * v22) * inv2 * inv24pi;
-        d[2] = n1 * inv + (n2 * n2 - v22) * inv2 * inv8pi;
-        d[3] = n0 * inv + (n1 * n2 - v12) * inv2 + (n2 * n2 * n2 - 3.0 * n2 * v22) * inv3 * inv12pi;
+        c2 = n2 * i2 * (P)inv4pi;
+        if constexpr (PHI) phi += n0 * d0 + (n1 * n2 - v12) * inv + (n2 * n2 * n2 - 3.0 * n2 * v22) * inv2 * inv24pi;
+        d[2] = n1 * i1 + (n2 * n2 - v22) * i2 * (P)inv8pi;
+        d[3] = n0 * i1 + (n1 * n2 - v12) * i2 + (n2 * n2 * n2 - (P)3 * n2 * v22) * (P)inv3 * (P)inv12pi;
       }
-      d[4] = -a2x * inv;
-      d[5] = -a2y * inv;
-      d[6] = -a2z * inv;
-      d[7] = -a1x * inv - c2 * a2x;
-      d[8] = -a1y * inv - c2 * a2y;
-      d[9] = -a1z * inv - c2 * a2z;
+      d[4] = -a2x * i1;
+      d[5] = -a2y * i1;
+      d[6] = -a2z * i1;
+      d[7] = -a1x * i1 - c2 * a2x;
+      d[8] = -a1y * i1 - c2 * a2y;
+      d[9] = -a1z * i1 - c2 * a2z;
 #pragma unroll
       for (int q = 0; q < kFields; ++q) {
         if (h) val[q * EZ + m].y = (T)d[q];
