@@ -174,7 +174,7 @@ def cpu_all_cores(n=96):
     evaluating the benchmark recipe at n^3 (numpy's FFT runs on one thread
     per process); aggregate grid-pt*species/s over the wall time."""
     import multiprocessing as mp
-    cores = min(len(os.sched_getaffinity(0)), 32)
+    cores = min(len(os.sched_getaffinity(0)), 16)  # the host share of one GPU
     ctx = mp.get_context("spawn")   # fresh interpreters: this process has initialised the GPU
     with ctx.Pool(cores) as pool:
         pool.map(_cpu_worker, [16] * cores)  # start-up and imports, not timed
@@ -202,20 +202,21 @@ def _cpu_direct_worker(n):
 
 def bench_cpu():
     """The CPU baselines of the method's scope on the host (one JSON line):
-    the direct O(N^2) oracle at 16^3, 24^3, 32^3 and the numpy-FFT route at
-    64^3 and 256^3, each on one thread and on every core (one process per
-    core, independent evaluations: the oracle's numpy kernels run on one
+    the direct O(N^2) oracle at 16^3 and 24^3 and the numpy-FFT route at
+    64^3 and 256^3, on one thread and on every core (at most 16: one process
+    per core, independent evaluations; the oracle's numpy kernels run on one
     thread per process).  The benchmark recipe (three-species channel,
     packing 0.45, all terms) throughout."""
     import multiprocessing as mp
     import pnp_inputs as P
-    cores = min(len(os.sched_getaffinity(0)), 32)
+    cores = min(len(os.sched_getaffinity(0)), 16)  # the host share of one GPU
     out = {"host": host_info(), "results": []}
     ctx = mp.get_context("spawn")
     with ctx.Pool(cores) as pool:
         pool.map(_cpu_worker, [16] * cores)  # start-up, not timed
-        for route, n, conc in (("direct", 16, cores), ("direct", 24, cores), ("direct", 32, 1),
-                               ("fft", 64, cores), ("fft", 256, 1), ("fft", 256, min(cores, 8))):
+        for route, n, conc in (("direct", 16, 1), ("direct", 16, cores), ("direct", 24, 1),
+                               ("direct", 24, cores), ("fft", 64, cores), ("fft", 256, 1),
+                               ("fft", 256, min(cores, 8))):
             work = _cpu_direct_worker if route == "direct" else _cpu_worker
             t0 = time.perf_counter()
             if conc == 1:

@@ -392,7 +392,9 @@ void pnp_plan_destroy(pnp_plan plan);
  * mixed precision, 4 in FP64, 6 with a factor 3; 4, 2 or 6 for the
  * derivative pass) and a secondary one with half as many elements per
  * thread, twice the threads per pencil and smaller radices, where such a
- * radix plan exists (else the two are the same).  Every pass also has a
+ * radix plan exists; for the x transforms of sizes with a factor 3, twice
+ * as many (12: fewer, larger radix stages); elsewhere the two are the
+ * same.  Every pass also has a
  * default tile shape (workgroups carrying 16 pencils or rows, for
  * full-width HBM bursts on large grids) and, for grids up to 128^3, a
  * narrow one with a quarter of the pencils per workgroup and four times the
@@ -410,9 +412,9 @@ void pnp_plan_destroy(pnp_plan plan);
  * equilibrium solve, free energies, weighted densities), so an instance gets
  * the same arithmetic alone and in any batch.  Before any tuning the
  * schedule is a built-in table of the autotuner's choices measured on an
- * MI355X for each supported size and precision (at 256^3 in mixed
- * precision: the secondary schedule for the two z passes and the first y
- * pass).  The two schedules order the floating-point
+ * MI355X for each supported size and precision (at 256^3: the secondary
+ * schedule for the two z passes; at 192^3 also for the two x passes in
+ * mixed precision).  The two schedules order the floating-point
  * operations differently: results agree to rounding, not bit for bit.  The
  * tile shape is stored under (precision, n, instance-count class of the
  * launch: 1, 2-3, 4-15, >= 16); it does not change the arithmetic.  The

@@ -72,9 +72,14 @@ constexpr bool plan_ok(int len, int ept) {
 // the secondary schedule of a pass family: half the primary elements per
 // thread where that has a radix plan and stays within 1024 threads per
 // workgroup (`per` pencils per workgroup in the wide tile shape, the larger
-// one, so both shapes get the same schedule), else the primary one
-constexpr int alt_ept(int len, int prim, int per) {
-  return (plan_ok(len, prim / 2) && per * (len / (prim / 2)) <= 1024) ? prim / 2 : prim;
+// one, so both shapes get the same schedule); else, where `dbl` allows it,
+// twice the primary elements per thread (fewer, larger radix stages: on
+// lengths with a factor 3 six elements per thread leave only radix-2 stages
+// after the first); else the primary one
+constexpr int alt_ept(int len, int prim, int per, bool dbl = false) {
+  return (plan_ok(len, prim / 2) && per * (len / (prim / 2)) <= 1024) ? prim / 2
+         : (dbl && plan_ok(len, 2 * prim))                            ? 2 * prim
+                                                                       : prim;
 }
 
 template <typename T, int N, int V = 0> struct Geo {
@@ -94,7 +99,7 @@ template <typename T, int N, int V = 0> struct Geo {
   // x passes
   static constexpr int PX = narrow(pow2_divisor_le(N, sizeof(T) == 4 ? 16 : 8), V);
   static constexpr int EX0 = R3 ? 6 : (sizeof(T) == 4 ? (N >= 8 ? 8 : N) : (N >= 4 ? 4 : N));
-  static constexpr int EX = SEC ? alt_ept(N, EX0, pow2_divisor_le(N, sizeof(T) == 4 ? 16 : 8)) : EX0;
+  static constexpr int EX = SEC ? alt_ept(N, EX0, pow2_divisor_le(N, sizeof(T) == 4 ? 16 : 8), true) : EX0;
   static constexpr int TX = N / EX;
   // tiles per instance
   static constexpr int tiles_z = (N * N) / RZ;
@@ -773,8 +778,12 @@ __device__ __forceinline__ void wb_coeff(double x, double inv, double lnu, doubl
 // of instances that select the other one exit, so a launch list holding both
 // runs each variant over it and every instance gets the same arithmetic as
 // when evaluated alone
+// The FP32 Rosenfeld variant (the hot one) is held to two waves per SIMD:
+// with six elements per thread (sizes with a factor 3) the compiler would
+// otherwise take a few registers past 256 and run one wave per SIMD (a
+// 2.5x slower pass at 192^3), where two waves cost a spill of 16 registers.
 template <typename T, int N, bool PHI = false, bool WB = false, int EZD = default_ezd<T, N>(), int V = 0>
-__global__ void __launch_bounds__((GeoD<T, N, EZD, V>::RDD * GeoD<T, N, EZD, V>::TZD))
+__global__ void __launch_bounds__((GeoD<T, N, EZD, V>::RDD * GeoD<T, N, EZD, V>::TZD), (PHI || WB || sizeof(T) == 8) ? 1 : 2)
     k_zderiv(const EvalArgs* __restrict__ args) {
   using D = GeoD<T, N, EZD, V>;
   constexpr int H = D::H, TZ = D::TZD, EZ = D::EZD, RD = D::RDD;
@@ -792,8 +801,13 @@ __global__ void __launch_bounds__((GeoD<T, N, EZD, V>::RDD * GeoD<T, N, EZD, V>:
   const BufN<N> B = make_buf<stream_policy<N>()>(a.specB, spec_bytes<T>(a, kFields));
   const uint32_t fbytes = __builtin_amdgcn_readfirstlane((uint32_t)(a.fstride * sizeof(cx<T>)));
   cx<T> val[kFields * EZ];
-  TwReg<T, H, EZ> twr;  // the FFT twiddles of this lane, for all twenty transforms
-  cx<T> twk[EZ];        // the r2c / c2r twiddles W^k of this lane's elements
+  // The FFT twiddles of this lane and the r2c / c2r twiddles W^k of its
+  // elements, held in registers for all twenty transforms; with six elements
+  // per thread (sizes with a factor 3) the registers go to the values and the
+  // twiddles are read from LDS instead.
+  constexpr bool kTwRegs = EZ < 6;
+  typename std::conditional<kTwRegs, TwReg<T, H, EZ>, char>::type twr;
+  cx<T> twk[kTwRegs ? EZ : 1];
   {
     // the raw values of field q + 1 are in flight while field q is transformed;
     // those of field 0 while the twiddle tables are built
@@ -803,19 +817,33 @@ __global__ void __launch_bounds__((GeoD<T, N, EZD, V>::RDD * GeoD<T, N, EZD, V>:
     init_twiddles<T, N>(twN);
     log_table_init(logt);
     __syncthreads();
-    twr.load(t, twH);
+    if constexpr (kTwRegs) {
+      twr.load(t, twH);
 #pragma unroll
-    for (int m = 0; m < EZ; ++m) twk[m] = twN[t + TZ * m];
+      for (int m = 0; m < EZ; ++m) twk[m] = twN[t + TZ * m];
+    }
 #pragma unroll
     for (int q = 0; q < kFields; ++q) {
-      cx<T>* kc = (q & 1) ? k1 : k0;
-      cx<T>* mc = (q & 1) ? m1 : m0;
+      // with six elements per thread there is no room for a second buffer:
+      // each field's values are loaded just before its transform
+      constexpr bool kAhead = kTwRegs;
+      cx<T>* kc = (kAhead && (q & 1)) ? k1 : k0;
+      cx<T>* mc = (kAhead && (q & 1)) ? m1 : m0;
       cx<T>* kn = (q & 1) ? k0 : k1;
       cx<T>* mn = (q & 1) ? m0 : m1;
-      if (q + 1 < kFields) c2r_load<T, N, TZ, EZ>(kn, mn, t, B, (uint32_t)(q + 1) * fbytes, row);
+      if constexpr (kAhead) {
+        if (q + 1 < kFields) c2r_load<T, N, TZ, EZ>(kn, mn, t, B, (uint32_t)(q + 1) * fbytes, row);
+      } else {
+        if (q > 0) c2r_load<T, N, TZ, EZ>(k0, m0, t, B, (uint32_t)q * fbytes, row);
+      }
       // the z component of each vector density is i s_z Q_b, formed here
-      c2r_combine_r<T, N, TZ, EZ>(val + q * EZ, kc, mc, t, twk, q == kSlotZ || q == kSlotZ + kVecStride);
-      fft_pencil<T, N / 2, EZ, false>(val + q * EZ, t, twr, lp);
+      if constexpr (kTwRegs) {
+        c2r_combine_r<T, N, TZ, EZ>(val + q * EZ, kc, mc, t, twk, q == kSlotZ || q == kSlotZ + kVecStride);
+        fft_pencil<T, N / 2, EZ, false>(val + q * EZ, t, twr, lp);
+      } else {
+        c2r_combine<T, N, TZ, EZ>(val + q * EZ, kc, mc, t, twN, q == kSlotZ || q == kSlotZ + kVecStride);
+        fft_pencil<T, N / 2, EZ, false>(val + q * EZ, t, (const cx<T>*)twH, lp);
+      }
     }
   }
   if (a.ext_n != 0) {
@@ -902,9 +930,14 @@ __global__ void __launch_bounds__((GeoD<T, N, EZD, V>::RDD * GeoD<T, N, EZD, V>:
   }
 #pragma unroll
   for (int q = 0; q < kFields; ++q) {
-    fft_pencil<T, N / 2, EZ, true>(val + q * EZ, t, twr, lp);
     // the z components of the vector derivatives leave as i s_z F_z
-    r2c_post_r<T, N, TZ, EZ>(val + q * EZ, t, twk, lrow, B, q * fbytes, row, q == kSlotZ || q == kSlotZ + kVecStride);
+    if constexpr (kTwRegs) {
+      fft_pencil<T, N / 2, EZ, true>(val + q * EZ, t, twr, lp);
+      r2c_post_r<T, N, TZ, EZ>(val + q * EZ, t, twk, lrow, B, q * fbytes, row, q == kSlotZ || q == kSlotZ + kVecStride);
+    } else {
+      fft_pencil<T, N / 2, EZ, true>(val + q * EZ, t, (const cx<T>*)twH, lp);
+      r2c_post<T, N, TZ, EZ>(val + q * EZ, t, twN, lrow, B, q * fbytes, row, q == kSlotZ || q == kSlotZ + kVecStride);
+    }
     __builtin_amdgcn_sched_barrier(0);
   }
   if (bad) raise_status(a.status, bad, badidx);
