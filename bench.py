@@ -6,8 +6,9 @@ A step is one evaluation of beta mu_ex (all nine passes: weighted densities,
 FMT derivatives, back-convolution, electrostatic-correlation and square-well
 terms, Slotboom factors) of one synthetic problem whose densities are already
 resident in HBM.  The default workload is the 256^3 three-species channel
-electrolyte at packing fraction 0.45 in mixed precision (FP32 FFTs and weight
-multiplies, FP64 derivatives, constants and exp).  One JSON line is printed.
+electrolyte at packing fraction 0.45 in mixed precision (FP32 FFTs, weight
+multiplies and derivative products; FP64 ln(1 - n3), powers of 1/(1 - n3),
+constants and exp).  One JSON line is printed.
 
 Besides throughput the default line carries:
   * a per-pass table from a run with every pass bracketed by HIP events; the
@@ -23,7 +24,7 @@ Besides throughput the default line carries:
     against the same trace on the plain FP64 path;
   * `cpu_baseline`: the oracle timed on the host (numpy-FFT route on the
     full problem, one thread; the direct O(N^2) route at 16^3; all host cores
-    on concurrent evaluations of a 96^3 sample).
+    (at most 16) on concurrent evaluations of a 128^3 sample).
 """
 import argparse
 import itertools
@@ -364,7 +365,7 @@ def bench_batch(ev, steps, warmup):
         "metric": "mu_ex grid-pts*species/s, 64-instance uneven batch", "value": pts / (ms / 1e3),
         "unit": "grid-pt*species/s", "n_gpus": 1, "steps": steps, "warmup": warmup, "ms_per_step": ms,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32 FFT/weights + f64 derivatives/accumulation", "data": "synthetic (seeded)",
+        "dtype": "f32 FFTs/weights/products + f64 ln(1-n3), 1/(1-n3)^k, constants, output", "data": "synthetic (seeded)",
         "config": {"workload": "64 instances, n in {32,48,64,96,128}, S in {2,3,4}, T 250-350 K, HS+EC+SW, mixed",
                    "sizes": hist, "grid_pt_species": pts},
         "hbm": {"model_bytes_per_step": bytes_model, "GBps": bytes_model / 1e9 / (ms / 1e3),
@@ -421,7 +422,7 @@ def bench_aperiodic(ev, steps, warmup):
         "metric": "aperiodic mu_ex: domain grid-pts*species/s", "value": pts / (ms / 1e3),
         "unit": "grid-pt*species/s", "n_gpus": 1, "steps": steps, "warmup": warmup, "ms_per_step": ms,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32 FFT/weights + f64 derivatives/accumulation", "data": "synthetic (seeded)",
+        "dtype": "f32 FFTs/weights/products + f64 ln(1-n3), 1/(1-n3)^k, constants, output", "data": "synthetic (seeded)",
         "config": {"workload": "aperiodic channel electrolyte, 128^3 domain on the doubled 256^3 grid, S=3, "
                                "eta_max=0.45, HS+EC+SW, mixed"},
         "doubled_grid_pt_species_per_s": 8 * pts / (ms / 1e3),
@@ -629,7 +630,7 @@ def bench_serve(ev, duration, rate):
         "metric": "served requests: p50/p99 latency (arrival to done) and grid-pts*species/s",
         "value": work / span, "unit": "grid-pt*species/s", "n_gpus": 1, "steps": out["trace"]["requests"],
         "warmup": 0, "ms_per_step": span * 1e3 / max(1, out["trace"]["requests"]), "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f32 FFT/weights + f64 derivatives/accumulation",
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32 FFTs/weights/products + f64 ln(1-n3), 1/(1-n3)^k, constants, output",
         "data": "synthetic (seeded Poisson trace)",
         "config": {"workload": f"Poisson {rate:g} req/s for {duration:g} s, n in {{48,64,96,128,192}}, "
                                "S in {2,3,4}, 5 steps per request, HS+EC+SW, mixed, budget 32 GiB"},
@@ -796,7 +797,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32 FFT/weights + f64 derivatives/accumulation" if prec == 1 else "f64",
+        "dtype": "f32 FFTs/weights/products + f64 ln(1-n3), 1/(1-n3)^k, constants, output" if prec == 1 else "f64",
         "data": "synthetic (seeded)",
         "config": {"workload": desc, "grid": n, "species": S, "global_batch": 1,
                    "precision": "mixed" if prec == 1 else "fp64"},
