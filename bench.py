@@ -431,10 +431,11 @@ def bench_aperiodic(ev, steps, warmup):
     }
 
 
-def sphere_stencil_size(r, k):
+def sphere_stencil_size(r, k, cubic=False):
     """Integer offsets of the merged stencil of one sphere (radius r in grid
-    units, k-by-k rule): the distinct trilinear corners with nonzero weight
-    over all nodes.  Used only to count the kernel's flops."""
+    units, k-by-k rule): the distinct interpolation points (trilinear
+    corners, or the tricubic 4 x 4 x 4 points) with nonzero weight over all
+    nodes.  Used only to count the kernel's flops."""
     import numpy as np
     x, _ = np.polynomial.legendre.leggauss(k)
     seen = set()
@@ -445,8 +446,10 @@ def sphere_stencil_size(r, k):
             p = r * np.array([math.cos(th) * math.sin(ph), math.sin(th) * math.sin(ph), math.cos(ph)])
             b = np.floor(p)
             t = p - b
-            for c in itertools.product((0, 1), repeat=3):
-                w = np.prod([t[a] if c[a] else 1.0 - t[a] for a in range(3)])
+            offs = (-1, 0, 1, 2) if cubic else (0, 1)
+            for c in itertools.product(offs, repeat=3):
+                # a point carries weight unless t sits exactly on a node of that axis's interpolant
+                w = np.prod([np.prod([t[a] - o for o in offs if o != c[a]]) for a in range(3)])
                 if w != 0.0:
                     seen.add(tuple(int(v) for v in b + np.array(c)))
     return len(seen)
@@ -475,19 +478,23 @@ def bench_sphere(ev, steps, warmup, no_cpu):
     entries = [sphere_stencil_size(R / prob.h, k) for R in radii]
     flops = 8.0 * n3 * sum(entries)
     hbm = n3 * prob.S * (8 + 4 * 8)
+    entries_cubic = [sphere_stencil_size(R / prob.h, k, cubic=True) for R in radii]
+    flops_cubic = 8.0 * n3 * sum(entries_cubic)
     res = {}
-    for name, prec in (("mixed", MIXED), ("fp64", FP64)):
+    from paper_1407_0674_amd import FLAG_CUBIC
+    for name, prec, fl, fo in (("mixed", MIXED, 0, flops), ("fp64", FP64, 0, flops),
+                               ("mixed_cubic", MIXED, FLAG_CUBIC, flops_cubic)):
         for _ in range(warmup):
-            ev.sphere_quadrature(rd, radii, prob.h, k, precision=prec, out=out)
+            ev.sphere_quadrature(rd, radii, prob.h, k, precision=prec, flags=fl, out=out)
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
         for _ in range(steps):
-            ev.sphere_quadrature(rd, radii, prob.h, k, precision=prec, flags=FLAG_ASYNC, out=out)
+            ev.sphere_quadrature(rd, radii, prob.h, k, precision=prec, flags=FLAG_ASYNC | fl, out=out)
         e1.record()
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / steps
-        res[name] = {"ms": ms, "tflops": flops / (ms / 1e3) / 1e12, "hbm_GBps": hbm / (ms / 1e3) / 1e9}
+        res[name] = {"ms": ms, "tflops": fo / (ms / 1e3) / 1e12, "hbm_GBps": hbm / (ms / 1e3) / 1e9}
     ev.sphere_quadrature(rd, radii, prob.h, k, precision=MIXED, out=out)   # waits: errors surface here
     del out, rd
     torch.cuda.empty_cache()
@@ -510,9 +517,12 @@ def bench_sphere(ev, steps, warmup, no_cpu):
     fd = torch.from_numpy(f[None].copy()).to("cuda:0")
     acc = {"spectral_weights": float(np.max(np.abs(ev.weighted_densities(bprob, fd, precision=FP64)[2].cpu().numpy()
                                                    - I_ex)) / scale)}
+    from paper_1407_0674_amd import FLAG_CUBIC
     for kk in (4, 8, 16):
         got = ev.sphere_quadrature(fd, [R], h, kk, precision=FP64)[0, 0].cpu().numpy()
         acc[f"quadrature_k{kk}"] = float(np.max(np.abs(got - I_ex)) / scale)
+        got = ev.sphere_quadrature(fd, [R], h, kk, precision=FP64, flags=FLAG_CUBIC)[0, 0].cpu().numpy()
+        acc[f"quadrature_cubic_k{kk}"] = float(np.max(np.abs(got - I_ex)) / scale)
 
     cpu = None
     if not no_cpu:
@@ -538,6 +548,8 @@ def bench_sphere(ev, steps, warmup, no_cpu):
         "roofline": {"bound": "alu", "achieved": res["mixed"]["tflops"], "peak": 157.3, "unit": "TFLOP/s",
                      "frac": res["mixed"]["tflops"] / 157.3, "traffic": traffic_from_profile("sphere_quad", 1)},
         "fp64": dict(res["fp64"], frac_of_78_6=res["fp64"]["tflops"] / 78.6),
+        "mixed_cubic": dict(res["mixed_cubic"], stencil_offsets=entries_cubic,
+                            frac_of_157_3=res["mixed_cubic"]["tflops"] / 157.3),
         "hbm_GBps_effective": res["mixed"]["hbm_GBps"],
         "accuracy_vs_exact_gaussian_bump_64": acc,
         "cpu_baseline": cpu,

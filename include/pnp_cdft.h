@@ -109,10 +109,11 @@ enum {
 enum {
   PNP_FLAG_ASYNC = 1,     /* do not wait for the status word; read it later with
                              pnp_read_status() */
-  PNP_FLAG_APERIODIC = 2  /* the grid is the domain of a non-periodic problem
+  PNP_FLAG_APERIODIC = 2, /* the grid is the domain of a non-periodic problem
                              (Sec. 3.4): every convolution integrates over the
-                             domain only, its integrand (rho, or rho - rho_bulk
-                             for the EC term) zero outside, and runs on the
+                             domain only, its integrand (rho, rho - rho_bulk
+                             for the EC term, dPhi/dn_alpha for the hard-sphere
+                             back-convolution) zero outside, and runs on the
                              doubled grid (2n)^3 of the same spacing with the
                              domain at its corner; results are the domain's.
                              n may be any size whose double is supported
@@ -120,6 +121,10 @@ enum {
                              pnp_cdft_mu_ex and pnp_workspace_bytes only;
                              pnp_bulk_mu_ex ignores it; every other entry
                              point returns PNP_E_ARG. */
+  PNP_FLAG_CUBIC = 4      /* pnp_sphere_quadrature only: the integrand between
+                             grid points is the tricubic interpolant (Lagrange
+                             cubics through the 4 x 4 x 4 surrounding points)
+                             instead of the trilinear one */
 };
 
 typedef struct pnp_ctx_s* pnp_ctx;
@@ -287,8 +292,10 @@ pnp_status pnp_weighted_densities(pnp_ctx ctx, const pnp_grid* grid, int32_t S,
  * n_ij = (cos theta_i sin phi_j, sin theta_i sin phi_j, cos phi_j), over
  * theta_i = 2 pi i / k (weights 2 pi / k) and the k Gauss-Legendre points
  * phi_j of [0, pi]; f between grid points is the trilinear interpolant of
- * the grid values.  The paper fixes neither the 1D rules nor the
- * interpolation; these are the readings taken.  I_a is the correlation with
+ * the grid values (error O(h^2)), or with PNP_FLAG_CUBIC the tricubic one
+ * through the 4 x 4 x 4 surrounding points (Lagrange cubics on the offsets
+ * -1, 0, 1, 2 of each axis; error O(h^4)).  The paper fixes neither the 1D
+ * rules nor the interpolation; these are the readings taken.  I_a is the correlation with
  * the vector weight x/|x| delta(|x| - R) (x = r' - r), the convention of
  * pnp_weighted_densities, so with R_s = d_s / 2:
  *   n2 = sum_s I_s, n1 = sum_s I_s / (4 pi R_s), n0 = sum_s I_s / (4 pi R_s^2),
@@ -297,16 +304,18 @@ pnp_status pnp_weighted_densities(pnp_ctx ctx, const pnp_grid* grid, int32_t S,
  *   F          number of fields, 1..64
  *   f          device, float64 [F][nx][ny][nz], z fastest; read-only
  *   radius     host, F radii [nm], 0 < R <= 16 h; the stencil reach
- *              (about R / h + 1 grid points) must fit the LDS tile: up to 11
- *              points in PNP_MIXED, 8 in PNP_FP64 (else PNP_E_UNSUPPORTED_SIZE);
+ *              (about R / h + 1 grid points, one more with PNP_FLAG_CUBIC)
+ *              must fit the LDS tile: up to 11 points in PNP_MIXED, 8 in
+ *              PNP_FP64 (else PNP_E_UNSUPPORTED_SIZE);
  *              reaches above 4 (FP64) or 7 (mixed) run with one workgroup
  *              per compute unit
  *   order      k in [1, 64] (k*k nodes per sphere)
  *   precision  PNP_FP64 (double arithmetic) or PNP_MIXED (float arithmetic,
  *              float weights; inputs and outputs stay double)
  *   flags      PNP_FLAG_APERIODIC: f is zero outside the grid (the paper's
- *              zero extension); otherwise periodic images.  PNP_FLAG_ASYNC:
- *              do not wait for the kernel.
+ *              zero extension); otherwise periodic images.  PNP_FLAG_CUBIC:
+ *              tricubic interpolation.  PNP_FLAG_ASYNC: do not wait for the
+ *              kernel.
  *   out        device, float64 [F][4][nx][ny][nz]: (I, I_x, I_y, I_z) per field
  * The stencil (at most a few hundred offsets per field for R / h <= 4) is
  * built on the host in double and copied to the context's ring on `stream`

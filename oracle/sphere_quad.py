@@ -17,7 +17,10 @@ The readings taken here:
   * phi: k Gauss-Legendre points mapped from [-1, 1] onto [0, pi], weights
     scaled by pi / 2, with sin(phi_j) in the integrand as in the paper's sum;
   * the integrand between grid points: trilinear interpolation of the
-    grid values (exact for affine fields);
+    grid values (exact for affine fields), or, with cubic=True, the
+    tricubic interpolant through the 4 x 4 x 4 grid points around the node
+    (Lagrange cubics on the offsets -1, 0, 1, 2 of each axis: exact for
+    polynomials of degree 3 in each coordinate);
   * outside the grid: periodic images (the periodic box of the rest of the
     evaluation), or zero (the paper's zero extension; `aperiodic=True`).
 
@@ -68,29 +71,44 @@ def _shifted(f, base, aperiodic):
     return out
 
 
-def interpolate_shifted(f, p, aperiodic=False):
-    """Trilinear interpolant of the grid function f at r + p for every grid point r.
+def axis_weights(t, cubic=False):
+    """Interpolation offsets along one axis and their weights at fraction t
+    (the node lies at base + t, base = floor): linear, the two points
+    (0, 1) with (1 - t, t); cubic, the four points (-1, 0, 1, 2) with the
+    Lagrange cubics through them evaluated at t.  t may be an array."""
+    t = np.asarray(t, dtype=np.float64)
+    if not cubic:
+        return (0, 1), (1.0 - t, t)
+    return (-1, 0, 1, 2), (-t * (t - 1.0) * (t - 2.0) / 6.0,
+                           (t + 1.0) * (t - 1.0) * (t - 2.0) / 2.0,
+                           -(t + 1.0) * t * (t - 2.0) / 2.0,
+                           (t + 1.0) * t * (t - 1.0) / 6.0)
 
-    p is a displacement in grid units (3 floats); the eight corners of the
-    cell that holds r + p are weighted by the products of the fractional
-    distances, as in the textbook trilinear formula.
+
+def interpolate_shifted(f, p, aperiodic=False, cubic=False):
+    """Interpolant of the grid function f at r + p for every grid point r.
+
+    p is a displacement in grid units (3 floats).  Trilinear: the eight
+    corners of the cell that holds r + p, weighted by the products of the
+    fractional distances (the textbook formula); cubic: the products of the
+    per-axis Lagrange weights of `axis_weights` over 4 x 4 x 4 points.
     """
     p = np.asarray(p, dtype=np.float64)
     base = np.floor(p).astype(np.int64)
     t = p - base
+    offs = [axis_weights(t[a], cubic) for a in range(3)]
     out = np.zeros_like(f)
-    for cx in (0, 1):
-        for cy in (0, 1):
-            for cz in (0, 1):
-                wgt = ((t[0] if cx else 1.0 - t[0]) * (t[1] if cy else 1.0 - t[1])
-                       * (t[2] if cz else 1.0 - t[2]))
+    for ox, wx in zip(*offs[0]):
+        for oy, wy in zip(*offs[1]):
+            for oz, wz in zip(*offs[2]):
+                wgt = float(wx * wy * wz)
                 if wgt == 0.0:
                     continue
-                out += wgt * _shifted(f, base + np.array([cx, cy, cz]), aperiodic)
+                out += wgt * _shifted(f, base + np.array([ox, oy, oz]), aperiodic)
     return out
 
 
-def shell_integrals(f, R, h, k, aperiodic=False):
+def shell_integrals(f, R, h, k, aperiodic=False, cubic=False):
     """Sec. 3.5 product quadrature of one field on the sphere of radius R about every grid point.
 
     f: [nx, ny, nz] grid values (z fastest); R, h in the same length unit.
@@ -109,19 +127,19 @@ def shell_integrals(f, R, h, k, aperiodic=False):
                           math.sin(theta[i]) * math.sin(phi[j]),
                           math.cos(phi[j])])
             weight = R * R * math.sin(phi[j]) * w_theta[i] * w_phi[j]
-            g = interpolate_shifted(f, (R / h) * n, aperiodic)
+            g = interpolate_shifted(f, (R / h) * n, aperiodic, cubic)
             scalar += weight * g
             for a in range(3):
                 vector[a] += (weight * n[a]) * g
     return scalar, vector
 
 
-def shell_integrals_at(f, R, h, k, points, aperiodic=False):
+def shell_integrals_at(f, R, h, k, points, aperiodic=False, cubic=False):
     """The same sums as `shell_integrals`, at chosen grid points only.
 
     points: [P, 3] integer grid indices.  Each node position r + R n / h is
-    interpolated on its own (floor, fractions, eight corners), for sampled
-    checks on grids too large for the whole-grid form.
+    interpolated on its own (floor, fractions, eight or 64 points), for
+    sampled checks on grids too large for the whole-grid form.
     Returns (I [P], Iv [3, P]).
     """
     f = np.asarray(f, dtype=np.float64)
@@ -140,11 +158,12 @@ def shell_integrals_at(f, R, h, k, points, aperiodic=False):
             base = np.floor(pos).astype(np.int64)
             t = pos - base
             g = np.zeros(len(pts))
-            for cx in (0, 1):
-                for cy in (0, 1):
-                    for cz in (0, 1):
+            offs = [axis_weights(t[:, a], cubic) for a in range(3)]
+            for cx, wx in zip(*offs[0]):
+                for cy, wy in zip(*offs[1]):
+                    for cz, wz in zip(*offs[2]):
                         c = np.array([cx, cy, cz])
-                        wgt = np.prod(np.where(c == 1, t, 1.0 - t), axis=1)
+                        wgt = wx * wy * wz
                         idx = base + c
                         if aperiodic:
                             inside = np.all((idx >= 0) & (idx < shape), axis=1)
@@ -160,7 +179,7 @@ def shell_integrals_at(f, R, h, k, points, aperiodic=False):
     return scalar, vector
 
 
-def shell_weighted_densities(rho, radii, h, k, aperiodic=False):
+def shell_weighted_densities(rho, radii, h, k, aperiodic=False, cubic=False):
     """n0, n1, n2, n1v, n2v of Sec. 2.3.1 from the sphere quadrature (n3 is a volume integral, not here).
 
     rho: [S, nx, ny, nz]; radii: S sphere radii R_i = d_i / 2.
@@ -171,7 +190,7 @@ def shell_weighted_densities(rho, radii, h, k, aperiodic=False):
     acc = {"n0": np.zeros(shape), "n1": np.zeros(shape), "n2": np.zeros(shape),
            "n1v": np.zeros((3,) + shape), "n2v": np.zeros((3,) + shape)}
     for i, R in enumerate(radii):
-        I, Iv = shell_integrals(rho[i], R, h, k, aperiodic)
+        I, Iv = shell_integrals(rho[i], R, h, k, aperiodic, cubic)
         acc["n2"] += I
         acc["n1"] += I / (4.0 * math.pi * R)
         acc["n0"] += I / (4.0 * math.pi * R * R)

@@ -16,6 +16,7 @@ TERM_HS, TERM_EC, TERM_SW, TERM_ALL, TERM_HS_WB = 1, 2, 4, 7, 8
 FP64, MIXED = 0, 1
 FLAG_ASYNC = 1
 FLAG_APERIODIC = 2  # non-periodic domain: zero extension onto the doubled grid
+FLAG_CUBIC = 4  # sphere quadrature: tricubic instead of trilinear interpolation
 
 STATUS_NAMES = {
     0: "PNP_OK", -1: "PNP_E_ARG", -2: "PNP_E_UNSUPPORTED_SIZE", -3: "PNP_E_NOMEM",

@@ -226,6 +226,7 @@ pnp_status validate(pnp_ctx ctx, const pnp_grid* g, int S, const pnp_species* sp
   if (!ctx) return PNP_E_ARG;
   if (!g || !sp || !p) return fail(ctx, PNP_E_ARG, "null grid, species or params");
   if (g->nx != g->ny || g->ny != g->nz) return fail(ctx, PNP_E_UNSUPPORTED_SIZE, "grid must be cubic (nx = ny = nz)");
+  if (p->flags & ~(uint32_t)(PNP_FLAG_ASYNC | PNP_FLAG_APERIODIC)) return fail(ctx, PNP_E_ARG, "unsupported flag");
   const bool aperiodic = p->flags & PNP_FLAG_APERIODIC;
   if (aperiodic && !aperiodic_ok) return fail(ctx, PNP_E_ARG, "PNP_FLAG_APERIODIC is not available here");
   if (aperiodic ? !(g->nx >= 4 && g->nx <= 128 && size_ok(2 * g->nx)) : !size_ok(g->nx))
@@ -1117,14 +1118,15 @@ pnp_status pnp_sphere_quadrature(pnp_ctx ctx, const pnp_grid* g, int32_t F, cons
   if (F < 1 || F > kQuadMaxFields) return fail(ctx, PNP_E_ARG, "field count must be in [1, 64]");
   if (order < 1 || order > 64) return fail(ctx, PNP_E_ARG, "order must be in [1, 64]");
   if (precision != PNP_FP64 && precision != PNP_MIXED) return fail(ctx, PNP_E_ARG, "bad precision");
-  if (flags & ~(uint32_t)(PNP_FLAG_APERIODIC | PNP_FLAG_ASYNC)) return fail(ctx, PNP_E_ARG, "unsupported flag");
+  if (flags & ~(uint32_t)(PNP_FLAG_APERIODIC | PNP_FLAG_ASYNC | PNP_FLAG_CUBIC))
+    return fail(ctx, PNP_E_ARG, "unsupported flag");
   for (int i = 0; i < F; ++i)
     if (!(radius[i] > 0.0) || !std::isfinite(radius[i]) || radius[i] / g->h > 16.0)
       return fail(ctx, PNP_E_ARG, "field " + std::to_string(i) + ": radius must be in (0, 16 h]");
   std::vector<QuadStencil> st;
   int H = 0;
   for (int i = 0; i < F; ++i) {
-    st.push_back(build_quad_stencil(radius[i] / g->h, radius[i], order));
+    st.push_back(build_quad_stencil(radius[i] / g->h, radius[i], order, (flags & PNP_FLAG_CUBIC) != 0));
     H = std::max(H, st.back().reach);
   }
   H = std::max(H, 1);

@@ -220,12 +220,30 @@ struct QuadStencil {
   int reach = 0;          // max |offset|
 };
 
+// Interpolation points along one axis at fraction t of a cell (the node at
+// base + t): trilinear, offsets 0 and 1 with 1 - t and t; tricubic, offsets
+// -1, 0, 1, 2 with the Lagrange cubics through those points at t.  Returns
+// the count; off[] and w[] receive the offsets and weights.
+inline int interp_axis(double t, bool cubic, int* off, double* w) {
+  if (!cubic) {
+    off[0] = 0; w[0] = 1.0 - t;
+    off[1] = 1; w[1] = t;
+    return 2;
+  }
+  off[0] = -1; w[0] = -t * (t - 1.0) * (t - 2.0) / 6.0;
+  off[1] = 0;  w[1] = (t + 1.0) * (t - 1.0) * (t - 2.0) / 2.0;
+  off[2] = 1;  w[2] = -(t + 1.0) * t * (t - 2.0) / 2.0;
+  off[3] = 2;  w[3] = (t + 1.0) * t * (t - 1.0) / 6.0;
+  return 4;
+}
+
 // The k-by-k rule of one sphere of radius r (grid units) and physical radius
-// R, merged over the trilinear corners of every node into integer offsets.
-inline QuadStencil build_quad_stencil(double r, double R, int k) {
+// R, merged over the interpolation points of every node (8 trilinear
+// corners, or 64 tricubic points) into integer offsets.
+inline QuadStencil build_quad_stencil(double r, double R, int k, bool cubic) {
   std::vector<double> gx, gw;
   gauss_legendre(k, gx, gw);
-  const int Hc = (int)std::floor(r) + 1;
+  const int Hc = (int)std::floor(r) + (cubic ? 2 : 1);
   const int side = 2 * Hc + 1;
   std::vector<double> acc((size_t)side * side * side * 4, 0.0);
   std::vector<char> hit((size_t)side * side * side, 0);
@@ -235,20 +253,19 @@ inline QuadStencil build_quad_stencil(double r, double R, int k) {
       const double ph = 0.5 * M_PI * (gx[j] + 1.0), wph = 0.5 * M_PI * gw[j];
       const double n[3] = {std::cos(th) * std::sin(ph), std::sin(th) * std::sin(ph), std::cos(ph)};
       const double W = R * R * std::sin(ph) * wth * wph;
-      int b[3];
-      double fr[3];
+      int b[3], off[3][4], cnt[3];
+      double wa[3][4];
       for (int a = 0; a < 3; ++a) {
         const double p = r * n[a];
         b[a] = (int)std::floor(p);
-        fr[a] = p - b[a];
+        cnt[a] = interp_axis(p - b[a], cubic, off[a], wa[a]);
       }
-      for (int cx = 0; cx < 2; ++cx)
-        for (int cy = 0; cy < 2; ++cy)
-          for (int cz = 0; cz < 2; ++cz) {
-            const double tw = (cx ? fr[0] : 1.0 - fr[0]) * (cy ? fr[1] : 1.0 - fr[1]) *
-                              (cz ? fr[2] : 1.0 - fr[2]);
+      for (int cx = 0; cx < cnt[0]; ++cx)
+        for (int cy = 0; cy < cnt[1]; ++cy)
+          for (int cz = 0; cz < cnt[2]; ++cz) {
+            const double tw = wa[0][cx] * wa[1][cy] * wa[2][cz];
             if (tw == 0.0) continue;
-            const int ox = b[0] + cx + Hc, oy = b[1] + cy + Hc, oz = b[2] + cz + Hc;
+            const int ox = b[0] + off[0][cx] + Hc, oy = b[1] + off[1][cy] + Hc, oz = b[2] + off[2][cz] + Hc;
             const size_t cell = ((size_t)ox * side + oy) * side + oz;
             hit[cell] = 1;
             acc[cell * 4 + 0] += W * tw;

@@ -1,8 +1,9 @@
 """GPU sphere quadrature (pnp_sphere_quadrature, Sec. 3.5) against the oracle.
 
-The kernel merges the k-by-k product rule and the trilinear corners into one
-integer stencil on the host and sums it from an LDS tile; the oracle sums the
-rule node by node.  Parity is element by element on small grids (ragged in
+The kernel merges the k-by-k product rule and the interpolation points
+(trilinear corners, or the tricubic 4 x 4 x 4 points with PNP_FLAG_CUBIC)
+into one integer stencil on the host and sums it from an LDS tile; the
+oracle sums the rule node by node.  Parity is element by element on small grids (ragged in
 every axis against the 8 x 8 x 32 output tile, smaller than the sphere, one
 point, 64 fields, every order class, both boundary modes), on sampled points
 at 256^3 with the benchmark's densities and radii, and at the limits of the
@@ -16,7 +17,7 @@ import pytest
 import pnp_inputs as P
 from conftest import to_dev
 from oracle.sphere_quad import gaussian_bump_shell, shell_integrals, shell_integrals_at
-from paper_1407_0674_amd import FLAG_APERIODIC, FP64, MIXED, PnpError
+from paper_1407_0674_amd import FLAG_APERIODIC, FLAG_CUBIC, FP64, MIXED, PnpError
 
 pytestmark = pytest.mark.gpu
 
@@ -24,9 +25,9 @@ FLAG_ASYNC = 1
 TOL = {FP64: 1e-12, MIXED: 1e-5}
 
 
-def _compare(got, f, radii, h, k, aperiodic, tol):
+def _compare(got, f, radii, h, k, aperiodic, tol, cubic=False):
     for i, R in enumerate(radii):
-        I, Iv = shell_integrals(f[i], R, h, k, aperiodic=aperiodic)
+        I, Iv = shell_integrals(f[i], R, h, k, aperiodic=aperiodic, cubic=cubic)
         scale = max(float(np.max(np.abs(I))), 1e-300)
         assert np.max(np.abs(got[i, 0] - I)) / scale < tol, (i, "I")
         for a in range(3):
@@ -116,6 +117,69 @@ def test_fullsize_sampled(ev, precision, aperiodic):
     torch.cuda.empty_cache()
 
 
+@pytest.mark.parametrize("precision", [FP64, MIXED])
+@pytest.mark.parametrize("aperiodic", [False, True])
+def test_cubic_parity_benchmark_radii_ragged_grid(ev, precision, aperiodic):
+    shape, h, radii, k = (20, 12, 40), 0.05, [0.075, 0.15, 0.2], 8
+    f = _fields(shape, 3, 21)
+    flags = FLAG_CUBIC | (FLAG_APERIODIC if aperiodic else 0)
+    got = ev.sphere_quadrature(to_dev(f), radii, h, k, precision=precision, flags=flags).cpu().numpy()
+    _compare(got, f, radii, h, k, aperiodic, TOL[precision], cubic=True)
+
+
+@pytest.mark.parametrize("shape,radius,k,aperiodic", [
+    ((33, 17, 65), 0.17, 5, False),
+    ((3, 5, 2), 0.15, 4, False),
+    ((3, 5, 2), 0.15, 4, True),
+    ((1, 1, 1), 0.12, 3, True),
+    ((16, 16, 16), 0.13, 1, False),
+])
+def test_cubic_parity_shapes(ev, shape, radius, k, aperiodic):
+    h = 0.05
+    f = _fields(shape, 1, 22)
+    flags = FLAG_CUBIC | (FLAG_APERIODIC if aperiodic else 0)
+    got = ev.sphere_quadrature(to_dev(f), [radius], h, k, precision=FP64, flags=flags).cpu().numpy()
+    _compare(got, f, [radius], h, k, aperiodic, TOL[FP64], cubic=True)
+
+
+@pytest.mark.parametrize("precision,ratio", [(MIXED, 5.9), (FP64, 2.9), (MIXED, 9.9), (FP64, 6.9)])
+def test_cubic_largest_reach(ev, precision, ratio):
+    # one point less of radius than the trilinear stencil at each tile size
+    shape, h, k = (12, 10, 36), 0.05, 8
+    f = _fields(shape, 2, 23)
+    radii = [ratio * h, 0.5 * h]
+    got = ev.sphere_quadrature(to_dev(f), radii, h, k, precision=precision, flags=FLAG_CUBIC).cpu().numpy()
+    _compare(got, f, radii, h, k, False, TOL[precision], cubic=True)
+
+
+def test_cubic_gaussian_bump_fourth_order(ev):
+    """With the tricubic interpolant the kernel's error against the exact
+    sphere integrals of the Gaussian bump falls as h^4 (about 16x when h
+    halves) and lies far below the trilinear one."""
+    errs, lin = [], []
+    for n in (24, 48):
+        L, s, R = 4.8, 0.3, 0.25
+        h = L / n
+        x = h * np.arange(n)
+        c = np.array([L / 2, L / 2 + 0.5 * h, L / 2 - 0.3 * h])
+        X, Y, Z = np.meshgrid(x, x, x, indexing="ij")
+        d = np.sqrt((X - c[0]) ** 2 + (Y - c[1]) ** 2 + (Z - c[2]) ** 2)
+        f = to_dev(np.exp(-d * d / (2 * s * s))[None])
+        I_ex, _ = gaussian_bump_shell(d, R, s)
+        got = ev.sphere_quadrature(f, [R], h, 16, precision=FP64, flags=FLAG_CUBIC).cpu().numpy()
+        errs.append(np.max(np.abs(got[0, 0] - I_ex)) / np.max(I_ex))
+        got1 = ev.sphere_quadrature(f, [R], h, 16, precision=FP64).cpu().numpy()
+        lin.append(np.max(np.abs(got1[0, 0] - I_ex)) / np.max(I_ex))
+    assert errs[0] < 0.25 * lin[0] and errs[1] < 0.1 * lin[1]
+    assert 9.0 < errs[0] / errs[1] < 25.0, errs
+
+
+def test_cubic_flag_is_refused_by_the_evaluation(ev):
+    prob, rho = P.channel_problem(16, 2401)
+    with pytest.raises(PnpError, match="flag"):
+        ev.mu_ex(prob, to_dev(rho), flags=FLAG_CUBIC)
+
+
 def test_async_and_repeat_bit_identical(ev):
     import torch
     shape, h, radii, k = (24, 24, 24), 0.05, [0.075, 0.2], 8
@@ -152,7 +216,9 @@ def test_gaussian_bump_against_closed_form(ev):
     (dict(radius=[0.0]), "radius"),
     (dict(radius=[-0.1]), "radius"),
     (dict(radius=[17 * 0.05]), "radius"),
-    (dict(flags=4), "flag"),
+    (dict(flags=8), "flag"),
+    (dict(radius=[7.2 * 0.05], precision=FP64, flags=FLAG_CUBIC), "LDS"),
+    (dict(radius=[10.6 * 0.05], precision=MIXED, flags=FLAG_CUBIC), "LDS"),
     (dict(precision=7), "precision"),
     (dict(radius=[8.2 * 0.05], precision=FP64), "LDS"),
     (dict(radius=[11.6 * 0.05], precision=MIXED), "LDS"),

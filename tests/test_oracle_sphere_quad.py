@@ -55,7 +55,49 @@ def test_affine_field_interior():
         assert np.max(np.abs(Iv[ax][s] - want)) < 1e-11 * 4.0 * math.pi * R ** 3
 
 
-def _bump_errors(n, k=16):
+def test_cubic_weights_reproduce_cubics():
+    # the tricubic interpolant is exact for every polynomial of degree <= 3 per axis
+    # (a wrong Lagrange coefficient breaks one of these monomials)
+    rng = np.random.default_rng(11)
+    n = 12
+    i = np.arange(n, dtype=np.float64)
+    X, Y, Z = np.meshgrid(i, i, i, indexing="ij")
+    s = (slice(3, n - 3),) * 3
+    for px, py, pz in ((3, 0, 0), (0, 3, 0), (0, 0, 3), (2, 1, 3), (1, 1, 1), (0, 2, 2)):
+        f = X ** px * Y ** py * Z ** pz
+        for _ in range(3):
+            p = rng.uniform(-2.0, 2.0, size=3)
+            g = Q.interpolate_shifted(f, p, aperiodic=True, cubic=True)
+            want = (X + p[0]) ** px * (Y + p[1]) ** py * (Z + p[2]) ** pz
+            assert np.max(np.abs(g[s] - want[s])) < 1e-10 * np.max(np.abs(want[s])), (px, py, pz, p)
+    # and, unlike the trilinear one, it is not exact for degree 4
+    f = X ** 4
+    g = Q.interpolate_shifted(f, (0.5, 0.0, 0.0), aperiodic=True, cubic=True)
+    assert np.max(np.abs(g[s] - ((X + 0.5) ** 4)[s])) > 1e-3
+
+
+def test_cubic_field_interior_closed_form():
+    # f = x^3: R^2 int (x + R n_x)^3 dOmega = 4 pi R^2 (x^3 + x R^2), and the
+    # x component of the vector integral R^2 int (x + R n_x)^3 n_x dOmega =
+    # 4 pi R^3 x^2 + 4 pi R^5 / 5; the y and z components vanish
+    n, h, R = 18, 0.1, 0.37
+    x = h * np.arange(n)
+    X = np.meshgrid(x, x, x, indexing="ij")[0]
+    f = X ** 3
+    pts = np.array([[a, b, c] for a in (7, 9, 10) for b in (6, 8) for c in (7, 11)])
+    I, Iv = Q.shell_integrals_at(f, R, h, 24, pts, aperiodic=True, cubic=True)
+    xs = h * pts[:, 0]
+    ref = 4.0 * math.pi * R * R * (xs ** 3 + xs * R * R)
+    assert np.max(np.abs(I - ref)) < 1e-9 * np.max(np.abs(ref))
+    refv = 4.0 * math.pi * R ** 3 * xs ** 2 + 4.0 * math.pi * R ** 5 / 5.0
+    assert np.max(np.abs(Iv[0] - refv)) < 1e-9 * np.max(np.abs(refv))
+    assert np.max(np.abs(Iv[1:])) < 1e-9 * np.max(np.abs(refv))
+    # the trilinear interpolant misses the curvature
+    I1, _ = Q.shell_integrals_at(f, R, h, 24, pts, aperiodic=True)
+    assert np.max(np.abs(I1 - ref)) > 1e-4 * np.max(np.abs(ref))
+
+
+def _bump_errors(n, k=16, cubic=False):
     L, s, R = 4.8, 0.3, 0.25
     h = L / n
     x = h * np.arange(n)
@@ -64,7 +106,7 @@ def _bump_errors(n, k=16):
     D = np.stack([X - c[0], Y - c[1], Z - c[2]])
     d = np.sqrt(np.sum(D * D, axis=0))
     f = np.exp(-d * d / (2.0 * s * s))
-    I, Iv = Q.shell_integrals(f, R, h, k)
+    I, Iv = Q.shell_integrals(f, R, h, k, cubic=cubic)
     I_ex, Ir_ex = Q.gaussian_bump_shell(d, R, s)
     Iv_ex = Ir_ex * D / np.where(d > 0, d, 1.0)
     e_s = np.max(np.abs(I - I_ex)) / np.max(np.abs(I_ex))
@@ -81,6 +123,17 @@ def test_gaussian_bump_closed_form_second_order():
     assert e2s < 0.025 and e2v < 0.04
     assert 3.0 < e1s / e2s < 5.5, (e1s, e2s)
     assert 3.0 < e1v / e2v < 5.5, (e1v, e2v)
+
+
+def test_gaussian_bump_cubic_fourth_order():
+    # with the tricubic interpolant the error falls as h^4: far below the
+    # trilinear one, and by about 16 when h halves
+    e1s, e1v = _bump_errors(24, cubic=True)
+    e2s, e2v = _bump_errors(48, cubic=True)
+    t1s, _ = _bump_errors(24)
+    assert e1s < 0.25 * t1s
+    assert 9.0 < e1s / e2s < 25.0, (e1s, e2s)
+    assert 9.0 < e1v / e2v < 25.0, (e1v, e2v)
 
 
 def test_bump_closed_form_small_distance_limit():
