@@ -218,7 +218,9 @@ __device__ __forceinline__ void lds_sync() {
   }
 }
 
-// LDS view of one pencil: element pos lives at base[pos * es]
+// LDS view of one pencil: element pos lives at base[pos * es].  After the
+// reads of an exchange the buffer must not be rewritten until every thread
+// has read it: done() synchronises again.
 template <typename T, bool WAVE = false> struct LdsPencil {
   cx<T>* base;
   int es;
@@ -226,6 +228,26 @@ template <typename T, bool WAVE = false> struct LdsPencil {
   __device__ __forceinline__ void st(int pos, cx<T> v) const { base[pos * es] = v; }
   __device__ __forceinline__ cx<T> ld(int pos) const { return base[pos * es]; }
   __device__ __forceinline__ void sync() const { lds_sync<WAVE>(); }
+  __device__ __forceinline__ void done() const { lds_sync<WAVE>(); }
+};
+
+// The same view over two buffers used in turn: exchange e writes and reads
+// buffer e mod 2, so the next exchange writes the other one and only one
+// synchronisation per exchange is needed (a thread that writes buffer b again
+// has passed the synchronisation of the exchange in between, which every
+// thread reaches only after its reads of b).  Every thread of the workgroup
+// must run the same sequence of exchanges.
+template <typename T, bool WAVE = false> struct LdsPencil2 {
+  cx<T>* base0;
+  cx<T>* base1;
+  int es;
+  mutable int cur = 0;
+  static constexpr bool wave = WAVE;
+  __device__ __forceinline__ cx<T>* b() const { return cur ? base1 : base0; }
+  __device__ __forceinline__ void st(int pos, cx<T> v) const { b()[pos * es] = v; }
+  __device__ __forceinline__ cx<T> ld(int pos) const { return b()[pos * es]; }
+  __device__ __forceinline__ void sync() const { lds_sync<WAVE>(); }
+  __device__ __forceinline__ void done() const { cur ^= 1; }
 };
 
 // twiddle table tw[i] = exp(-2 pi i * i / N), i in [0, N), in LDS
@@ -331,7 +353,7 @@ __device__ __forceinline__ void stockham_stage(cx<T>* v, int t, const TW& tw, co
     lds.sync();
 #pragma unroll
     for (int m = 0; m < EPT; ++m) v[m] = lds.ld(t + TPP * m);
-    lds.sync();
+    lds.done();
   }
 }
 
