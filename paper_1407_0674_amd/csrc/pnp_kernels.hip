@@ -1110,7 +1110,10 @@ __device__ __forceinline__ uint64_t table_m(int /*unused*/) { return 3ull * (N /
 // sin and cos of x >= 0 in FP32 for the arguments k R of a grid (x up to a
 // few hundred): Cody-Waite reduction by pi/2 with a three-part constant and
 // fused multiply-adds, then Taylor polynomials on [-pi/4, pi/4].  Absolute
-// error about 6e-8 up to x = 700.
+// error about 6e-8 up to x = 700.  SIGNBITS: the quadrant's sign flips as
+// xors of the sign bit (fewer instructions; the back pass keeps the selects,
+// with which its register allocation does not spill).
+template <bool SIGNBITS = false>
 __device__ __forceinline__ void sincos_f32(float x, float& sn, float& cs) {
   const float n = __builtin_rintf(x * 0.636619746685f);
   float r = __builtin_fmaf(-n, 1.57079637050628662f, x);
@@ -1126,26 +1129,37 @@ __device__ __forceinline__ void sincos_f32(float x, float& sn, float& cs) {
   pc = __builtin_fmaf(r2, pc, 4.16666679084e-02f);
   pc = __builtin_fmaf(r2, pc, -0.5f);
   const float c = __builtin_fmaf(r2, pc, 1.0f);  // cos r
-  const int q = (int)n & 3;
-  sn = q == 0 ? s : q == 1 ? c : q == 2 ? -s : -c;
-  cs = q == 0 ? c : q == 1 ? -s : q == 2 ? -c : s;
+  if constexpr (SIGNBITS) {
+    // odd q swaps sine and cosine; the sine's sign flips for q = 2, 3 and
+    // the cosine's for q = 1, 2
+    const uint32_t q = (uint32_t)(int)n;
+    const bool odd = (q & 1u) != 0u;
+    const float a = odd ? c : s, b = odd ? s : c;
+    sn = __builtin_bit_cast(float, __builtin_bit_cast(uint32_t, a) ^ ((q & 2u) << 30));
+    cs = __builtin_bit_cast(float, __builtin_bit_cast(uint32_t, b) ^ (((q + 1u) & 2u) << 30));
+  } else {
+    const int q = (int)n & 3;
+    sn = q == 0 ? s : q == 1 ? c : q == 2 ? -s : -c;
+    cs = q == 0 ? c : q == 1 ? -s : q == 2 ? -c : s;
+  }
 }
 
 // Hard-sphere weights at |k| = k for radius R, in FP32 registers:
 // j0(kR), 4 pi R^3 j1(kR)/(kR) (ball) and 4 pi R^2 j1(kR) (shell magnitude).
 // j1(x)/x switches to its Taylor series below x = 1, where the closed form
 // loses digits to cancellation.
+template <bool SIGNBITS = false>
 __device__ __forceinline__ void hs_weights_f32(float k, float R, float& j0, float& w3, float& v2) {
   const float x = k * R;
   float sn, cs;
-  sincos_f32(x, sn, cs);
+  sincos_f32<SIGNBITS>(x, sn, cs);
   const float x2 = x * x;
   // j1(x)/x = 1/3 - x^2/30 + x^4/840 - x^6/45360 + x^8/3991680 - x^10/518918400 + ...
   const float ser =
       0.333333333333f -
       x2 * (3.33333333333e-2f - x2 * (1.19047619048e-3f - x2 * (2.20458553792e-5f - x2 * (2.50521083854e-7f -
                                                                                            x2 * 1.92708526042e-9f))));
-  const float rx = 1.0f / x;
+  const float rx = __builtin_amdgcn_rcpf(x);  // 1 ulp; inf at x = 0, where both uses take their series
   const float j1x = x < 1.0f ? ser : (sn - x * cs) * rx * rx * rx;
   j0 = x < 1e-3f ? 1.0f - x2 * 0.166666667f : sn * rx;
   const float a2 = 12.5663706144f * R * R;
@@ -1155,11 +1169,11 @@ __device__ __forceinline__ void hs_weights_f32(float k, float R, float& j0, floa
 
 // Weights of species i at the integer class m = |j|^2: computed in registers
 // for FP32, gathered from the FP64 table otherwise.
-template <typename T>
+template <typename T, bool SIGNBITS = false>
 __device__ __forceinline__ void hs_weights(const EvalArgs& a, const Buf& hs, int S, int i, int m, T& j0, T& w3,
                                            T& v2) {
   if constexpr (sizeof(T) == 4) {
-    hs_weights_f32((float)a.kscale * __builtin_sqrtf((float)m), (float)a.R[i], j0, w3, v2);
+    hs_weights_f32<SIGNBITS>((float)a.kscale * __builtin_sqrtf((float)m), (float)a.R[i], j0, w3, v2);
   } else {
     const v4<T> w = hs.template ld<v4<T>>((uint32_t)(m * S + i) * (uint32_t)sizeof(v4<T>));
     j0 = w.x;
@@ -1260,7 +1274,7 @@ __global__ void __launch_bounds__((PX * (N / EX)))
 #pragma unroll
       for (int m = 0; m < EX; ++m) {
         T j0, s3, vv;
-        hs_weights<T>(a, hs, S, i, mm[m], j0, s3, vv);
+        hs_weights<T, true>(a, hs, S, i, mm[m], j0, s3, vv);
         if (i == 0) {
           acc[0][m] = cscale<T>(cur[m], j0);
           acc[1][m] = cscale<T>(cur[m], j0 * R);
@@ -1417,6 +1431,9 @@ __global__ void __launch_bounds__((PX * (N / EX)))
         cfma<T>(u, dv, -v2);
         out[c][m] = u;
       }
+      // one species at a time: hoisting the weights of later species ahead
+      // (they do not depend on F) would keep them live beside F and spill
+      __builtin_amdgcn_sched_barrier(0);
     }
   } else {
 #pragma unroll
