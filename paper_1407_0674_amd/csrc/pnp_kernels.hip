@@ -1182,6 +1182,51 @@ __device__ __forceinline__ void hs_weights(const EvalArgs& a, const Buf& hs, int
   }
 }
 
+// FP32 weights of a thread's EX elements of one x pencil (element e at
+// kx = t + TX e), shared with the mirror thread.  |k| depends on kx only
+// through |sx|, and element e >= EX/2 of thread t has the |sx| of element
+// EX-1-e of thread TX-t (of element EX-e of thread 0 when t = 0; element
+// EX/2 of thread 0, the column kx = N/2, is its own mirror).  Each thread
+// evaluates its first EX/2 elements (thread 0 also element EX/2), leaves them
+// in LDS slot [e][t][p] of `buf`, and after a workgroup barrier reads the
+// rest from its mirror's slots.  Callers alternate between two buffers, so
+// one barrier per call suffices (a thread writes a buffer again only after
+// the barrier of the call in between).
+struct WTrip {
+  float j0, w3, v2;
+};
+
+template <int N, int EX, int TX, int PX>
+__device__ __forceinline__ void x_weights_shared(float kscale, float R, const int* mm, int t, int p, WTrip* buf,
+                                                 float* j0, float* w3, float* v2) {
+  constexpr int EH = EX / 2;
+  static_assert(EX % 2 == 0 && TX * EX == N, "mirror map");
+#pragma unroll
+  for (int e = 0; e < EH; ++e) {
+    WTrip w;
+    hs_weights_f32<true>(kscale * __builtin_sqrtf((float)mm[e]), R, w.j0, w.w3, w.v2);
+    buf[(e * TX + t) * PX + p] = w;
+  }
+  WTrip ny{0.0f, 0.0f, 0.0f};
+  if (t == 0) hs_weights_f32<true>(kscale * __builtin_sqrtf((float)mm[EH]), R, ny.j0, ny.w3, ny.v2);
+  __syncthreads();
+  const int tm = t == 0 ? 0 : TX - t;
+#pragma unroll
+  for (int e = 0; e < EX; ++e) {
+    WTrip w;
+    if (e < EH) {
+      w = buf[(e * TX + t) * PX + p];
+    } else {
+      const int em = t == 0 ? (e == EH ? 0 : EX - e) : EX - 1 - e;
+      w = buf[(em * TX + tm) * PX + p];
+      if (e == EH && t == 0) w = ny;
+    }
+    j0[e] = w.j0;
+    w3[e] = w.w3;
+    v2[e] = w.v2;
+  }
+}
+
 // signed index of a wavenumber along one axis, 0 on the Nyquist plane
 template <typename T, int N>
 __device__ __forceinline__ T s_axis(int k) {
@@ -1232,6 +1277,8 @@ __global__ void __launch_bounds__((PX * (N / EX)))
   constexpr int TX = N / EX;
   __shared__ cx<T> tw[N];
   __shared__ cx<T> xch[2 * PX * N];
+  // FP32: the weights of the current species, two buffers in turn (x_weights_shared)
+  __shared__ WTrip wsh[2][sizeof(T) == 4 ? (EX / 2) * TX * PX : 1];
   int tile;
   const EvalArgs& a = args[inst_of_part((N * (N / 2)) / PX, N / PX, part, tile)];
   if (!a.hs_on) return;  // uniform per block
@@ -1271,10 +1318,17 @@ __global__ void __launch_bounds__((PX * (N / EX)))
       }
       fft_pencil<T, N, EX, true>(cur, t, tw, lp);
       const T R = (T)a.R[i], ar = (T)a.area[i], i4 = (T)a.inv4piR[i];
+      float sj0[EX], ss3[EX], svv[EX];
+      if constexpr (sizeof(T) == 4)
+        x_weights_shared<N, EX, TX, PX>((float)a.kscale, (float)a.R[i], mm, t, p, wsh[i & 1], sj0, ss3, svv);
 #pragma unroll
       for (int m = 0; m < EX; ++m) {
         T j0, s3, vv;
-        hs_weights<T, true>(a, hs, S, i, mm[m], j0, s3, vv);
+        if constexpr (sizeof(T) == 4) {
+          j0 = sj0[m]; s3 = ss3[m]; vv = svv[m];
+        } else {
+          hs_weights<T>(a, hs, S, i, mm[m], j0, s3, vv);
+        }
         if (i == 0) {
           acc[0][m] = cscale<T>(cur[m], j0);
           acc[1][m] = cscale<T>(cur[m], j0 * R);
