@@ -1399,6 +1399,13 @@ __global__ void __launch_bounds__((PX * (N / EX)))
   __shared__ cx<T> xch[2 * PX * N];
   int tile;
   const EvalArgs& a = args[inst_of_part((N * (N / 2)) / PX, N / PX, part, tile)];
+  // FP32 with at most three outputs: the weights of every output species for
+  // the first half of each thread's elements (and the column kx = N/2 of
+  // thread 0), evaluated while the first pencil loads are in flight; an
+  // element's other half is its mirror's (see x_weights_shared)
+  constexpr bool kPre = sizeof(T) == 4 && CH <= 3;
+  constexpr int EH = EX / 2;
+  __shared__ WTrip wpre[kPre ? CH * EH * TX * PX + CH * PX : 1];
   if (a.S > CH) return;  // uniform per block
   const int p = threadIdx.x % PX, t = threadIdx.x / PX;
   const XPencil<N, PX> pc(tile, p);
@@ -1430,6 +1437,25 @@ __global__ void __launch_bounds__((PX * (N / EX)))
   } else if (pair_on) {
 #pragma unroll
     for (int m = 0; m < EX; ++m) b0[m] = A.template ldnt<cx<T>>(xa.vo, m * xa.mstride);
+  }
+  if constexpr (kPre) {
+    if (hs_on) {
+#pragma unroll
+      for (int c = 0; c < CH; ++c) {
+        const float R = (float)a.R[c < S ? c : 0];
+#pragma unroll
+        for (int e = 0; e < EH; ++e) {
+          WTrip w;
+          hs_weights_f32<true>((float)a.kscale * __builtin_sqrtf((float)mm[e]), R, w.j0, w.w3, w.v2);
+          wpre[((c * EH + e) * TX + t) * PX + p] = w;
+        }
+        if (t == 0) {
+          WTrip w;
+          hs_weights_f32<true>((float)a.kscale * __builtin_sqrtf((float)mm[EH]), R, w.j0, w.w3, w.v2);
+          wpre[CH * EH * TX * PX + c * PX + p] = w;
+        }
+      }
+    }
   }
   init_twiddles<T, N>(tw);
   __syncthreads();
@@ -1473,7 +1499,18 @@ __global__ void __launch_bounds__((PX * (N / EX)))
 #pragma unroll
       for (int m = 0; m < EX; ++m) {
         T j0, w3, v2;
-        hs_weights<T>(a, hs, S, i, mm[m], j0, w3, v2);
+        if constexpr (kPre) {
+          // own slot, the mirror's slot, or thread 0's column kx = N/2
+          const int tm = t == 0 ? 0 : TX - t;
+          const int em = t == 0 ? EX - m : EX - 1 - m;
+          const int idx = m < EH ? ((c * EH + m) * TX + t) * PX + p
+                          : (t == 0 && m == EH) ? CH * EH * TX * PX + c * PX + p
+                                                : ((c * EH + em) * TX + tm) * PX + p;
+          const WTrip w = wpre[idx];
+          j0 = w.j0; w3 = w.w3; v2 = w.v2;
+        } else {
+          hs_weights<T>(a, hs, S, i, mm[m], j0, w3, v2);
+        }
         cx<T> s0 = F[0][m];
         cfma<T>(s0, F[1][m], R);
         cfma<T>(s0, F[2][m], ar);
