@@ -1277,8 +1277,15 @@ __global__ void __launch_bounds__((PX * (N / EX)))
   constexpr int TX = N / EX;
   __shared__ cx<T> tw[N];
   __shared__ cx<T> xch[2 * PX * N];
-  // FP32: the weights of the current species, two buffers in turn (x_weights_shared)
-  __shared__ WTrip wsh[2][sizeof(T) == 4 ? (EX / 2) * TX * PX : 1];
+  // FP32 weights.  With at most three species: every species' weights for
+  // the first half of each thread's elements (and the column kx = N/2 of
+  // thread 0), evaluated while the first pencil loads are in flight; an
+  // element's other half is its mirror's.  With more species the first two
+  // regions serve as the two buffers of x_weights_shared, one species at a
+  // time.
+  constexpr int EH = EX / 2;
+  constexpr int kRegion = EH * TX * PX;
+  __shared__ WTrip wall[sizeof(T) == 4 ? 3 * kRegion + 3 * PX : 1];
   int tile;
   const EvalArgs& a = args[inst_of_part((N * (N / 2)) / PX, N / PX, part, tile)];
   if (!a.hs_on) return;  // uniform per block
@@ -1305,6 +1312,28 @@ __global__ void __launch_bounds__((PX * (N / EX)))
   // the first species' pencil is in flight while the twiddle table is built
 #pragma unroll
   for (int m = 0; m < EX; ++m) b0[m] = A.template ld<cx<T>>(xa.vo, m * xa.mstride);
+  const bool pre = sizeof(T) == 4 && S <= 3;  // uniform
+  if constexpr (sizeof(T) == 4) {
+    if (pre) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        if (c < S) {
+          const float R = (float)a.R[c];
+#pragma unroll
+          for (int e = 0; e < EH; ++e) {
+            WTrip w;
+            hs_weights_f32<true>((float)a.kscale * __builtin_sqrtf((float)mm[e]), R, w.j0, w.w3, w.v2);
+            wall[c * kRegion + (e * TX + t) * PX + p] = w;
+          }
+          if (t == 0) {
+            WTrip w;
+            hs_weights_f32<true>((float)a.kscale * __builtin_sqrtf((float)mm[EH]), R, w.j0, w.w3, w.v2);
+            wall[3 * kRegion + c * PX + p] = w;
+          }
+        }
+      }
+    }
+  }
   init_twiddles<T, N>(tw);
   __syncthreads();
 #pragma unroll
@@ -1319,8 +1348,24 @@ __global__ void __launch_bounds__((PX * (N / EX)))
       fft_pencil<T, N, EX, true>(cur, t, tw, lp);
       const T R = (T)a.R[i], ar = (T)a.area[i], i4 = (T)a.inv4piR[i];
       float sj0[EX], ss3[EX], svv[EX];
-      if constexpr (sizeof(T) == 4)
-        x_weights_shared<N, EX, TX, PX>((float)a.kscale, (float)a.R[i], mm, t, p, wsh[i & 1], sj0, ss3, svv);
+      if constexpr (sizeof(T) == 4) {
+        if (i < 3 && pre) {
+          // own slot, the mirror's slot, or thread 0's column kx = N/2
+          const int tm = t == 0 ? 0 : TX - t;
+#pragma unroll
+          for (int m = 0; m < EX; ++m) {
+            const int em = t == 0 ? EX - m : EX - 1 - m;
+            const int idx = m < EH ? i * kRegion + (m * TX + t) * PX + p
+                            : (t == 0 && m == EH) ? 3 * kRegion + i * PX + p
+                                                  : i * kRegion + (em * TX + tm) * PX + p;
+            const WTrip w = wall[idx];
+            sj0[m] = w.j0; ss3[m] = w.w3; svv[m] = w.v2;
+          }
+        } else {
+          x_weights_shared<N, EX, TX, PX>((float)a.kscale, (float)a.R[i], mm, t, p, wall + (i & 1) * kRegion, sj0,
+                                          ss3, svv);
+        }
+      }
 #pragma unroll
       for (int m = 0; m < EX; ++m) {
         T j0, s3, vv;
