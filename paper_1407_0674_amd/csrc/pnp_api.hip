@@ -181,7 +181,7 @@ Layout layout_of(int n, int S, int precision, bool hs, bool pairs, bool per_term
   const size_t ts = precision == PNP_MIXED ? 4 : 8;
   const long H = n / 2;
   L.M = (int)(3 * H * H + 1);
-  L.fstride = (long)n * n * H + (long)n * n;
+  L.fstride = (long)spec_fstride(n, (int)ts);
   const size_t prow = (size_t)S * padded_species(S);
   size_t o = 0;
   L.status = o; o = up(o + 64);

@@ -399,6 +399,14 @@ __global__ void __launch_bounds__(256) k_tables(const TableArgs* __restrict__ ta
 // wave-local.
 template <int TZ> constexpr bool row_in_wave() { return TZ <= 64 && 64 % TZ == 0; }
 
+// first element of row row_id = kx * N + ky of a spectral field's main block,
+// and of the Nyquist plane
+template <typename T, int N>
+__device__ __forceinline__ uint32_t spec_row(uint32_t row_id) {
+  return row_id * (uint32_t)(N / 2) + (row_id / (uint32_t)N) * (uint32_t)spec_pad(N, sizeof(T));
+}
+template <typename T, int N> constexpr uint32_t spec_nyq() { return (uint32_t)(N * spec_plane(N, sizeof(T))); }
+
 // v holds C[k] at k = t + TZ m; writes X[k] (k < H) and X[H] of one row.
 // zmul: store i s_z X instead (s_z = k below the Nyquist index, 0 at it).
 template <typename T, int N, int TZ, int EZ, typename BF>
@@ -418,9 +426,9 @@ __device__ __forceinline__ void r2c_post(cx<T>* v, int t, const cx<T>* twN, cx<T
     const cx<T> d = mk<T>((T)0.5 * (c.x - cm.x), (T)0.5 * (c.y - cm.y));  // O = d / i
     cx<T> x = cadd<T>(e, cmul<T>(twN[k], cmulmi<T>(d)));
     if (zmul) x = cscale<T>(cmuli<T>(x), (T)k);
-    f.template st<cx<T>>(x, (row_id * H + k) * cs, soff);
+    f.template st<cx<T>>(x, (spec_row<T, N>(row_id) + k) * cs, soff);
     if (k == 0) f.template st<cx<T>>(zmul ? mk<T>((T)0, (T)0) : mk<T>(c.x - c.y, (T)0),
-                            ((uint32_t)(N * N * H) + row_id) * cs, soff);
+                            (spec_nyq<T, N>() + row_id) * cs, soff);
   }
   lds_sync<row_in_wave<TZ>()>();
 }
@@ -437,8 +445,9 @@ __device__ __forceinline__ void c2r_pre(cx<T>* v, int t, const cx<T>* twN, const
 #pragma unroll
   for (int m = 0; m < EZ; ++m) {
     const int k = t + TZ * m;
-    cx<T> xk = f.template ld<cx<T>>((row_id * H + k) * cs, soff);
-    cx<T> xm = f.template ld<cx<T>>((k == 0 ? (uint32_t)(N * N * H) + row_id : row_id * H + (H - k)) * cs, soff);
+    const uint32_t r0 = spec_row<T, N>(row_id);
+    cx<T> xk = f.template ld<cx<T>>((r0 + k) * cs, soff);
+    cx<T> xm = f.template ld<cx<T>>((k == 0 ? spec_nyq<T, N>() + row_id : r0 + (H - k)) * cs, soff);
     if (k == 0) { xk.y = (T)0; xm.y = (T)0; }
     if (zmul) {
       xk = cscale<T>(cmuli<T>(xk), (T)k);
@@ -611,11 +620,12 @@ __device__ __forceinline__ void c2r_load(cx<T>* xk, cx<T>* xm, int t, const BF& 
                                          uint32_t row_id) {
   constexpr int H = N / 2;
   constexpr uint32_t cs = sizeof(cx<T>);
+  const uint32_t r0 = spec_row<T, N>(row_id);
 #pragma unroll
   for (int m = 0; m < EZ; ++m) {
     const int k = t + TZ * m;
-    xk[m] = f.template ldnt<cx<T>>((row_id * H + k) * cs, soff);
-    xm[m] = f.template ldnt<cx<T>>((k == 0 ? (uint32_t)(N * N * H) + row_id : row_id * H + (H - k)) * cs, soff);
+    xk[m] = f.template ldnt<cx<T>>((r0 + k) * cs, soff);
+    xm[m] = f.template ldnt<cx<T>>((k == 0 ? spec_nyq<T, N>() + row_id : r0 + (H - k)) * cs, soff);
   }
 }
 
@@ -679,9 +689,9 @@ __device__ __forceinline__ void r2c_post_r(cx<T>* v, int t, const cx<T>* twk, cx
     const cx<T> d = mk<T>((T)0.5 * (c.x - cm.x), (T)0.5 * (c.y - cm.y));
     cx<T> x = cadd<T>(e, cmul<T>(twk[m], cmulmi<T>(d)));
     if (zmul) x = cscale<T>(cmuli<T>(x), (T)k);
-    f.template st<cx<T>>(x, (row_id * H + k) * cs, soff);
+    f.template st<cx<T>>(x, (spec_row<T, N>(row_id) + k) * cs, soff);
     if (k == 0) f.template st<cx<T>>(zmul ? mk<T>((T)0, (T)0) : mk<T>(c.x - c.y, (T)0),
-                            ((uint32_t)(N * N * H) + row_id) * cs, soff);
+                            (spec_nyq<T, N>() + row_id) * cs, soff);
   }
   lds_sync<row_in_wave<TZ>()>();
 }
@@ -991,14 +1001,14 @@ __global__ void __launch_bounds__((Geo<T, N, V>::PY * Geo<T, N, V>::TY))
     const int p = threadIdx.x % PY;
     t = threadIdx.x / PY;
     const uint32_t pen = (uint32_t)(tile * PY + p);  // (x, kz)
-    off = (pen / H) * (N * H) + (pen % H);
+    off = (pen / H) * (uint32_t)spec_plane(N, sizeof(T)) + (pen % H);
     es = H;
     lp = LdsPencil<T>{xch + p, PY};
   } else {
     const int p = threadIdx.x / TY;
     t = threadIdx.x % TY;
     const uint32_t x = (uint32_t)((tile - tiles_main) * PY + p);
-    off = N * N * H + x * N;
+    off = spec_nyq<T, N>() + x * N;
     es = 1;
     lp = LdsPencil<T>{xch + p * N, 1};
   }
@@ -1055,7 +1065,7 @@ __global__ void __launch_bounds__((Geo<T, N, V>::PY * Geo<T, N, V>::TY))
 // x direction helpers: pencil (ky, kz) of the main array or ky of the Nyquist
 // plane, element kx at stride es.
 // ---------------------------------------------------------------------------
-template <int N, int PX>
+template <typename T, int N, int PX>
 struct XPencil {
   uint32_t off, es;  // element kx of the pencil at off + kx * es
   int ky, kz;
@@ -1064,10 +1074,10 @@ struct XPencil {
     const int pen = tile * PX + p;
     constexpr int nmain = N * H;
     if (pen < nmain) {
-      off = (uint32_t)pen; es = nmain; ky = pen / H; kz = pen % H;
+      off = (uint32_t)pen; es = (uint32_t)spec_plane(N, sizeof(T)); ky = pen / H; kz = pen % H;
     } else {
       const int q = pen - nmain;
-      off = (uint32_t)(nmain * N + q); es = N; ky = q; kz = H;
+      off = spec_nyq<T, N>() + (uint32_t)q; es = N; ky = q; kz = H;
     }
   }
 };
@@ -1254,7 +1264,7 @@ __device__ __forceinline__ constexpr int back_field(int q) {
 template <typename T, int N, int EX, int PX>
 struct XAddr {
   uint32_t vo, mstride;
-  __device__ __forceinline__ XAddr(const XPencil<N, PX>& pc, int t) {
+  __device__ __forceinline__ XAddr(const XPencil<T, N, PX>& pc, int t) {
     constexpr int TX = N / EX;
     vo = (pc.off + (uint32_t)t * pc.es) * (uint32_t)sizeof(cx<T>);
     mstride = __builtin_amdgcn_readfirstlane((uint32_t)TX * pc.es * (uint32_t)sizeof(cx<T>));
@@ -1290,7 +1300,7 @@ __global__ void __launch_bounds__((PX * (N / EX)))
   const EvalArgs& a = args[inst_of_part((N * (N / 2)) / PX, N / PX, part, tile)];
   if (!a.hs_on) return;  // uniform per block
   const int p = threadIdx.x % PX, t = threadIdx.x / PX;
-  const XPencil<N, PX> pc(tile, p);
+  const XPencil<T, N, PX> pc(tile, p);
   const LdsPencil2<T> lp{xch + p, xch + PX * N + p, PX};
   const int S = a.S;
   const Buf hs = make_buf(a.hs_tab, sizeof(T) == 8 ? table_m<T, N>(0) * S * sizeof(v4<T>) : 0);
@@ -1453,7 +1463,7 @@ __global__ void __launch_bounds__((PX * (N / EX)))
   __shared__ WTrip wpre[kPre ? CH * EH * TX * PX + CH * PX : 1];
   if (a.S > CH) return;  // uniform per block
   const int p = threadIdx.x % PX, t = threadIdx.x / PX;
-  const XPencil<N, PX> pc(tile, p);
+  const XPencil<T, N, PX> pc(tile, p);
   const LdsPencil2<T> lp{xch + p, xch + PX * N + p, PX};
   const int S = a.S;
   const bool hs_on = a.hs_on, pair_on = a.pair_on;
@@ -1662,7 +1672,7 @@ __global__ void __launch_bounds__((PX * (N / EX)))
   init_twiddles<T, N>(tw);
   __syncthreads();
   const int p = threadIdx.x % PX, t = threadIdx.x / PX;
-  const XPencil<N, PX> pc(tile, p);
+  const XPencil<T, N, PX> pc(tile, p);
   const LdsPencil2<T> lp{xch + p, xch + PX * N + p, PX};
   const int S = a.S;
   const Buf hs = make_buf(a.hs_tab, sizeof(T) == 8 ? table_m<T, N>(0) * S * sizeof(v4<T>) : 0);
@@ -1786,7 +1796,7 @@ __global__ void __launch_bounds__((PX * (N / EX)))
   init_twiddles<T, N>(tw);
   __syncthreads();
   const int p = threadIdx.x % PX, t = threadIdx.x / PX;
-  const XPencil<N, PX> pc(tile, p);
+  const XPencil<T, N, PX> pc(tile, p);
   const LdsPencil<T> lp{xch + p, PX};
   const BufN<N> base = make_buf<stream_policy<N>()>(sel == 0 ? a.specA : sel == 1 ? a.specB : a.specC, spec_bytes<T>(a, nf));
   const uint32_t fbytes = (uint32_t)(a.fstride * sizeof(cx<T>));
@@ -1818,7 +1828,7 @@ __global__ void k_export(const EvalArgs* __restrict__ args, int nf, double* buf,
     const long ky = (rem / (H + 1)) % N;
     const long kz = rem % (H + 1);
     const gp<cx<T>> s =
-        A + f * a.fstride + (kz < H ? (kx * N + ky) * H + kz : (long)N * N * H + kx * N + ky);
+        A + f * a.fstride + (kz < H ? kx * spec_plane(N, sizeof(T)) + ky * H + kz : (long)spec_nyq<T, N>() + kx * N + ky);
     if (to_numpy) {
       bb[2 * e] = (double)s->x;
       bb[2 * e + 1] = (double)s->y;
