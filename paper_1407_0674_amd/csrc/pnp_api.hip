@@ -434,6 +434,7 @@ const Ops* ops_for(int precision, int n, int variant = 0) {
 struct OpsSel {
   const Ops* v[4] = {nullptr, nullptr, nullptr, nullptr};
   uint32_t mask = 0, smask = 0;
+  int precision = PNP_FP64;
   const Ops* at(int pass) const {
     const int sch = ((smask >> pass) & 1u) ? 2 : 0;
     const Ops* o = ((mask >> pass) & 1u) ? v[sch | 1] : nullptr;
@@ -553,22 +554,40 @@ void run_sequence(pnp_ctx c, const OpsSel& op, const EvalArgs* ea, const TableAr
   PassTimer pt{c, s};
   Split sp(c, s, n);
   const int mp = sp.main_part();
-  pt.begin(0); op.at(0)->tables(ta, count, M, sm.maxS, s); pt.end();
+  // The radial tables are first read by the x passes (the forward one only in
+  // FP64: the FP32 hard-sphere weights are evaluated in registers).  With the
+  // side stream they are built there, beside the first z and y passes, and
+  // joined before their first reader (256^3 mixed: 13 us off the evaluation).
+  bool tab_pending = false;
+  if (sp.on) {
+    sp.fork();
+    PassTimer ps{c, sp.nyq()};
+    ps.begin(0); op.at(0)->tables(ta, count, M, sm.maxS, sp.nyq()); ps.end();
+    tab_pending = true;
+  } else {
+    pt.begin(0); op.at(0)->tables(ta, count, M, sm.maxS, s); pt.end();
+  }
   pt.begin(1); op.at(1)->zfwd(ea, count, s); pt.end();
   sp.fork();
   pt.begin(2); op.at(2)->ystep(ea, count, 0, -1, true, mp, s); pt.end();
   if (sp.on) op.at(2)->ystep(ea, count, 0, -1, true, kPartNyquist, sp.nyq());
   if (fmask) {
+    if (tab_pending && op.precision == PNP_FP64) {
+      sp.join();
+      tab_pending = false;
+    }
     pt.begin(3); op.at(3)->xfwd(ea, count, mp, s); pt.end();
     if (sp.on) op.at(3)->xfwd(ea, count, kPartNyquist, sp.nyq());
     pt.begin(4); op.at(4)->ystep(ea, count, 1, kVecMode, false, mp, s); pt.end();
     if (sp.on) op.at(4)->ystep(ea, count, 1, kVecMode, false, kPartNyquist, sp.nyq());
     sp.join();
+    tab_pending = false;
     pt.begin(5); op.at(5)->zderiv(ea, count, false, fmask, s); pt.end();
     sp.fork();
     pt.begin(6); op.at(6)->ystep(ea, count, 1, kVecMode, true, mp, s); pt.end();
     if (sp.on) op.at(6)->ystep(ea, count, 1, kVecMode, true, kPartNyquist, sp.nyq());
   }
+  if (tab_pending) sp.join();
   pt.begin(7); op.at(7)->xback(ea, count, sm.small, sm.maxS > 4, mp, s); pt.end();
   if (sp.on) op.at(7)->xback(ea, count, sm.small, sm.maxS > 4, kPartNyquist, sp.nyq());
   pt.begin(8); op.at(8)->ystep(ea, count, 2, -1, false, mp, s); pt.end();
@@ -581,6 +600,7 @@ void run_sequence(pnp_ctx c, const OpsSel& op, const EvalArgs* ea, const TableAr
 // of `count` instances of it
 OpsSel select_ops(pnp_ctx c, int precision, int n, int count) {
   OpsSel o;
+  o.precision = precision;
   for (int v = 0; v < 4; ++v) o.v[v] = ops_for(precision, n, v);
   auto it = c->tune.find(tune_key(precision, n, count_class(count)));
   if (it != c->tune.end()) o.mask = it->second;
@@ -1363,6 +1383,7 @@ pnp_status pnp_autotune(pnp_ctx ctx, int32_t count, pnp_request* reqs, int32_t r
     upload_args(ctx, g.ta.data(), cnt, g.ea.data(), cnt, s, dta, dea);
     if (!dta || !dea) { st = device_check(ctx, "argument upload"); break; }
     OpsSel sel;
+    sel.precision = g.precision;
     for (int v = 0; v < 4; ++v) sel.v[v] = ops_for(g.precision, g.n, v);
     const uint32_t alt = sel.v[0]->sched_alt;       // passes with a secondary schedule
     const uint32_t all = (1u << PNP_NUM_PASSES) - 2u;  // every pass but the tables
