@@ -1,5 +1,8 @@
 """GPU: the library's 3D real DFT passes against numpy's rfftn (a library
-FFT) on seeded random fields, every supported size, both precisions."""
+FFT) on seeded random fields, every supported size, both precisions.  From
+192^3 up the spectral fields pad each kx plane (more values in FP32 than in
+FP64), so the largest sizes also check the padded layout of every pass and of
+the export to numpy's layout."""
 import numpy as np
 import pytest
 import torch
@@ -8,7 +11,7 @@ from conftest import relerr, to_dev
 
 pytestmark = pytest.mark.gpu
 
-SIZES = [8, 16, 24, 32, 48, 64, 96, 128]
+SIZES = [8, 16, 24, 32, 48, 64, 96, 128, 192, 256]
 
 
 @pytest.mark.parametrize("n", SIZES)
