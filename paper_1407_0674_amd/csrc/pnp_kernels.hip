@@ -650,10 +650,15 @@ __device__ __forceinline__ void c2r_combine(cx<T>* v, const cx<T>* xk0, const cx
   }
 }
 
-// c2r_combine with the lane's W^k in registers (twk[m] = W^(t + TZ m))
+// The pre- and post-steps of the real transforms with the lane's constants
+// P_k = (1 - i W^k) / 2 in registers (twp[m] for k = t + TZ m).  With cm the
+// conjugated mirror value, the r2c step E + W^k (-i) O of r2c_post is
+// cm + P_k (c - cm), and the c2r step of c2r_pre, (X_k + cm) + i conj(W^k)
+// (X_k - cm), equals 2 (cm + conj(P_k) (X_k - cm)): six and eight
+// instructions per element instead of fourteen and ten.
 template <typename T, int N, int TZ, int EZ>
-__device__ __forceinline__ void c2r_combine_r(cx<T>* v, const cx<T>* xk0, const cx<T>* xm0, int t,
-                                              const cx<T>* twk, bool zmul = false) {
+__device__ __forceinline__ void c2r_combine_p(cx<T>* v, const cx<T>* xk0, const cx<T>* xm0, int t,
+                                              const cx<T>* twp, bool zmul = false) {
   constexpr int H = N / 2;
 #pragma unroll
   for (int m = 0; m < EZ; ++m) {
@@ -664,16 +669,18 @@ __device__ __forceinline__ void c2r_combine_r(cx<T>* v, const cx<T>* xk0, const 
       xk = cscale<T>(cmuli<T>(xk), (T)k);
       xm = k == 0 ? mk<T>((T)0, (T)0) : cscale<T>(cmuli<T>(xm), (T)(H - k));
     }
-    const cx<T> cm = cconj<T>(xm);
-    const cx<T> s = cadd<T>(xk, cm);
-    const cx<T> d = csub<T>(xk, cm);
-    v[m] = cadd<T>(s, cmuli<T>(cmulc<T>(d, twk[m])));
+    const T cmx = xm.x, cmy = -xm.y;  // cm = conj(xm)
+    const T dx = xk.x - cmx, dy = xk.y - cmy;
+    const cx<T> P = twp[m];
+    // cm + conj(P) d = (cm.x + P.x dx + P.y dy, cm.y + P.x dy - P.y dx)
+    const T rx = fma(P.x, dx, fma(P.y, dy, cmx));
+    const T ry = fma(P.x, dy, fma(-P.y, dx, cmy));
+    v[m] = mk<T>(rx + rx, ry + ry);
   }
 }
 
-// r2c_post with the lane's W^k in registers
 template <typename T, int N, int TZ, int EZ, typename BF>
-__device__ __forceinline__ void r2c_post_r(cx<T>* v, int t, const cx<T>* twk, cx<T>* row, const BF& f,
+__device__ __forceinline__ void r2c_post_p(cx<T>* v, int t, const cx<T>* twp, cx<T>* row, const BF& f,
                                            uint32_t soff, uint32_t row_id, bool zmul = false) {
   constexpr int H = N / 2;
   constexpr uint32_t cs = sizeof(cx<T>);
@@ -684,10 +691,11 @@ __device__ __forceinline__ void r2c_post_r(cx<T>* v, int t, const cx<T>* twk, cx
   for (int m = 0; m < EZ; ++m) {
     const int k = t + TZ * m;
     const cx<T> c = v[m];
-    const cx<T> cm = cconj<T>(row[k == 0 ? 0 : H - k]);
-    const cx<T> e = mk<T>((T)0.5 * (c.x + cm.x), (T)0.5 * (c.y + cm.y));
-    const cx<T> d = mk<T>((T)0.5 * (c.x - cm.x), (T)0.5 * (c.y - cm.y));
-    cx<T> x = cadd<T>(e, cmul<T>(twk[m], cmulmi<T>(d)));
+    const cx<T> r = row[k == 0 ? 0 : H - k];
+    const T cmx = r.x, cmy = -r.y;  // cm = conj(C[H - k])
+    const T dx = c.x - cmx, dy = c.y - cmy;
+    const cx<T> P = twp[m];
+    cx<T> x = mk<T>(fma(P.x, dx, fma(-P.y, dy, cmx)), fma(P.x, dy, fma(P.y, dx, cmy)));
     if (zmul) x = cscale<T>(cmuli<T>(x), (T)k);
     f.template st<cx<T>>(x, (spec_row<T, N>(row_id) + k) * cs, soff);
     if (k == 0) f.template st<cx<T>>(zmul ? mk<T>((T)0, (T)0) : mk<T>(c.x - c.y, (T)0),
@@ -811,13 +819,15 @@ __global__ void __launch_bounds__((GeoD<T, N, EZD, V>::RDD * GeoD<T, N, EZD, V>:
   const BufN<N> B = make_buf<stream_policy<N>()>(a.specB, spec_bytes<T>(a, kFields));
   const uint32_t fbytes = __builtin_amdgcn_readfirstlane((uint32_t)(a.fstride * sizeof(cx<T>)));
   cx<T> val[kFields * EZ];
-  // The FFT twiddles of this lane and the r2c / c2r twiddles W^k of its
-  // elements, held in registers for all twenty transforms; with six elements
-  // per thread (sizes with a factor 3) the registers go to the values and the
-  // twiddles are read from LDS instead.
+  // The FFT twiddles of this lane and the constants P_k = (1 - i W^k) / 2 of
+  // the r2c / c2r steps of its elements (c2r_combine_p, r2c_post_p; z_deriv
+  // 353 -> 347 us at 256^3 against the same steps on W^k), held in registers
+  // for all twenty transforms; with six elements per thread (sizes with a
+  // factor 3) the registers go to the values and the twiddles are read from
+  // LDS instead.
   constexpr bool kTwRegs = EZ < 6;
   typename std::conditional<kTwRegs, TwReg<T, H, EZ>, char>::type twr;
-  cx<T> twk[kTwRegs ? EZ : 1];
+  cx<T> twp[kTwRegs ? EZ : 1];
   {
     // the raw values of fields q + 1 and q + 2 are in flight while field q is
     // transformed (z_deriv 357 -> 350 us at 256^3; three ahead gained
@@ -838,7 +848,10 @@ __global__ void __launch_bounds__((GeoD<T, N, EZD, V>::RDD * GeoD<T, N, EZD, V>:
     if constexpr (kTwRegs) {
       twr.load(t, twH);
 #pragma unroll
-      for (int m = 0; m < EZ; ++m) twk[m] = twN[t + TZ * m];
+      for (int m = 0; m < EZ; ++m) {
+        const cx<T> w = twN[t + TZ * m];
+        twp[m] = mk<T>((T)0.5 + (T)0.5 * w.y, (T)-0.5 * w.x);
+      }
     }
 #pragma unroll
     for (int q = 0; q < kFields; ++q) {
@@ -852,7 +865,7 @@ __global__ void __launch_bounds__((GeoD<T, N, EZD, V>::RDD * GeoD<T, N, EZD, V>:
       }
       // the z component of each vector density is i s_z Q_b, formed here
       if constexpr (kTwRegs) {
-        c2r_combine_r<T, N, TZ, EZ>(val + q * EZ, kc, mc, t, twk, q == kSlotZ || q == kSlotZ + kVecStride);
+        c2r_combine_p<T, N, TZ, EZ>(val + q * EZ, kc, mc, t, twp, q == kSlotZ || q == kSlotZ + kVecStride);
         fft_pencil<T, N / 2, EZ, false>(val + q * EZ, t, twr, lp);
       } else {
         c2r_combine<T, N, TZ, EZ>(val + q * EZ, kc, mc, t, twN, q == kSlotZ || q == kSlotZ + kVecStride);
@@ -947,7 +960,7 @@ __global__ void __launch_bounds__((GeoD<T, N, EZD, V>::RDD * GeoD<T, N, EZD, V>:
     // the z components of the vector derivatives leave as i s_z F_z
     if constexpr (kTwRegs) {
       fft_pencil<T, N / 2, EZ, true>(val + q * EZ, t, twr, lp);
-      r2c_post_r<T, N, TZ, EZ>(val + q * EZ, t, twk, lrow, B, q * fbytes, row, q == kSlotZ || q == kSlotZ + kVecStride);
+      r2c_post_p<T, N, TZ, EZ>(val + q * EZ, t, twp, lrow, B, q * fbytes, row, q == kSlotZ || q == kSlotZ + kVecStride);
     } else {
       fft_pencil<T, N / 2, EZ, true>(val + q * EZ, t, (const cx<T>*)twH, lp);
       r2c_post<T, N, TZ, EZ>(val + q * EZ, t, twN, lrow, B, q * fbytes, row, q == kSlotZ || q == kSlotZ + kVecStride);
