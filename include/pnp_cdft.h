@@ -413,7 +413,10 @@ void pnp_plan_destroy(pnp_plan plan);
  * (schedule, shape) combination after one warm-up round, times every pass
  * with HIP events, and keeps per pass the narrow shape where it is faster
  * by more than 3 % under a schedule, and the secondary schedule where its
- * best shape is faster than the primary's by more than 3 %.
+ * best shape is faster than the primary's by more than 3 %.  That choice is
+ * then timed end to end (`reps` more rounds) against the size's default
+ * schedule with the default shapes, and kept only if its passes take more
+ * than 1 % less in total; otherwise the default is stored.
  *
  * The schedule is stored in the context under (precision, n): the last
  * autotune or import for that pair sets it for every later evaluation of

@@ -401,8 +401,9 @@ class Evaluator:
 
     def autotune(self, problems: Sequence, rhos: Sequence, reps: int = 3):
         """Time both FFT schedules and both tile shapes of every pass on these
-        problems (evaluated as one batch) and keep the faster per pass in
-        this context (schedule per precision and size, tile shape also per
+        problems (evaluated as one batch), keep the faster per pass, and keep
+        that choice in this context only if it beats the size's default end
+        to end (schedule per precision and size, tile shape also per
         instance-count class); returns the statuses.  Saved to
         $PNP_TUNE_CACHE when that is set."""
         count = len(problems)

@@ -1420,6 +1420,31 @@ pnp_status pnp_autotune(pnp_ctx ctx, int32_t count, pnp_request* reqs, int32_t r
       if (sc) smask |= 1u << p;
       if (nar[sc]) tmask |= 1u << p;
     }
+    // Per-pass choices need not add up (a pass's time depends on what the
+    // one before left in the caches), and the default schedule of the size
+    // mixes the two: the choice is timed end to end against the default
+    // (its schedule, wide tiles) and kept only if its passes take more than
+    // 1 % less in total.
+    const uint32_t dsm = default_sched(g.precision, g.n);
+    if (smask != dsm || tmask != 0u) {
+      const uint32_t two[2][2] = {{dsm, 0u}, {smask, tmask}};
+      double tot[2] = {0.0, 0.0};
+      for (int r = 0; r <= reps && st == PNP_OK; ++r)
+        for (int c = 0; c < 2 && st == PNP_OK; ++c) {
+          sel.smask = two[c][0];
+          sel.mask = two[c][1];
+          run_sequence(ctx, sel, dea, dta, cnt, g.M, g.fmask, g.mix, s, g.n);
+          double ms[PNP_NUM_PASSES];
+          st = pnp_profile_read(ctx, ms, nullptr, PNP_NUM_PASSES, 1);
+          if (r > 0)
+            for (int p = 1; p < PNP_NUM_PASSES; ++p) tot[c] += ms[p];
+        }
+      if (st != PNP_OK) break;
+      if (!(tot[1] < 0.99 * tot[0])) {
+        smask = dsm;
+        tmask = 0u;
+      }
+    }
     ctx->sched[sched_key(g.precision, g.n)] = smask;
     ctx->tune[tune_key(g.precision, g.n, count_class(cnt))] = tmask;
   }
