@@ -556,19 +556,23 @@ void run_sequence(pnp_ctx c, const OpsSel& op, const EvalArgs* ea, const TableAr
   const int mp = sp.main_part();
   // The radial tables are first read by the x passes (the forward one only in
   // FP64: the FP32 hard-sphere weights are evaluated in registers).  With the
-  // side stream they are built there, beside the first z and y passes, and
-  // joined before their first reader (256^3 mixed: 13 us off the evaluation).
+  // side stream they are built there, beside the first y pass, and joined
+  // before their first reader.  Beside the y pass (2 waves per SIMD) their
+  // small workgroups fill idle register slots; beside the first z pass (4
+  // waves per SIMD) they displaced its workgroups (256^3 mixed, the same
+  // run: 1.657 ms per evaluation beside the y pass, 1.666 ms beside the z
+  // pass).
   bool tab_pending = false;
-  if (sp.on) {
-    sp.fork();
-    PassTimer ps{c, sp.nyq()};
-    ps.begin(0); op.at(0)->tables(ta, count, M, sm.maxS, sp.nyq()); ps.end();
-    tab_pending = true;
-  } else {
+  if (!sp.on) {
     pt.begin(0); op.at(0)->tables(ta, count, M, sm.maxS, s); pt.end();
   }
   pt.begin(1); op.at(1)->zfwd(ea, count, s); pt.end();
   sp.fork();
+  if (sp.on) {
+    PassTimer ps{c, sp.nyq()};
+    ps.begin(0); op.at(0)->tables(ta, count, M, sm.maxS, sp.nyq()); ps.end();
+    tab_pending = true;
+  }
   pt.begin(2); op.at(2)->ystep(ea, count, 0, -1, true, mp, s); pt.end();
   if (sp.on) op.at(2)->ystep(ea, count, 0, -1, true, kPartNyquist, sp.nyq());
   if (fmask) {
