@@ -56,7 +56,12 @@
  * PNP_OK.  pnp_last_error() gives a human-readable reason.
  *
  * Concurrency: a context is not thread-safe; use one per host thread.  Work
- * is enqueued on the caller's HIP stream.  Unless PNP_FLAG_ASYNC is set, a
+ * is enqueued on the caller's HIP stream.  From 192^3 up part of it (the
+ * Nyquist-plane tiles of the y and x passes and the radial tables) runs on a
+ * second stream that the context owns (default priority), forked from the
+ * caller's stream after the work enqueued so far and joined back into it
+ * before the call's last pass, so to the caller the work is ordered as if
+ * it ran on its stream alone.  Unless PNP_FLAG_ASYNC is set, a
  * call waits for its own work to finish so that it can return the status
  * that the kernels raised (packing fraction >= 1, non-finite values,
  * overflow of exp(-mu)).
