@@ -69,7 +69,7 @@ def pass_bytes_per_point(S: int, precision: int, slot: bool = True):
     }
 
 
-def survey_bytes_per_point(S: int, precision: int):
+def all_fields_bytes_per_point(S: int, precision: int):
     """The all-fields bytes model of the path's scope (60 S + 32 F per point in
     the mixed path, 96 S + 64 F in FP64): every pass carries all ten FMT
     fields."""
@@ -731,7 +731,7 @@ def main():
 
     lat = latencies(ev, prob, rho_d, out, slot, args.latency_reps, prec)
 
-    sbp = survey_bytes_per_point(S, prec)
+    sbp = all_fields_bytes_per_point(S, prec)
     per_pass = {}
     for name, (tot, cnt) in passes.items():
         if cnt == 0:
