@@ -80,8 +80,8 @@ def test_batch_empty(ev):
 
 def test_config4_batch(ev):
     """The 64-instance uneven mix (n from 32 to 128, S from 2 to 4, mixed
-    precision): batch equals alone for every instance; the three smallest
-    instances also against the oracle."""
+    precision): batch equals alone for every instance; against the oracle,
+    the instance with the most species of every grid size."""
     inst = P.config4()
     rhos = [to_dev(r) for _, r in inst]
     mus, slots, st = ev.batch([p for p, _ in inst], rhos)
@@ -90,13 +90,20 @@ def test_config4_batch(ev):
         m1, s1 = _alone(ev, p, rd)
         assert torch.equal(mu, m1), p.name
         assert torch.equal(sl, s1), p.name
-    small = sorted(range(len(inst)), key=lambda k: (inst[k][0].n, inst[k][0].S))[:3]
-    for k in small:
+    per_size = {}
+    for k, (p, _) in enumerate(inst):
+        if p.n not in per_size or p.S > inst[per_size[p.n]][0].S:
+            per_size[p.n] = k
+    assert sorted(per_size) == [32, 48, 64, 96, 128]
+    for n, k in sorted(per_size.items()):
         p, rho = inst[k]
+        print(f"oracle n={n} S={p.S}", flush=True)
         ref = oracle.mu_ex(p, rho, "fft")
-        mu = mus[k].cpu().numpy()
+        mu, sl = mus[k].cpu().numpy(), slots[k].cpu().numpy()
         for i in range(p.S):
             assert relerr(mu[i], ref["total"][i]) < 1e-5, (p.name, i)
+        stol = 1e-5 * max(1.0, float(np.max(np.abs(ref["total"]))))
+        assert float(np.max(np.abs(sl / ref["slotboom"] - 1.0))) < stol, p.name
 
 
 @pytest.mark.parametrize("lam,clip", [(0.0, 0.0), (0.1, 0.0), (1.0, 0.0), (0.5, 1.0), (1.0, 0.3)])

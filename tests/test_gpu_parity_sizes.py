@@ -63,3 +63,29 @@ def _check(ev, n, precision, tol):
                                                for p, t in ((P.FP64, 1e-10), (P.MIXED, 1e-5))])
 def test_sizes(ev, n, precision, tol):
     _check(ev, n, precision, tol)
+
+
+@pytest.mark.parametrize("n", [96, 192])
+def test_mixed_term_sum_in_k_space(ev, n):
+    """The mixed path sums the three terms in k-space in FP32, before the last
+    inverse transform.  Against the oracle that total is no less accurate
+    than the FP64 sum of the three per-term outputs (each inverse-transformed
+    on its own in FP32): the FP32 rounding comes from the transforms, whose
+    error scales with the transformed field, and the summed field is no
+    larger than its parts."""
+    prob, rho, ref = _case(n)
+    prob = prob.with_(precision=P.MIXED)
+    rd = to_dev(rho)
+    mu3, _ = ev.mu_ex(prob, rd, per_term=True, slotboom=False)
+    sum64 = (mu3[0] + mu3[1] + mu3[2]).cpu().numpy()
+    del mu3
+    mu, _ = ev.mu_ex(prob, rd, slotboom=False)
+    mu = mu.cpu().numpy()
+    for i in range(prob.S):
+        e_tot = relerr(mu[i], ref["total"][i])
+        e_sum = relerr(sum64[i], ref["total"][i])
+        print(f"n={n} species {i}: k-space FP32 sum {e_tot:.3e}, FP64 sum of terms {e_sum:.3e}", flush=True)
+        assert e_tot < 1e-5 and e_sum < 1e-5
+        assert e_tot <= 2.0 * e_sum + 1e-7, (n, i, e_tot, e_sum)
+    del rd
+    torch.cuda.empty_cache()
