@@ -433,21 +433,77 @@ __device__ __forceinline__ void r2c_post(cx<T>* v, int t, const cx<T>* twN, cx<T
   lds_sync<row_in_wave<TZ>()>();
 }
 
-// inverse: from X[k] (k < H) and X[H] build C[k] = (X[k] + conj X[H-k]) +
-// i (X[k] - conj X[H-k]) W^-k; the unnormalised length-H inverse of C is
-// then n (a[2j] + i a[2j+1])
-// zmul: transform i s_z X instead of X (s_z = k below the Nyquist index, 0 at it)
+// raw loads for the c2r pre-step of one row: X[k] and X[H-k] (X[H] from the
+// Nyquist plane for k = 0) at the lane's elements k = t + TZ m (streaming
+// loads: the buffer's policy)
 template <typename T, int N, int TZ, int EZ, typename BF>
-__device__ __forceinline__ void c2r_pre(cx<T>* v, int t, const cx<T>* twN, const BF& f, uint32_t soff,
-                                        uint32_t row_id, bool zmul = false) {
+__device__ __forceinline__ void c2r_load(cx<T>* xk, cx<T>* xm, int t, const BF& f, uint32_t soff,
+                                         uint32_t row_id) {
   constexpr int H = N / 2;
   constexpr uint32_t cs = sizeof(cx<T>);
+  const uint32_t r0 = spec_row<T, N>(row_id);
 #pragma unroll
   for (int m = 0; m < EZ; ++m) {
     const int k = t + TZ * m;
-    const uint32_t r0 = spec_row<T, N>(row_id);
-    cx<T> xk = f.template ld<cx<T>>((r0 + k) * cs, soff);
-    cx<T> xm = f.template ld<cx<T>>((k == 0 ? spec_nyq<T, N>() + row_id : r0 + (H - k)) * cs, soff);
+    xk[m] = f.template ldnt<cx<T>>((r0 + k) * cs, soff);
+    xm[m] = f.template ldnt<cx<T>>((k == 0 ? spec_nyq<T, N>() + row_id : r0 + (H - k)) * cs, soff);
+  }
+}
+
+// Where the mirror values X[H - k] of the c2r steps come from: on grids that
+// stream their fields (192^3 on) from the row's LDS buffer after one load of
+// the row (c2r_load_k, c2r_mirror; at 256^3: z_deriv 341 -> 318 us, FP64
+// 192^3 z_inv 96 -> 83 us); on smaller grids, whose fields stay in the
+// caches, from a second load of the row (c2r_load), which costs less there
+// than the LDS round trip (128^3 z_deriv 43 against 45 us).
+template <int N> constexpr bool mirror_lds() { return stream_policy<N>() != 0; }
+
+// raw loads for the c2r pre-step with the mirror values taken from LDS: X[k]
+// at the lane's elements and, in every lane, X[H] of the row (its Nyquist
+// plane value); streaming loads (the buffer's policy) or default ones
+template <typename T, int N, int TZ, int EZ, bool STREAM = true, typename BF>
+__device__ __forceinline__ void c2r_load_k(cx<T>* xk, cx<T>& xn, int t, const BF& f, uint32_t soff,
+                                           uint32_t row_id) {
+  constexpr uint32_t cs = sizeof(cx<T>);
+  const uint32_t r0 = spec_row<T, N>(row_id);
+#pragma unroll
+  for (int m = 0; m < EZ; ++m) {
+    const uint32_t o = (r0 + t + TZ * m) * cs;
+    xk[m] = STREAM ? f.template ldnt<cx<T>>(o, soff) : f.template ld<cx<T>>(o, soff);
+  }
+  const uint32_t on = (spec_nyq<T, N>() + row_id) * cs;
+  xn = STREAM ? f.template ldnt<cx<T>>(on, soff) : f.template ld<cx<T>>(on, soff);
+}
+
+// X[H - k] of the lane's elements k = t + TZ m (X[H] for k = 0) through the
+// row's LDS buffer, which is free again on return
+template <typename T, int N, int TZ, int EZ>
+__device__ __forceinline__ void c2r_mirror(cx<T>* xm, const cx<T>* xk, cx<T> xn, int t, cx<T>* row) {
+  constexpr int H = N / 2;
+#pragma unroll
+  for (int m = 0; m < EZ; ++m) row[t + TZ * m] = xk[m];
+  lds_sync<row_in_wave<TZ>()>();
+#pragma unroll
+  for (int m = 0; m < EZ; ++m) {
+    const int k = t + TZ * m;
+    xm[m] = k == 0 ? xn : row[H - k];
+  }
+  lds_sync<row_in_wave<TZ>()>();
+}
+
+// The c2r pre-step (inverse real transform along z): from X[k] (k < H) and
+// X[H] build C[k] = (X[k] + conj X[H-k]) + i (X[k] - conj X[H-k]) W^-k; the
+// unnormalised length-H inverse of C is then n (a[2j] + i a[2j+1]).
+// xk0, xm0: X[k] and X[H - k] (X[H] for k = 0) at the lane's elements.
+// zmul: transform i s_z X instead of X (s_z = k below the Nyquist index, 0 at it)
+template <typename T, int N, int TZ, int EZ>
+__device__ __forceinline__ void c2r_combine(cx<T>* v, const cx<T>* xk0, const cx<T>* xm0, int t,
+                                            const cx<T>* twN, bool zmul = false) {
+  constexpr int H = N / 2;
+#pragma unroll
+  for (int m = 0; m < EZ; ++m) {
+    const int k = t + TZ * m;
+    cx<T> xk = xk0[m], xm = xm0[m];
     if (k == 0) { xk.y = (T)0; xm.y = (T)0; }
     if (zmul) {
       xk = cscale<T>(cmuli<T>(xk), (T)k);
@@ -553,9 +609,16 @@ __global__ void __launch_bounds__((Geo<T, N, V>::RZ * Geo<T, N, V>::TZ))
   const BufN<N> slot = make_buf<stream_policy<N>()>(a.slot, a.slot ? (uint64_t)a.nreal * n3b : 0);
   uint32_t bad = 0u, badidx = 0xffffffffu;
   for (int s = 0; s < a.nreal; ++s) {
-    cx<T> v[EZ];
-    c2r_pre<T, N, TZ, EZ>(v, t, twN, src, (uint32_t)(s * a.fstride * sizeof(cx<T>)), row,
-                          (a.zmul_mask >> s) & 1u);
+    cx<T> v[EZ], xk[EZ], xm[EZ];
+    const uint32_t si = (uint32_t)(s * a.fstride * sizeof(cx<T>));
+    if constexpr (mirror_lds<N>()) {
+      cx<T> xn;
+      c2r_load_k<T, N, TZ, EZ, false>(xk, xn, t, src, si, row);
+      c2r_mirror<T, N, TZ, EZ>(xm, xk, xn, t, xch + r * H);
+    } else {
+      c2r_load<T, N, TZ, EZ>(xk, xm, t, src, si, row);  // the policy is the default one here
+    }
+    c2r_combine<T, N, TZ, EZ>(v, xk, xm, t, twN, (a.zmul_mask >> s) & 1u);
     fft_pencil<T, H, EZ, false>(v, t, twH, lp);
     const uint32_t so = (uint32_t)s * n3b;
     if (a.final_mode) {
@@ -613,47 +676,10 @@ template <typename T, int N, int EZ = default_ezd<T, N>(), int V = 0> struct Geo
   static constexpr int tiles = (N * N) / RDD;
 };
 
-// raw loads for the c2r pre-step of one row: X[k] and X[H-k] (X[H] from the
-// Nyquist plane for k = 0) at the lane's elements k = t + TZ m
-template <typename T, int N, int TZ, int EZ, typename BF>
-__device__ __forceinline__ void c2r_load(cx<T>* xk, cx<T>* xm, int t, const BF& f, uint32_t soff,
-                                         uint32_t row_id) {
-  constexpr int H = N / 2;
-  constexpr uint32_t cs = sizeof(cx<T>);
-  const uint32_t r0 = spec_row<T, N>(row_id);
-#pragma unroll
-  for (int m = 0; m < EZ; ++m) {
-    const int k = t + TZ * m;
-    xk[m] = f.template ldnt<cx<T>>((r0 + k) * cs, soff);
-    xm[m] = f.template ldnt<cx<T>>((k == 0 ? spec_nyq<T, N>() + row_id : r0 + (H - k)) * cs, soff);
-  }
-}
-
-// the c2r pre-step on loaded values (same arithmetic as c2r_pre)
-template <typename T, int N, int TZ, int EZ>
-__device__ __forceinline__ void c2r_combine(cx<T>* v, const cx<T>* xk0, const cx<T>* xm0, int t,
-                                            const cx<T>* twN, bool zmul = false) {
-  constexpr int H = N / 2;
-#pragma unroll
-  for (int m = 0; m < EZ; ++m) {
-    const int k = t + TZ * m;
-    cx<T> xk = xk0[m], xm = xm0[m];
-    if (k == 0) { xk.y = (T)0; xm.y = (T)0; }
-    if (zmul) {
-      xk = cscale<T>(cmuli<T>(xk), (T)k);
-      xm = k == 0 ? mk<T>((T)0, (T)0) : cscale<T>(cmuli<T>(xm), (T)(H - k));
-    }
-    const cx<T> cm = cconj<T>(xm);
-    const cx<T> s = cadd<T>(xk, cm);
-    const cx<T> d = csub<T>(xk, cm);
-    v[m] = cadd<T>(s, cmuli<T>(cmulc<T>(d, twN[k])));
-  }
-}
-
 // The pre- and post-steps of the real transforms with the lane's constants
 // P_k = (1 - i W^k) / 2 in registers (twp[m] for k = t + TZ m).  With cm the
 // conjugated mirror value, the r2c step E + W^k (-i) O of r2c_post is
-// cm + P_k (c - cm), and the c2r step of c2r_pre, (X_k + cm) + i conj(W^k)
+// cm + P_k (c - cm), and the c2r step of c2r_combine, (X_k + cm) + i conj(W^k)
 // (X_k - cm), equals 2 (cm + conj(P_k) (X_k - cm)): six and eight
 // instructions per element instead of fourteen and ten.
 template <typename T, int N, int TZ, int EZ>
@@ -835,12 +861,17 @@ __global__ void __launch_bounds__((GeoD<T, N, EZD, V>::RDD * GeoD<T, N, EZD, V>:
     // built.  With six elements per thread (sizes with a factor 3) there is
     // no room for further buffers: each field's values are loaded just before
     // its transform.
+    // With the mirror values from LDS (mirror_lds) only X[k] and X[H] of a
+    // row are in flight: half the load instructions and registers.
     constexpr int kAhead = kTwRegs ? 2 : 0;
     constexpr int kBufs = kAhead + 1;
-    cx<T> kb[kBufs][EZ], mb[kBufs][EZ];
+    constexpr bool kLds = mirror_lds<N>();
+    cx<T> kb[kBufs][EZ], mb[kLds ? 1 : kBufs][EZ], nb[kLds ? kBufs : 1];
 #pragma unroll
-    for (int q = 0; q < (kAhead > 0 ? kAhead : 1); ++q)
-      c2r_load<T, N, TZ, EZ>(kb[q], mb[q], t, B, (uint32_t)q * fbytes, row);
+    for (int q = 0; q < (kAhead > 0 ? kAhead : 1); ++q) {
+      if constexpr (kLds) c2r_load_k<T, N, TZ, EZ>(kb[q], nb[q], t, B, (uint32_t)q * fbytes, row);
+      else c2r_load<T, N, TZ, EZ>(kb[q], mb[q], t, B, (uint32_t)q * fbytes, row);
+    }
     init_twiddles<T, H>(twH);
     init_twiddles<T, N>(twN);
     log_table_init(logt);
@@ -856,13 +887,18 @@ __global__ void __launch_bounds__((GeoD<T, N, EZD, V>::RDD * GeoD<T, N, EZD, V>:
 #pragma unroll
     for (int q = 0; q < kFields; ++q) {
       cx<T>* kc = kb[q % kBufs];
-      cx<T>* mc = mb[q % kBufs];
+      cx<T>* mc = mb[kLds ? 0 : q % kBufs];
       if constexpr (kAhead > 0) {
-        if (q + kAhead < kFields)
-          c2r_load<T, N, TZ, EZ>(kb[(q + kAhead) % kBufs], mb[(q + kAhead) % kBufs], t, B, (uint32_t)(q + kAhead) * fbytes, row);
-      } else {
-        if (q > 0) c2r_load<T, N, TZ, EZ>(kc, mc, t, B, (uint32_t)q * fbytes, row);
+        if (q + kAhead < kFields) {
+          const int qa = q + kAhead, ba = qa % kBufs;
+          if constexpr (kLds) c2r_load_k<T, N, TZ, EZ>(kb[ba], nb[ba], t, B, (uint32_t)qa * fbytes, row);
+          else c2r_load<T, N, TZ, EZ>(kb[ba], mb[ba], t, B, (uint32_t)qa * fbytes, row);
+        }
+      } else if (q > 0) {
+        if constexpr (kLds) c2r_load_k<T, N, TZ, EZ>(kc, nb[0], t, B, (uint32_t)q * fbytes, row);
+        else c2r_load<T, N, TZ, EZ>(kc, mc, t, B, (uint32_t)q * fbytes, row);
       }
+      if constexpr (kLds) c2r_mirror<T, N, TZ, EZ>(mc, kc, nb[q % kBufs], t, lrow);
       // the z component of each vector density is i s_z Q_b, formed here
       if constexpr (kTwRegs) {
         c2r_combine_p<T, N, TZ, EZ>(val + q * EZ, kc, mc, t, twp, q == kSlotZ || q == kSlotZ + kVecStride);
