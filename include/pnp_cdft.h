@@ -375,7 +375,9 @@ pnp_status pnp_batch_mu_ex(pnp_ctx ctx, int32_t count, pnp_request* reqs, void* 
  * pnp_plan_create validates every request (reqs[r].status receives the
  * result; failed requests are left out of the graph), copies their argument
  * records into a device block owned by the plan (a few KiB per request),
- * and captures the graph on a private stream.  The request array and the
+ * and captures the graph on a private stream, each grid size on a branch of
+ * its own (the replay runs the sizes side by side: requests must not share
+ * a workspace or an output buffer).  The request array and the
  * host arrays it points to may be released afterwards; the device buffers
  * must stay allocated while the plan exists.  Errors: PNP_E_ARG (no valid
  * plan arguments, or a bad relax spec), PNP_E_DEVICE (capture failed).

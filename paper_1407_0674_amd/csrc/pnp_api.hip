@@ -1296,14 +1296,44 @@ pnp_status pnp_plan_create(pnp_ctx ctx, int32_t count, pnp_request* reqs, const 
     pnp_plan_destroy(p);
     return device_check(ctx, "capture stream");
   }
+  // The size groups share nothing (every request has its own workspace and
+  // outputs), so each is captured on a stream of its own, forked from the
+  // capture stream and joined back: the replay runs them as parallel
+  // branches, and the launches of small grids fill compute units that those
+  // of the large ones leave idle.  Without these streams (creation failed,
+  // or a single group) every group is captured on the capture stream.
+  const size_t ng = groups.size();
+  std::vector<hipStream_t> gs;
+  std::vector<hipEvent_t> gev;  // [0] fork, [1 + k] group k done
+  if (ng > 1) {
+    gs.assign(ng, nullptr);
+    gev.assign(ng + 1, nullptr);
+    bool made = true;
+    for (size_t k = 0; k < ng && made; ++k) made = hipStreamCreateWithFlags(&gs[k], hipStreamNonBlocking) == hipSuccess;
+    for (size_t k = 0; k <= ng && made; ++k) made = hipEventCreateWithFlags(&gev[k], hipEventDisableTiming) == hipSuccess;
+    if (!made) {
+      (void)hipGetLastError();
+      for (hipStream_t x : gs)
+        if (x) (void)hipStreamDestroy(x);
+      for (hipEvent_t e : gev)
+        if (e) (void)hipEventDestroy(e);
+      gs.clear();
+      gev.clear();
+    }
+  }
+  const bool branches = !gs.empty();
   char* blk = (char*)p->block;
   bool ok = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess;
   if (ok) {
     ctx->capturing = true;
-    for (size_t k = 0; k < groups.size(); ++k) {
+    if (branches) ok = hipEventRecord(gev[0], cs) == hipSuccess;
+    for (size_t k = 0; k < ng && ok; ++k) {
       const Group& g = groups[k];
+      hipStream_t st = branches ? gs[k] : cs;
+      if (branches) ok = hipStreamWaitEvent(st, gev[0], 0) == hipSuccess;
       run_sequence(ctx, select_ops(ctx, g.precision, g.n, (int)g.ids.size()), (const EvalArgs*)(blk + ea_off[k]),
-                   (const TableArgs*)(blk + ta_off[k]), (int)g.ids.size(), g.M, g.fmask, g.mix, cs, g.n);
+                   (const TableArgs*)(blk + ta_off[k]), (int)g.ids.size(), g.M, g.fmask, g.mix, st, g.n);
+      if (branches && ok) ok = hipEventRecord(gev[1 + k], st) == hipSuccess && hipStreamWaitEvent(cs, gev[1 + k], 0) == hipSuccess;
     }
     if (relax)
       for (int r = 0; r < count; ++r) {
@@ -1316,10 +1346,14 @@ pnp_status pnp_plan_create(pnp_ctx ctx, int32_t count, pnp_request* reqs, const 
                            (const uint32_t*)p->status[r], fixed_mask(q.S, q.species));
       }
     ctx->capturing = false;
-    ok = hipStreamEndCapture(cs, &p->graph) == hipSuccess && p->graph;
+    // end the capture in every case (a failed fork or join above leaves ok false)
+    const bool ended = hipStreamEndCapture(cs, &p->graph) == hipSuccess && p->graph;
+    ok = ok && ended;
   }
   if (ok) ok = hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0) == hipSuccess;
   (void)hipStreamDestroy(cs);
+  for (hipStream_t x : gs) (void)hipStreamDestroy(x);
+  for (hipEvent_t e : gev) (void)hipEventDestroy(e);
   if (!ok) {
     pnp_plan_destroy(p);
     return device_check(ctx, "graph capture");
