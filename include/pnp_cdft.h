@@ -351,9 +351,14 @@ typedef struct {
 /*
  * Evaluate `count` independent requests of possibly different sizes,
  * temperatures and compositions.  Requests with equal grid size share every
- * kernel launch (one grid of workgroups spans all of them).  A request that
- * fails (bad packing, overflow, ...) reports its own status and does not
- * affect the others.  Returns PNP_OK when the batch ran (check each status).
+ * kernel launch (one grid of workgroups spans all of them).  With two or
+ * more grid sizes below 192^3, each of those sizes runs on a stream of the
+ * context's own (default priority), forked from `stream` and joined back
+ * before the call returns or, with PNP_FLAG_ASYNC, before later work on
+ * `stream`; requests must not share a workspace or an output buffer.  A
+ * request that fails (bad packing, overflow, ...) reports its own status and
+ * does not affect the others.  Returns PNP_OK when the batch ran (check each
+ * status).
  */
 pnp_status pnp_batch_mu_ex(pnp_ctx ctx, int32_t count, pnp_request* reqs, void* stream);
 

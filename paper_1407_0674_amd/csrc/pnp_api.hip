@@ -50,6 +50,13 @@ struct pnp_ctx_s {
   hipStream_t side = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   bool side_failed = false;
+  // branch streams (default priority) on which a batch runs its grid sizes
+  // below 192^3 side by side, with the fork event and one join event each;
+  // created on first use
+  std::vector<hipStream_t> br;
+  std::vector<hipEvent_t> br_done;
+  hipEvent_t br_fork = nullptr;
+  bool br_failed = false;
 };
 
 // Scratch of the allocation-free evaluation (pnp_cdft_mu_ex_noalloc): one
@@ -793,6 +800,9 @@ void pnp_destroy(pnp_ctx c) {
   if (c->side) (void)hipStreamDestroy(c->side);
   if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
   if (c->ev_join) (void)hipEventDestroy(c->ev_join);
+  for (hipStream_t x : c->br) (void)hipStreamDestroy(x);
+  for (hipEvent_t e : c->br_done) (void)hipEventDestroy(e);
+  if (c->br_fork) (void)hipEventDestroy(c->br_fork);
   for (auto& o : c->ev_open) { hipEventDestroy(o.second.first); hipEventDestroy(o.second.second); }
   for (hipEvent_t e : c->ev_pool) hipEventDestroy(e);
   delete c;
@@ -1194,6 +1204,27 @@ pnp_status pnp_sphere_quadrature(pnp_ctx ctx, const pnp_grid* g, int32_t F, cons
   return PNP_OK;
 }
 
+// At least k branch streams with their join events (and the fork event);
+// false (and every group stays on the caller's stream) if they cannot be made.
+static bool branch_streams(pnp_ctx c, size_t k) {
+  if (c->br_failed) return false;
+  bool ok = c->br_fork || hipEventCreateWithFlags(&c->br_fork, hipEventDisableTiming) == hipSuccess;
+  while (ok && c->br.size() < k) {
+    hipStream_t x = nullptr;
+    hipEvent_t e = nullptr;
+    ok = hipStreamCreateWithFlags(&x, hipStreamNonBlocking) == hipSuccess;
+    if (ok) ok = hipEventCreateWithFlags(&e, hipEventDisableTiming) == hipSuccess;
+    if (x) c->br.push_back(x);
+    if (e) c->br_done.push_back(e);
+    ok = ok && c->br.size() == c->br_done.size();
+  }
+  if (!ok) {
+    (void)hipGetLastError();
+    c->br_failed = true;
+  }
+  return ok;
+}
+
 pnp_status pnp_batch_mu_ex(pnp_ctx ctx, int32_t count, pnp_request* reqs, void* stream) {
   if (!ctx) return PNP_E_ARG;
   if (count < 0 || (count > 0 && !reqs)) return fail(ctx, PNP_E_ARG, "bad request array");
@@ -1202,13 +1233,33 @@ pnp_status pnp_batch_mu_ex(pnp_ctx ctx, int32_t count, pnp_request* reqs, void* 
   std::vector<Layout> lay;
   std::vector<Group> groups;
   prepare_batch(ctx, count, reqs, lay, groups);
+  // Grid sizes below kSplitMinN leave most of the chip idle in their
+  // launches: with two or more of them each runs on a branch stream of its
+  // own, forked from the caller's stream and joined back before the status
+  // reads (the groups share no buffer, and every upload takes its own arena
+  // slot).  Larger sizes fill the chip, use the side stream, and stay on the
+  // caller's stream, beside the branches.
+  size_t nsmall = 0;
+  for (const Group& g : groups)
+    if (g.n < kSplitMinN) ++nsmall;
+  const bool fork = nsmall >= 2 && branch_streams(ctx, nsmall);
+  if (fork && hipEventRecord(ctx->br_fork, s) != hipSuccess) return device_check(ctx, "batch fork");
+  size_t b = 0;
   for (const Group& g : groups) {
     const int cnt = (int)g.ids.size();
+    const bool branch = fork && g.n < kSplitMinN;
+    hipStream_t gs = branch ? ctx->br[b] : s;
+    if (branch && hipStreamWaitEvent(gs, ctx->br_fork, 0) != hipSuccess) return device_check(ctx, "batch fork");
     const TableArgs* dta = nullptr;
     const EvalArgs* dea = nullptr;
-    upload_args(ctx, g.ta.data(), cnt, g.ea.data(), cnt, s, dta, dea);
+    upload_args(ctx, g.ta.data(), cnt, g.ea.data(), cnt, gs, dta, dea);
     if (!dta || !dea) return device_check(ctx, "argument upload");
-    run_sequence(ctx, select_ops(ctx, g.precision, g.n, cnt), dea, dta, cnt, g.M, g.fmask, g.mix, s, g.n);
+    run_sequence(ctx, select_ops(ctx, g.precision, g.n, cnt), dea, dta, cnt, g.M, g.fmask, g.mix, gs, g.n);
+    if (branch) {
+      if (hipEventRecord(ctx->br_done[b], gs) != hipSuccess || hipStreamWaitEvent(s, ctx->br_done[b], 0) != hipSuccess)
+        return device_check(ctx, "batch join");
+      ++b;
+    }
   }
   pnp_status st = device_check(ctx, "batch launch");
   if (st != PNP_OK) return st;
