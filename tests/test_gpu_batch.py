@@ -45,6 +45,29 @@ def test_batch_equals_alone_small(ev):
         assert torch.equal(sl, s1), p.name
 
 
+def test_batch_large_and_small_sizes(ev):
+    """A 192^3 instance (on the caller's stream, its Nyquist tiles on the
+    side stream) in one batch with instances of three smaller sizes (each
+    size on a branch stream of its own): every instance equals its single
+    call bit for bit, and a second batch call gives the same bits."""
+    rng = np.random.default_rng(17)
+    inst = [P.random_instance(rng, (192,), P.MIXED)]
+    inst += [P.random_instance(rng, (n,), P.MIXED if k % 2 else P.FP64) for k, n in enumerate((16, 24, 32, 16))]
+    rhos = [to_dev(r) for _, r in inst]
+    mus, slots, st = ev.batch([p for p, _ in inst], rhos)
+    assert st == [0] * len(inst)
+    mus = [m.clone() for m in mus]
+    slots = [s_.clone() for s_ in slots]
+    for (p, _), rd, mu, sl in zip(inst, rhos, mus, slots):
+        m1, s1 = _alone(ev, p, rd)
+        assert torch.equal(mu, m1), p.name
+        assert torch.equal(sl, s1), p.name
+    mus2, slots2, st2 = ev.batch([p for p, _ in inst], rhos)
+    assert st2 == [0] * len(inst)
+    for a, b in zip(mus, mus2):
+        assert torch.equal(a, b)
+
+
 def test_batch_vs_oracle(ev):
     inst = _mixed_instances(12, 5, (16, 24))
     mus, slots, st = ev.batch([p for p, _ in inst], [to_dev(r) for _, r in inst])
