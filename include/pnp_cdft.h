@@ -61,7 +61,10 @@
  * second stream that the context owns (default priority), forked from the
  * caller's stream after the work enqueued so far and joined back into it
  * before the call's last pass, so to the caller the work is ordered as if
- * it ran on its stream alone.  Unless PNP_FLAG_ASYNC is set, a
+ * it ran on its stream alone.  A batch with two or more grid sizes below
+ * 192^3 runs each of them on a further stream of the context's (default
+ * priority, one per size, created on first use), forked and joined the same
+ * way.  Unless PNP_FLAG_ASYNC is set, a
  * call waits for its own work to finish so that it can return the status
  * that the kernels raised (packing fraction >= 1, non-finite values,
  * overflow of exp(-mu)).
