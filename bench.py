@@ -77,7 +77,7 @@ def all_fields_bytes_per_point(S: int, precision: int):
     return {
         "z_fwd_rho": (8 + c) * S, "y_fwd_rho": 2 * c * S, "x_fwd_weights": c * S + c * F,
         "y_inv_n": 2 * c * F, "z_deriv": 2 * c * F, "y_fwd_dphi": 2 * c * F,
-        "x_back_pairs": c * F + 2 * c * S, "y_inv_mu": 2 * c * S, "z_inv_final": c * S + (24 - c) * S,
+        "x_back_pairs": c * F + 2 * c * S, "y_inv_mu": 2 * c * S, "z_inv_final": c * S + 16 * S,
     }
 
 
