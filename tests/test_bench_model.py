@@ -41,3 +41,32 @@ def test_without_slotboom_output():
     bare = bench.pass_bytes_per_point(3, MIXED, slot=False)
     assert full["z_inv_final"] - bare["z_inv_final"] == 8 * 3
     assert {k: v for k, v in full.items() if k != "z_inv_final"} == {k: v for k, v in bare.items() if k != "z_inv_final"}
+
+
+def _oracle_offsets(r, k, cubic):
+    """Distinct grid offsets with a nonzero interpolation weight over the
+    nodes of the oracle's rule (its node directions and per-axis weights)."""
+    import math
+    import numpy as np
+    import oracle.sphere_quad as sq
+    theta, _, phi, _ = sq.sphere_rule(k)
+    seen = set()
+    for th in theta:
+        for ph in phi:
+            p = r * np.array([math.cos(th) * math.sin(ph), math.sin(th) * math.sin(ph), math.cos(ph)])
+            base = np.floor(p).astype(np.int64)
+            ax = [sq.axis_weights(p[a] - base[a], cubic) for a in range(3)]
+            for ox, wx in zip(*ax[0]):
+                for oy, wy in zip(*ax[1]):
+                    for oz, wz in zip(*ax[2]):
+                        if float(wx * wy * wz) != 0.0:
+                            seen.add((int(base[0] + ox), int(base[1] + oy), int(base[2] + oz)))
+    return len(seen)
+
+
+@pytest.mark.parametrize("cubic", [False, True])
+@pytest.mark.parametrize("r,k", [(1.5, 8), (3.0, 8), (4.0, 8), (3.0, 4), (2.0, 16)])
+def test_sphere_stencil_count_matches_the_oracle_rule(r, k, cubic):
+    """The sphere workload's flop count rests on the number of distinct
+    stencil offsets; counted from the oracle's rule it must agree."""
+    assert bench.sphere_stencil_size(r, k, cubic) == _oracle_offsets(r, k, cubic)
