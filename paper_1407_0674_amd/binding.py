@@ -372,8 +372,10 @@ class Evaluator:
             sl = None
             if slotboom:
                 sl = slots[r] if slots is not None else torch.empty(tuple(rho.shape), dtype=torch.float64, device=rho.device)
-            nb = self.workspace_bytes(p)
-            ws = workspaces[r] if workspaces is not None else torch.empty(nb, dtype=torch.uint8, device=rho.device)
+            if workspaces is not None:
+                ws = workspaces[r]
+            else:
+                ws = torch.empty(self.workspace_bytes(p), dtype=torch.uint8, device=rho.device)
             keep.append(ws)
             reqs[r].grid = m.grid
             reqs[r].S = m.S
