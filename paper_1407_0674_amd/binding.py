@@ -231,7 +231,9 @@ class Evaluator:
         return ctypes.c_void_p(_torch().cuda.current_stream().cuda_stream)
 
     def workspace_bytes(self, problem, per_term=False, precision=None, flags=0) -> int:
-        m = _Marshal(problem, per_term, flags, precision=precision)
+        return self._ws_bytes(_Marshal(problem, per_term, flags, precision=precision))
+
+    def _ws_bytes(self, m) -> int:
         out = ctypes.c_size_t()
         self._check(self.lib.pnp_workspace_bytes(self.ctx, ctypes.byref(m.grid), m.S,
                                                  ctypes.byref(m.params), ctypes.byref(out)))
@@ -267,8 +269,7 @@ class Evaluator:
             out = torch.empty(shape, dtype=torch.float64, device=rho.device)
         if slotboom and slot is None:
             slot = torch.empty((m.S, problem.n, problem.n, problem.n), dtype=torch.float64, device=rho.device)
-        nb = self.workspace_bytes(problem, per_term, precision, flags)
-        ws = self.workspace(nb) if workspace is None else workspace
+        ws = self.workspace(self._ws_bytes(m)) if workspace is None else workspace
         st = self.lib.pnp_cdft_mu_ex(
             self.ctx, ctypes.byref(m.grid), m.S, m.species, self._dev(rho, "rho"), m.T,
             ctypes.byref(m.params), self._dev(out, "mu_ex"),
